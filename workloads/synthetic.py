@@ -1,0 +1,83 @@
+"""Synthetic Pauli-basis tensor networks (the paper substitutes random numbers
+for subcircuit outputs of large benchmarks, Sec. VII-A).
+
+Values per tensor j: the all-I row T_j[I..I, :] ~ Dirichlet(alpha * 1) over
+its 2^{o_j} columns; every other row T_j[sigma, x] ~ U[-p(x), p(x)] with p the
+all-I row.  These are not physical distributions: the reconstructed vector
+can be negative and need not sum to 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .cutting import Network, TensorSpec
+
+
+def regular_multigraph(num_nodes, degree, rng, max_tries=10000):
+    """Configuration model without self-loops (multi-edges allowed)."""
+    for _ in range(max_tries):
+        stubs = np.repeat(np.arange(num_nodes), degree)
+        rng.shuffle(stubs)
+        pairs = stubs.reshape(-1, 2)
+        if np.all(pairs[:, 0] != pairs[:, 1]):
+            return [(int(a), int(b)) for a, b in pairs]
+    raise RuntimeError("no loop-free multigraph")
+
+
+def tensor_values(num_cuts, num_outputs, rng, alpha=0.1):
+    cols = 1 << num_outputs
+    T = np.empty((4 ** num_cuts, cols), dtype=np.float64)
+    p = rng.dirichlet(np.full(cols, alpha))
+    T[0] = p
+    if num_cuts:
+        T[1:] = rng.uniform(-1.0, 1.0, size=(4 ** num_cuts - 1, cols)) * p
+    return T
+
+
+def network_from_edges(n, num_tensors, edges, outputs_per_tensor, rng, alpha=0.1):
+    """edges: list of (a, b) tensor pairs, one per cut; orientation seeded."""
+    cuts = []
+    for a, b in edges:
+        cuts.append((a, b) if rng.integers(2) else (b, a))
+    qubits = rng.permutation(n)
+    tensors = []
+    pos = 0
+    for j in range(num_tensors):
+        o = outputs_per_tensor[j]
+        outs = sorted(int(q) for q in qubits[pos:pos + o])
+        pos += o
+        cids = [c for c, (u, d) in enumerate(cuts) if j in (u, d)]
+        T = tensor_values(len(cids), o, rng, alpha)
+        tensors.append(TensorSpec(cut_ids=cids, outputs=outs, basis="pauli", data=T))
+    assert pos == n
+    return Network(n=n, cuts=cuts, tensors=tensors)
+
+
+def precision_network(seed=None):
+    """6 tensors, 18 cuts (a 6-regular multigraph: every tensor has exactly 6
+    cuts), 34 output qubits split [6,6,6,6,5,5] in seeded order, 4 qubits fixed
+    to seeded values (a 2^30 slice)."""
+    from .configs import rng_for
+    rng = rng_for(3, 0, seed)
+    edges = regular_multigraph(6, 6, rng)
+    net = network_from_edges(34, 6, edges, [6, 6, 6, 6, 5, 5], rng)
+    fq = sorted(int(q) for q in rng.choice(34, size=4, replace=False))
+    fv = [int(v) for v in rng.integers(0, 2, size=4)]
+    net.meta.update(name="synthetic6_18cut_34q", fixed_qubits=fq, fixed_values=fv)
+    return net
+
+
+def random_network(num_tensors, num_cuts, outputs_per_tensor, seed, alpha=0.1,
+                   connected=True):
+    """Random connected multigraph network (spanning tree first, then extra
+    edges) for tests."""
+    rng = np.random.default_rng(seed)
+    edges = []
+    if connected:
+        for j in range(1, num_tensors):
+            edges.append((int(rng.integers(j)), j))
+    while len(edges) < num_cuts:
+        a, b = rng.choice(num_tensors, size=2, replace=False)
+        edges.append((int(a), int(b)))
+    n = int(sum(outputs_per_tensor))
+    return network_from_edges(n, num_tensors, edges[:num_cuts], outputs_per_tensor, rng, alpha)
