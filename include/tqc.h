@@ -1,0 +1,238 @@
+/*
+ * tqc.h - reconstruction of cut quantum circuits by tensor-network
+ * contraction on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (TensorQC, arXiv 2502.03445): a circuit on n qubits is cut on
+ * K wires into m subcircuits.  Each cut carries a 4-valued Pauli index
+ * (I, X, Y, Z); subcircuit j yields a tensor p_j of shape
+ * 4^(its cuts) x 2^(its output qubits) (Sec. II-A).  The output distribution
+ * is the contraction of those tensors over all cut indices (Eq. (1)),
+ * evaluated as an ordered sequence of m-1 pairwise contractions (Sec. III-B,
+ * Eq. (3)) with optional slicing of cut indices (Sec. III-E2).
+ *
+ * Conventions used throughout this interface
+ *   - Pauli digit order I=0, X=1, Y=2, Z=3.
+ *   - A tensor's rows are digits over its cuts in the order of cut_ids, the
+ *     first cut being the slowest digit; its columns are output bits, bit t
+ *     of the column index being the measured value of output_qubits[t].
+ *   - Raw (measured) tensors: rows are mixed-radix digits over the cuts,
+ *     radix 3 where the tensor is the upstream (measured) end of the cut
+ *     (0=Z, 1=X, 2=Y basis; I shares the Z rotation), radix 4 where it is
+ *     the downstream (prepared) end (0=|0>, 1=|1>, 2=|+>, 3=|i>); columns are
+ *     x * 2^u + b, with b bit i the measured value of the i-th upstream cut
+ *     in cut_ids order (Sec. II-A, variant count of Eq. (6)).
+ *   - Output probability vectors: bit q of the index is the measured value
+ *     of qubit q.  With fixed qubits, bit i of the index is the i-th free
+ *     qubit in ascending order, and entries are the unnormalised joint
+ *     probabilities P(x) with x on the fixed qubits equal to the given values.
+ *   - The factor 1/2 per cut of the identity decomposition (left implicit
+ *     in Eq. (1)) is applied by the library.
+ *
+ * Ownership and errors
+ *   - Host arrays passed in are copied during the call.
+ *   - Device pointers passed in (outputs) remain owned by the caller and must
+ *     hold the stated number of bytes on the current HIP device.
+ *   - Streams are hipStream_t values passed as void*; NULL is the default
+ *     stream.  All device work of a call is enqueued on that stream and may
+ *     still be running when the call returns.
+ *   - Every call returns a tqc_status; nothing throws or aborts across this
+ *     interface.  tqc_last_error() gives a thread-local description of the
+ *     last failure.  Device faults surface as TQC_ERR_DEVICE at a later call
+ *     or at the caller's stream synchronisation.
+ *   - Handles are created and destroyed in pairs; destroy a plan before the
+ *     network it was built from.
+ */
+#ifndef TQC_H
+#define TQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TQC_OK = 0,
+  TQC_ERR_INVALID_ARG = 1,     /* null pointer, out-of-range value          */
+  TQC_ERR_TOPOLOGY = 2,        /* cut/qubit structure is not a valid network */
+  TQC_ERR_SHAPE = 3,           /* data length or buffer size mismatch        */
+  TQC_ERR_OUT_OF_MEMORY = 4,   /* device allocation failed                   */
+  TQC_ERR_PLAN_INFEASIBLE = 5, /* no slicing fits the memory budget          */
+  TQC_ERR_DEVICE = 6,          /* HIP runtime error                          */
+  TQC_ERR_UNSUPPORTED = 7,     /* valid request this build does not handle   */
+  TQC_ERR_INTERNAL = 8
+} tqc_status;
+
+/* Arithmetic form of the pairwise contractions (the Pauli-basis transform and
+ * the cross-slice sum are always float64).
+ *   FP64   float64 operands, float64 MFMA.
+ *   FP32   float32 operands, float32 MFMA accumulation.
+ *   BF16X3 operands split a = hi + lo into two bfloat16 values (hi =
+ *          RNE(a), lo = RNE(a - hi)); products hi*hi + hi*lo + lo*hi on
+ *          bfloat16 MFMA with float32 accumulation.
+ *   BF16X6 three-way split a = hi + mid + lo; the six products whose
+ *          combined weight is above 2^-24 (hh, hm, mh, hl, mm, lh). */
+typedef enum { TQC_FP64 = 0, TQC_FP32 = 1, TQC_BF16X3 = 2, TQC_BF16X6 = 3 } tqc_precision;
+
+/* Element type of a device probability vector. */
+typedef enum { TQC_F64 = 0, TQC_F32 = 1 } tqc_dtype;
+
+typedef enum { TQC_BASIS_RAW = 0, TQC_BASIS_PAULI = 1 } tqc_basis;
+
+/* One cut edge: the tensor that measures the cut wire (upstream) and the
+ * tensor that prepares it (downstream); they must differ (each cut joins
+ * exactly two subcircuits, Sec. III-D). */
+typedef struct {
+  int32_t upstream;
+  int32_t downstream;
+} tqc_cut;
+
+/* One subcircuit tensor (host memory, float64, row-major).  Rows x columns:
+ *   PAULI: 4^num_cuts x 2^num_outputs
+ *   RAW:   (3^u * 4^d) x 2^(num_outputs + u)   (u upstream, d downstream) */
+typedef struct {
+  int32_t num_cuts;
+  const int32_t *cut_ids;       /* indices into the network's cut array */
+  int32_t num_outputs;
+  const int32_t *output_qubits; /* qubit ids, each in exactly one tensor */
+  tqc_basis basis;
+  const double *data;
+} tqc_tensor_desc;
+
+typedef struct tqc_network_s *tqc_network_t;
+typedef struct tqc_plan_s *tqc_plan_t;
+typedef struct tqc_costmodel_s *tqc_costmodel_t;
+
+/* ------------------------------------------------------------------ network
+ * tqc_network_create: validate and copy a network (Sec. II-A notation:
+ * n qubits, m subcircuits, cut set E).  Checks: every cut names two distinct
+ * tensors and appears in exactly those two tensors' cut lists; every qubit
+ * 0..num_qubits-1 is an output of exactly one tensor; data sizes follow the
+ * layouts above; values are finite.  Host-only: no device work happens until
+ * tqc_network_upload or the first tqc_execute.
+ * Errors: INVALID_ARG, TOPOLOGY, SHAPE. */
+tqc_status tqc_network_create(int32_t num_qubits, int32_t num_tensors,
+                              const tqc_tensor_desc *tensors, int32_t num_cuts,
+                              const tqc_cut *cuts, tqc_network_t *out);
+
+/* Copy the tensor data to the current device (synchronous).  Called
+ * implicitly by the first tqc_execute.  Errors: OUT_OF_MEMORY, DEVICE. */
+tqc_status tqc_network_upload(tqc_network_t net);
+
+void tqc_network_destroy(tqc_network_t net);
+
+/* --------------------------------------------------------------------- plan
+ * Contraction order (Sec. III-E1), two-level slicing (Sec. III-E2) and the
+ * per-step GEMM mapping.  The planner scores candidate plans with a
+ * roofline cost (flops / MFMA peak vs bytes / HBM bandwidth per step, the
+ * refinement of Eq. (7)) or with a trained cost model. */
+typedef enum { TQC_COST_FLOPBYTE = 0, TQC_COST_MLP = 1 } tqc_cost_kind;
+
+typedef struct {
+  tqc_precision precision;     /* contraction form                          */
+  tqc_dtype out_dtype;         /* element type of the output vector         */
+  uint64_t mem_budget_bytes;   /* device bytes for inputs + intermediates; 0 = unlimited */
+  int32_t num_fixed;           /* fixed-qubit slice of the output           */
+  const int32_t *fixed_qubits;
+  const int32_t *fixed_values; /* 0 or 1 each                                */
+  int32_t num_order_steps;     /* >0: use this contraction sequence          */
+  const int32_t *order;        /* 2*num_order_steps SSA ids: step s joins ids
+                                  order[2s], order[2s+1] into id m+s          */
+  int32_t num_sliced;          /* -1: planner chooses; >=0: slice exactly these */
+  const int32_t *sliced_cuts;
+  tqc_cost_kind cost_kind;
+  tqc_costmodel_t cost_model;  /* required for TQC_COST_MLP                  */
+  int32_t num_candidates;      /* randomised-greedy candidates (0 = default) */
+  uint64_t seed;
+  int32_t tile_policy;         /* 0 fixed default tiles, 1 autotuned table   */
+} tqc_plan_options;
+
+void tqc_plan_options_default(tqc_plan_options *opt);
+
+tqc_status tqc_plan_create(tqc_network_t net, const tqc_plan_options *opt, tqc_plan_t *out);
+void tqc_plan_destroy(tqc_plan_t plan);
+
+typedef struct {
+  int32_t num_steps;
+  int32_t num_sliced;
+  int32_t k_max_cuts;          /* K_max of Eq. (4): most cuts at any step     */
+  int32_t out_qubits;          /* free output qubits (log2 of output entries) */
+  uint64_t num_slices;         /* 4^num_sliced                                */
+  uint64_t out_entries;
+  double flops;                /* 2*M*N*K summed over steps and slices        */
+  double mults_per_state;      /* Sec. III-C count: cut dims only             */
+  double bytes;                /* algorithmic HBM bytes (operands + outputs)  */
+  double predicted_seconds;    /* cost model used by the planner              */
+  uint64_t workspace_bytes;    /* device workspace the plan allocates         */
+  double plan_seconds;         /* host time spent planning                    */
+} tqc_plan_stats;
+
+tqc_status tqc_plan_get_stats(tqc_plan_t plan, tqc_plan_stats *st);
+
+typedef struct {
+  int32_t lhs, rhs, result;    /* SSA ids                                    */
+  int32_t log2_m, log2_n, log2_k;
+  int32_t shared_cuts, open_cuts;
+  int32_t slice_dependent;     /* recomputed for every slice                  */
+  int32_t tile;                /* kernel tile id                              */
+  double flops, bytes;
+} tqc_step_info;
+
+tqc_status tqc_plan_get_step(tqc_plan_t plan, int32_t step, tqc_step_info *info);
+tqc_status tqc_plan_get_sliced(tqc_plan_t plan, int32_t *cuts_out /* num_sliced */);
+
+/* ------------------------------------------------------------------ execute
+ * Run the plan: Pauli-basis transform of raw tensors (float64), packing of
+ * the contraction operands (slice and fixed-qubit gathers, cast/split),
+ * every pairwise contraction, the float64 sum over slices, and the final
+ * conversion to out_dtype.  out must hold out_entries elements of out_dtype.
+ * Errors: SHAPE (out_bytes too small), OUT_OF_MEMORY, DEVICE. */
+tqc_status tqc_execute(tqc_plan_t plan, void *out, uint64_t out_bytes, void *stream);
+
+/* tqc_execute, then wait for the stream and report device time per phase,
+ * measured with HIP events on that stream: phase_ms[0] Pauli-basis
+ * transform, [1] operand packing, [2 + i] pairwise step i (summed over
+ * slices), [2 + num_steps] float64-to-float32 conversion (0 if none).
+ * num_phases >= 3 + num_steps.  Synchronous.  Used for the benchmark's
+ * per-kernel roofline and as training data of the learned cost model. */
+tqc_status tqc_execute_profiled(tqc_plan_t plan, void *out, uint64_t out_bytes, void *stream,
+                                double *phase_ms, int32_t num_phases);
+
+/* Run slices [slice_begin, slice_end) only, adding into a float64 output
+ * (accumulate=1) or overwriting it (accumulate=0).  Summing disjoint ranges
+ * gives the full result; used to resume after a partial run. */
+tqc_status tqc_execute_slices(tqc_plan_t plan, double *out, uint64_t out_bytes,
+                              uint64_t slice_begin, uint64_t slice_end,
+                              int32_t accumulate, void *stream);
+
+/* Pauli-basis tensor of network tensor j after the float64 transform
+ * (4^c x 2^o, the layout above) into a device buffer; for checking the
+ * transform on its own. */
+tqc_status tqc_network_pauli_tensor(tqc_network_t net, int32_t j, double *out,
+                                    uint64_t out_bytes, void *stream);
+
+/* ------------------------------------------------------------ output forms
+ * Top-k (Eq. (10): the sum of the k largest true probabilities is
+ * P_HSS^max): the k largest entries, larger value first, equal values by
+ * smaller index.  idx_out/val_out are device arrays of k elements.  1 <= k <=
+ * 4096 and k <= len.  Deterministic. */
+tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
+                    uint64_t *idx_out, double *val_out, void *stream);
+
+/* Marginal over the kept qubits: out[y] = sum of probs[x] over x whose bit
+ * keep[i] equals bit i of y; float64 sums in a fixed order (deterministic).
+ * num_keep = 0 gives the total (1 for a physical circuit).  out is a device
+ * array of 2^num_keep doubles; num_keep <= 24. */
+tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
+                        int32_t num_keep, const int32_t *keep, double *out, void *stream);
+
+/* --------------------------------------------------------------------- misc */
+const char *tqc_status_string(tqc_status s);
+const char *tqc_last_error(void);
+int32_t tqc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TQC_H */

@@ -1,0 +1,328 @@
+"""Python binding of libtqc (HIP, MI355X): reconstruction of cut quantum
+circuits by tensor-network contraction.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory and streams; torch is imported
+before the library is loaded so that both share one HIP runtime.  There is
+no CPU fallback: if ``libtqc.so`` is missing, loading fails.
+
+    net  = Network(n, tensors=[(cut_ids, outputs, basis, data), ...], cuts=[(up, down), ...])
+    plan = Plan(net, precision="fp32")
+    out  = plan.execute()                # torch tensor on the current device
+    idx, val = topk(out, k)
+    tot  = marginal(out, plan.out_qubits, [])
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+__all__ = ["lib", "Network", "Plan", "topk", "marginal", "TqcError", "PRECISIONS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtqc.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+DTYPES = {"f64": 0, "f32": 1}
+BASES = {"raw": 0, "pauli": 1}
+COST = {"flopbyte": 0, "mlp": 1}
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class TensorDesc(ctypes.Structure):
+    _fields_ = [("num_cuts", ctypes.c_int32), ("cut_ids", _i32p),
+                ("num_outputs", ctypes.c_int32), ("output_qubits", _i32p),
+                ("basis", ctypes.c_int), ("data", _dp)]
+
+
+class Cut(ctypes.Structure):
+    _fields_ = [("upstream", ctypes.c_int32), ("downstream", ctypes.c_int32)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("out_dtype", ctypes.c_int),
+                ("mem_budget_bytes", ctypes.c_uint64),
+                ("num_fixed", ctypes.c_int32), ("fixed_qubits", _i32p), ("fixed_values", _i32p),
+                ("num_order_steps", ctypes.c_int32), ("order", _i32p),
+                ("num_sliced", ctypes.c_int32), ("sliced_cuts", _i32p),
+                ("cost_kind", ctypes.c_int), ("cost_model", ctypes.c_void_p),
+                ("num_candidates", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("tile_policy", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("num_steps", ctypes.c_int32), ("num_sliced", ctypes.c_int32),
+                ("k_max_cuts", ctypes.c_int32), ("out_qubits", ctypes.c_int32),
+                ("num_slices", ctypes.c_uint64), ("out_entries", ctypes.c_uint64),
+                ("flops", ctypes.c_double), ("mults_per_state", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("predicted_seconds", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_uint64), ("plan_seconds", ctypes.c_double)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("lhs", ctypes.c_int32), ("rhs", ctypes.c_int32), ("result", ctypes.c_int32),
+                ("log2_m", ctypes.c_int32), ("log2_n", ctypes.c_int32), ("log2_k", ctypes.c_int32),
+                ("shared_cuts", ctypes.c_int32), ("open_cuts", ctypes.c_int32),
+                ("slice_dependent", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class TqcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def _declare(L):
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32
+    sigs = {
+        "tqc_network_create": [i32, i32, ctypes.POINTER(TensorDesc), i32, ctypes.POINTER(Cut),
+                               ctypes.POINTER(vp)],
+        "tqc_network_upload": [vp],
+        "tqc_plan_create": [vp, ctypes.POINTER(PlanOptions), ctypes.POINTER(vp)],
+        "tqc_plan_get_stats": [vp, ctypes.POINTER(PlanStats)],
+        "tqc_plan_get_step": [vp, i32, ctypes.POINTER(StepInfo)],
+        "tqc_plan_get_sliced": [vp, _i32p],
+        "tqc_execute": [vp, vp, u64, vp],
+        "tqc_execute_slices": [vp, vp, u64, u64, u64, i32, vp],
+        "tqc_execute_profiled": [vp, vp, u64, vp, _dp, i32],
+        "tqc_network_pauli_tensor": [vp, i32, vp, u64, vp],
+        "tqc_topk": [vp, ctypes.c_int, u64, i32, vp, vp, vp],
+        "tqc_marginal": [vp, ctypes.c_int, i32, i32, _i32p, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    for name in ("tqc_network_destroy", "tqc_plan_destroy"):
+        getattr(L, name).argtypes = [vp]
+        getattr(L, name).restype = None
+    L.tqc_plan_options_default.argtypes = [ctypes.POINTER(PlanOptions)]
+    L.tqc_plan_options_default.restype = None
+    L.tqc_status_string.argtypes = [ctypes.c_int]
+    L.tqc_status_string.restype = ctypes.c_char_p
+    L.tqc_last_error.argtypes = []
+    L.tqc_last_error.restype = ctypes.c_char_p
+    L.tqc_version.restype = ctypes.c_int32
+
+
+def lib():
+    """Load libtqc.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2502_03445_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _LIB = L
+    return _LIB
+
+
+def _check(st):
+    if st != 0:
+        L = lib()
+        raise TqcError(st, f"{L.tqc_status_string(st).decode()}: {L.tqc_last_error().decode()}")
+
+
+def _i32arr(vals):
+    a = (ctypes.c_int32 * max(1, len(vals)))(*[int(v) for v in vals])
+    return a
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Network:
+    """Subcircuit tensors plus cut-edge list (host copy; device upload on demand).
+
+    tensors: sequence of (cut_ids, output_qubits, basis, data) with basis
+    "raw" or "pauli" and data a float64 2-D array in the layout of tqc.h.
+    cuts: sequence of (upstream_tensor, downstream_tensor)."""
+
+    def __init__(self, n, tensors, cuts):
+        L = lib()
+        self._keep = []
+        descs = (TensorDesc * len(tensors))()
+        for d, (cids, outs, basis, data) in zip(descs, tensors):
+            arr = np.ascontiguousarray(np.asarray(data, dtype=np.float64))
+            ci, oq = _i32arr(cids), _i32arr(outs)
+            self._keep += [arr, ci, oq]
+            d.num_cuts = len(cids)
+            d.cut_ids = ctypes.cast(ci, _i32p)
+            d.num_outputs = len(outs)
+            d.output_qubits = ctypes.cast(oq, _i32p)
+            d.basis = BASES[basis]
+            d.data = arr.ctypes.data_as(_dp)
+        cc = (Cut * max(1, len(cuts)))(*[Cut(int(u), int(v)) for u, v in cuts])
+        h = ctypes.c_void_p()
+        _check(L.tqc_network_create(int(n), len(tensors), descs, len(cuts), cc, ctypes.byref(h)))
+        self._keep = None
+        self.handle = h
+        self.n = int(n)
+        self.m = len(tensors)
+        self.num_cuts = len(cuts)
+        self.shapes = [(len(t[0]), len(t[1])) for t in tensors]
+
+    @classmethod
+    def from_spec(cls, spec):
+        """From any object with .n, .cuts and .tensors (cut_ids, outputs, basis, data)."""
+        return cls(spec.n, [(t.cut_ids, t.outputs, t.basis, t.data) for t in spec.tensors], spec.cuts)
+
+    def upload(self):
+        _check(lib().tqc_network_upload(self.handle))
+
+    def pauli_tensor(self, j, stream=None):
+        c, o = self.shapes[j]
+        out = torch.empty((4 ** c, 1 << o), dtype=torch.float64, device="cuda")
+        _check(lib().tqc_network_pauli_tensor(self.handle, int(j), ctypes.c_void_p(out.data_ptr()),
+                                              out.numel() * 8, _stream_ptr(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.tqc_network_destroy(h)
+            self.handle = None
+
+
+class Plan:
+    """Contraction plan: order, slicing, GEMM mapping (host-only until executed)."""
+
+    def __init__(self, net, precision="fp32", out_dtype="f32", mem_budget=0, fixed=None,
+                 order=None, sliced=None, cost="flopbyte", cost_model=None, num_candidates=0,
+                 seed=0, tile_policy=0):
+        L = lib()
+        o = PlanOptions()
+        L.tqc_plan_options_default(ctypes.byref(o))
+        o.precision = PRECISIONS[precision]
+        o.out_dtype = DTYPES[out_dtype]
+        o.mem_budget_bytes = int(mem_budget)
+        keep = []
+        if fixed:
+            fq, fv = zip(*sorted(fixed.items()))
+            a, b = _i32arr(fq), _i32arr(fv)
+            keep += [a, b]
+            o.num_fixed = len(fq)
+            o.fixed_qubits = ctypes.cast(a, _i32p)
+            o.fixed_values = ctypes.cast(b, _i32p)
+        if order is not None:
+            flat = [int(x) for pair in order for x in pair]
+            a = _i32arr(flat)
+            keep.append(a)
+            o.num_order_steps = len(order)
+            o.order = ctypes.cast(a, _i32p)
+        if sliced is not None:
+            a = _i32arr(sliced)
+            keep.append(a)
+            o.num_sliced = len(sliced)
+            o.sliced_cuts = ctypes.cast(a, _i32p)
+        o.cost_kind = COST[cost]
+        o.cost_model = cost_model.handle if cost_model is not None else None
+        o.num_candidates = int(num_candidates)
+        o.seed = int(seed)
+        o.tile_policy = int(tile_policy)
+        h = ctypes.c_void_p()
+        _check(L.tqc_plan_create(net.handle, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self.net = net  # keep the network alive
+        self.out_dtype = out_dtype
+        st = PlanStats()
+        _check(L.tqc_plan_get_stats(h, ctypes.byref(st)))
+        self.stats = {f: getattr(st, f) for f, _ in PlanStats._fields_}
+        self.out_qubits = st.out_qubits
+        self.out_entries = st.out_entries
+
+    @property
+    def steps(self):
+        res = []
+        for s in range(self.stats["num_steps"]):
+            info = StepInfo()
+            _check(lib().tqc_plan_get_step(self.handle, s, ctypes.byref(info)))
+            res.append({f: getattr(info, f) for f, _ in StepInfo._fields_})
+        return res
+
+    @property
+    def sliced(self):
+        n = self.stats["num_sliced"]
+        a = (ctypes.c_int32 * max(1, n))()
+        _check(lib().tqc_plan_get_sliced(self.handle, ctypes.cast(a, _i32p)))
+        return [a[i] for i in range(n)]
+
+    def output_tensor(self, device="cuda"):
+        dt = torch.float32 if self.out_dtype == "f32" else torch.float64
+        return torch.empty(self.out_entries, dtype=dt, device=device)
+
+    def execute(self, out=None, stream=None):
+        if out is None:
+            out = self.output_tensor()
+        _check(lib().tqc_execute(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                 out.numel() * out.element_size(), _stream_ptr(stream)))
+        return out
+
+    def execute_profiled(self, out=None, stream=None):
+        """Execute and return (out, phase_ms): [transform, pack, step 0.., finalize]."""
+        if out is None:
+            out = self.output_tensor()
+        n = 3 + self.stats["num_steps"]
+        ms = (ctypes.c_double * n)()
+        _check(lib().tqc_execute_profiled(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                          out.numel() * out.element_size(), _stream_ptr(stream),
+                                          ctypes.cast(ms, _dp), n))
+        return out, [ms[i] for i in range(n)]
+
+    def execute_slices(self, out, begin, end, accumulate=True, stream=None):
+        assert out.dtype == torch.float64
+        _check(lib().tqc_execute_slices(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                        out.numel() * 8, int(begin), int(end), int(bool(accumulate)),
+                                        _stream_ptr(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.tqc_plan_destroy(h)
+            self.handle = None
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return DTYPES["f32"]
+    if t.dtype == torch.float64:
+        return DTYPES["f64"]
+    raise TypeError("probabilities must be float32 or float64")
+
+
+def topk(probs, k, stream=None):
+    """k largest entries (value desc, index asc): (int64 indices, float64 values) on device."""
+    idx = torch.empty(k, dtype=torch.int64, device=probs.device)
+    val = torch.empty(k, dtype=torch.float64, device=probs.device)
+    _check(lib().tqc_topk(ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), probs.numel(), int(k),
+                          ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                          _stream_ptr(stream)))
+    return idx, val
+
+
+def marginal(probs, num_qubits, keep, stream=None):
+    """float64 marginal over the kept qubits (bit i of the result index = keep[i])."""
+    if probs.numel() != (1 << int(num_qubits)):
+        raise ValueError("probs must hold 2^num_qubits entries")
+    out = torch.empty(1 << len(keep), dtype=torch.float64, device=probs.device)
+    k = _i32arr(keep)
+    _check(lib().tqc_marginal(ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), int(num_qubits),
+                              len(keep), ctypes.cast(k, _i32p), ctypes.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream)))
+    return out

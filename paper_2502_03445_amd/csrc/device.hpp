@@ -1,0 +1,71 @@
+// Device-side helpers and kernel argument structs shared by the kernels and
+// the executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tqc {
+
+constexpr int kMaxBits = 48;   // index bits per tensor
+constexpr int kMaxCutsT = 16;  // cuts per raw tensor in the transform kernel
+
+// ------------------------------------------------------------- bfloat16
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// ----------------------------------------------------------- transform
+// Direct form of the Pauli-basis transform for one raw tensor: every output
+// element T[sigma][x] is a signed sum over the measured cut bits of the
+// upstream cuts and the two or three preparations that build each Pauli on
+// the downstream cuts.
+struct TransformArgs {
+  const double *raw;
+  double *out;
+  int c, o, u;
+  int up[kMaxCutsT];        // 1 if upstream end
+  int bbit[kMaxCutsT];      // upstream: index of its measured bit in b
+  uint64_t w[kMaxCutsT];    // mixed-radix weight of the cut's raw row digit
+};
+
+// ---------------------------------------------------------------- pack
+// Gather one leaf operand from its float64 Pauli tensor: slice / fixed-qubit
+// selection via a base offset, arbitrary bit permutation, cast or split.
+struct PackArgs {
+  const double *src;
+  void *dst0, *dst1, *dst2;  // planes
+  uint64_t base;             // source offset of the fixed bits
+  int nbits;                 // destination index bits (k bits first)
+  int lk, kpad;              // k bits and padded row stride (log2)
+  int inpos[kMaxBits];       // source bit position of destination bit i
+  int prec;                  // 0 f64, 1 f32, 2 bf16x2 split, 3 bf16x3 split
+  double scale;              // exact power of two
+};
+
+// ---------------------------------------------------------------- GEMM
+enum OutKind : int {
+  OUT_F64 = 0,
+  OUT_F32 = 1,
+  OUT_SPLIT2 = 2,  // bfloat16 hi/lo planes
+  OUT_SPLIT3 = 3,  // bfloat16 hi/mid/lo planes
+  OUT_F64_ACC = 4, // float64 +=
+};
+
+struct GemmArgs {
+  const void *a0, *a1, *a2;  // operand A planes, [M][2^kpad]
+  const void *b0, *b1, *b2;  // operand B planes, [N][2^kpad]
+  void *c0, *c1, *c2;        // output planes
+  int lm, ln, lk, kpad;
+  int out_kind;
+  double scale;
+  uint8_t posM[kMaxBits];
+  uint8_t posN[kMaxBits];
+};
+
+}  // namespace tqc

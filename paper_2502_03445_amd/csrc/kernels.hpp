@@ -1,0 +1,25 @@
+// Host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace tqc {
+
+hipError_t launch_transform(const TransformArgs &a, hipStream_t s);
+hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s);
+hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
+// prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
+hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s);
+
+// output forms
+hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
+                       double *val_out, void *scratch, uint64_t scratch_bytes, hipStream_t s);
+uint64_t topk_scratch_bytes(uint64_t len, int k);
+hipError_t launch_marginal(const void *probs, int dtype, int n, int num_keep, const int *keep,
+                           double *out, void *scratch, uint64_t scratch_bytes, hipStream_t s);
+uint64_t marginal_scratch_bytes(int n, int num_keep);
+
+}  // namespace tqc

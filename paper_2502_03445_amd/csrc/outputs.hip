@@ -1,0 +1,432 @@
+// Output forms of a reconstructed probability vector: top-k (the sum of the
+// top |HSS| entries is P_HSS^max, Eq. (10)) and marginals / the total
+// probability.  Both are HBM-bound scans; both are deterministic (integer
+// atomics only, float64 sums in a fixed order).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace tqc {
+
+// ================================================================ top-k
+// Exact selection of the k-th largest value by radix select over an
+// order-preserving integer key (11-bit digits, most significant first), then
+// collection of every entry above that value plus the lowest-index entries
+// equal to it, then a bitonic sort of the k winners by (value desc, index
+// asc).
+
+constexpr int kDigitBits = 11;
+constexpr int kBins = 1 << kDigitBits;
+constexpr uint64_t kChunk = 1ull << 16;  // elements per block in ordered passes
+constexpr int kMaxK = 4096;
+
+struct TopkState {
+  unsigned long long prefix;  // resolved high key bits
+  int hi_shift;               // bits >= hi_shift are resolved
+  int pad;
+  unsigned long long kr;      // entries still needed among those matching prefix
+  unsigned long long n_gt;    // slots used by entries strictly above the threshold
+};
+
+__device__ inline uint64_t sort_key(const void *p, int dtype, uint64_t i) {
+  if (dtype == 1) {
+    uint32_t u = ((const uint32_t *)p)[i];
+    return (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+  }
+  uint64_t u = ((const uint64_t *)p)[i];
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double key_value(uint64_t key, int dtype) {
+  if (dtype == 1) {
+    uint32_t k = (uint32_t)key;
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return (double)__builtin_bit_cast(float, u);
+  }
+  uint64_t u = (key & 0x8000000000000000ull) ? (key & 0x7fffffffffffffffull) : ~key;
+  return __builtin_bit_cast(double, u);
+}
+
+__global__ void __launch_bounds__(256) topk_init(TopkState *st, unsigned long long *hist,
+                                                 int keybits, int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->prefix = 0;
+    st->hi_shift = keybits;
+    st->kr = (unsigned long long)k;
+    st->n_gt = 0;
+  }
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+}
+
+__global__ void __launch_bounds__(256) topk_hist(const void *p, int dtype, uint64_t len,
+                                                 const TopkState *st, unsigned long long *hist,
+                                                 int bits) {
+  __shared__ unsigned int lh[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const int hs = st->hi_shift;
+  const uint64_t prefix = st->prefix;
+  const int shift = hs - bits;
+  const uint64_t mask = (1ull << bits) - 1;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < len;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = sort_key(p, dtype, i);
+    const bool match = (hs >= 64) ? true : ((key >> hs) == (prefix >> hs));
+    if (match) atomicAdd(&lh[(key >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], (unsigned long long)lh[b]);
+}
+
+__global__ void topk_select(TopkState *st, unsigned long long *hist, int bits) {
+  if (threadIdx.x == 0) {
+    const int shift = st->hi_shift - bits;
+    unsigned long long cum = 0;
+    for (int b = (1 << bits) - 1; b >= 0; --b) {
+      const unsigned long long h = hist[b];
+      if (cum + h >= st->kr) {
+        st->prefix |= (unsigned long long)b << shift;
+        st->kr -= cum;
+        break;
+      }
+      cum += h;
+    }
+    st->hi_shift = shift;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+}
+
+// entries strictly above the threshold go to candidate slots [0, n_gt);
+// per-block counts of entries equal to it feed the ordered pass
+__global__ void __launch_bounds__(256) topk_collect_gt(const void *p, int dtype, uint64_t len,
+                                                       TopkState *st, uint64_t *cand_key,
+                                                       uint64_t *cand_idx,
+                                                       unsigned long long *blockcnt) {
+  __shared__ unsigned int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const uint64_t tau = st->prefix;
+  const uint64_t lo = blockIdx.x * kChunk;
+  const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
+  unsigned int mine = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const uint64_t key = sort_key(p, dtype, i);
+    if (key > tau) {
+      const unsigned long long s = atomicAdd(&st->n_gt, 1ull);
+      cand_key[s] = key;
+      cand_idx[s] = i;
+    } else if (key == tau) {
+      ++mine;
+    }
+  }
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) blockcnt[blockIdx.x] = cnt;
+}
+
+// exclusive scan of the per-block equal counts (one block, fixed order)
+__global__ void __launch_bounds__(1024) topk_scan(unsigned long long *blockcnt, uint64_t nblocks) {
+  __shared__ unsigned long long part[1024];
+  const uint64_t per = (nblocks + 1023) / 1024;
+  const uint64_t b0 = threadIdx.x * per;
+  unsigned long long s = 0;
+  for (uint64_t b = b0; b < b0 + per && b < nblocks; ++b) s += blockcnt[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const unsigned long long v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  unsigned long long run = part[threadIdx.x];
+  for (uint64_t b = b0; b < b0 + per && b < nblocks; ++b) {
+    const unsigned long long v = blockcnt[b];
+    blockcnt[b] = run;
+    run += v;
+  }
+}
+
+// equal entries in index order: the first kr of them are selected
+__global__ void __launch_bounds__(256) topk_collect_eq(const void *p, int dtype, uint64_t len,
+                                                       const TopkState *st, int k,
+                                                       uint64_t *cand_key, uint64_t *cand_idx,
+                                                       const unsigned long long *blockpre) {
+  const unsigned long long need = st->kr;
+  const unsigned long long base = blockpre[blockIdx.x];
+  if (base >= need) return;
+  const uint64_t tau = st->prefix;
+  const uint64_t lo = blockIdx.x * kChunk;
+  const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
+  const unsigned long long slot0 = (unsigned long long)k - need;
+  __shared__ unsigned int wcount[4];
+  __shared__ unsigned long long run;
+  if (threadIdx.x == 0) run = base;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint64_t c = lo; c < hi; c += blockDim.x) {
+    const uint64_t i = c + threadIdx.x;
+    const bool eq = (i < hi) && (sort_key(p, dtype, i) == tau);
+    const unsigned long long bal = __ballot(eq);
+    const unsigned int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    unsigned long long r = run;
+    for (int w = 0; w < wave; ++w) r += wcount[w];
+    r += below;
+    if (eq && r < need) {
+      cand_key[slot0 + r] = tau;
+      cand_idx[slot0 + r] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) run += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();
+    if (run >= need) break;
+  }
+}
+
+// bitonic sort of k (padded to a power of two) by (key desc, index asc)
+__global__ void __launch_bounds__(1024) topk_sort(const uint64_t *cand_key, const uint64_t *cand_idx,
+                                                  int k, int dtype, uint64_t *idx_out,
+                                                  double *val_out) {
+  __shared__ uint64_t sk[kMaxK];
+  __shared__ uint64_t si[kMaxK];
+  int n = 1;
+  while (n < k) n <<= 1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if (i < k) {
+      sk[i] = cand_key[i];
+      si[i] = cand_idx[i];
+    } else {
+      sk[i] = 0;
+      si[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  // "before(a, b)": a sorts earlier than b
+  auto before = [](uint64_t ka, uint64_t ia, uint64_t kb, uint64_t ib) {
+    return ka > kb || (ka == kb && ia < ib);
+  };
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = ((lo & size) == 0);
+        const bool swap = asc ? before(sk[hi], si[hi], sk[lo], si[lo])
+                              : before(sk[lo], si[lo], sk[hi], si[hi]);
+        if (swap) {
+          uint64_t a = sk[lo]; sk[lo] = sk[hi]; sk[hi] = a;
+          a = si[lo]; si[lo] = si[hi]; si[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    idx_out[i] = si[i];
+    val_out[i] = key_value(sk[i], dtype);
+  }
+}
+
+uint64_t topk_scratch_bytes(uint64_t len, int k) {
+  const uint64_t nblocks = (len + kChunk - 1) / kChunk;
+  return 256 + kBins * 8 + nblocks * 8 + 2 * (uint64_t)k * 8 + 1024;
+}
+
+hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
+                       double *val_out, void *scratch, uint64_t scratch_bytes, hipStream_t s) {
+  if (k < 1 || k > kMaxK || (uint64_t)k > len) return hipErrorInvalidValue;
+  if (scratch_bytes < topk_scratch_bytes(len, k)) return hipErrorInvalidValue;
+  char *sp = (char *)scratch;
+  TopkState *st = (TopkState *)sp;
+  unsigned long long *hist = (unsigned long long *)(sp + 256);
+  const uint64_t nblocks = (len + kChunk - 1) / kChunk;
+  unsigned long long *blockcnt = hist + kBins;
+  uint64_t *cand_key = (uint64_t *)(blockcnt + nblocks);
+  uint64_t *cand_idx = cand_key + k;
+  const int keybits = dtype == 1 ? 32 : 64;
+  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, st, hist, keybits, k);
+  uint64_t hb = (len + 255) / 256;
+  if (hb > 8192) hb = 8192;
+  for (int resolved = 0; resolved < keybits;) {
+    const int bits = (keybits - resolved) < kDigitBits ? (keybits - resolved) : kDigitBits;
+    hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb), dim3(256), 0, s, probs, dtype, len, st, hist, bits);
+    hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, st, hist, bits);
+    resolved += bits;
+  }
+  hipLaunchKernelGGL(topk_collect_gt, dim3((unsigned)nblocks), dim3(256), 0, s, probs, dtype, len, st,
+                     cand_key, cand_idx, blockcnt);
+  hipLaunchKernelGGL(topk_scan, dim3(1), dim3(1024), 0, s, blockcnt, nblocks);
+  hipLaunchKernelGGL(topk_collect_eq, dim3((unsigned)nblocks), dim3(256), 0, s, probs, dtype, len, st,
+                     k, cand_key, cand_idx, blockcnt);
+  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, cand_key, cand_idx, k, dtype, idx_out,
+                     val_out);
+  return hipGetLastError();
+}
+
+// ============================================================= marginal
+// out[y] = sum over x with bit keep[i] of x equal to bit i of y.
+// Pass 1: block b owns the contiguous chunk [b*2^c, (b+1)*2^c); the kept
+// bits below c give 2^rlo bins, each summed by a fixed set of threads in a
+// fixed order, then combined by a fixed tree: partial[b][bin].
+// Pass 2: out[y] = sum over the blocks whose kept high bits match y, in block
+// order, by one block per y (fixed strided split + fixed tree).
+struct MargArgs {
+  const void *p;
+  int dtype;
+  int n, c;              // qubits, log2 chunk
+  int rlo;               // kept bits below c
+  int keep_lo_pos[24];   // address bit of bin bit i (kept, < c), bin bit i <-> y bit ylo_bit[i]
+  int free_lo_pos[40];   // address bits < c that are summed, in increasing order
+  int nfree_lo;
+  double *partial;
+};
+
+__device__ inline double load_prob(const void *p, int dtype, uint64_t i) {
+  return dtype == 1 ? (double)((const float *)p)[i] : ((const double *)p)[i];
+}
+
+__global__ void __launch_bounds__(256) marg_pass1(MargArgs a) {
+  __shared__ double red[256];
+  const uint64_t base = (uint64_t)blockIdx.x << a.c;
+  const int nbins = 1 << a.rlo;
+  const uint64_t per_bin = 1ull << a.nfree_lo;
+  for (int bin0 = 0; bin0 < nbins; bin0 += 256) {
+    // threads per bin when bins < 256
+    const int bins_here = (nbins - bin0) < 256 ? (nbins - bin0) : 256;
+    const int tpb = 256 / bins_here;  // bins_here is a power of two
+    const int bin = bin0 + (int)(threadIdx.x % bins_here);
+    const int sub = (int)(threadIdx.x / bins_here);
+    uint64_t boff = 0;
+    for (int i = 0; i < a.rlo; ++i) boff |= (uint64_t)((bin >> i) & 1) << a.keep_lo_pos[i];
+    double s = 0.0;
+    if (sub < tpb) {
+      for (uint64_t z = sub; z < per_bin; z += tpb) {
+        uint64_t off = boff;
+        for (int i = 0; i < a.nfree_lo; ++i) off |= ((z >> i) & 1ull) << a.free_lo_pos[i];
+        s += load_prob(a.p, a.dtype, base + off);
+      }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    // tree over the threads of each bin (threads bin + bins_here * sub)
+    for (int w = tpb / 2; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w * bins_here) red[threadIdx.x] += red[threadIdx.x + w * bins_here];
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < bins_here)
+      a.partial[(uint64_t)blockIdx.x * nbins + bin0 + threadIdx.x] = red[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+struct Marg2Args {
+  const double *partial;
+  double *out;
+  int rlo, rhi;
+  int nblk_bits;               // log2 number of pass-1 blocks
+  int keep_hi_blockbit[24];    // block-index bit of y's high kept bit j
+  int free_hi_blockbit[40];    // block-index bits summed over, increasing
+  int nfree_hi;
+  int ylo_of_bin[24];          // y bit of bin bit i
+  int yhi_bit[24];             // y bit of high kept bit j
+};
+
+__global__ void __launch_bounds__(256) marg_pass2(Marg2Args a) {
+  __shared__ double red[256];
+  const uint64_t y = blockIdx.x;
+  uint64_t bin = 0;
+  for (int i = 0; i < a.rlo; ++i) bin |= ((y >> a.ylo_of_bin[i]) & 1ull) << i;
+  uint64_t bbase = 0;
+  for (int j = 0; j < a.rhi; ++j) bbase |= ((y >> a.yhi_bit[j]) & 1ull) << a.keep_hi_blockbit[j];
+  const uint64_t nsum = 1ull << a.nfree_hi;
+  double s = 0.0;
+  for (uint64_t w = threadIdx.x; w < nsum; w += 256) {
+    uint64_t b = bbase;
+    for (int i = 0; i < a.nfree_hi; ++i) b |= ((w >> i) & 1ull) << a.free_hi_blockbit[i];
+    s += a.partial[(b << a.rlo) + bin];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.out[y] = red[0];
+}
+
+static int marg_chunk_bits(int n) { return n < 16 ? n : 16; }
+
+uint64_t marginal_scratch_bytes(int n, int num_keep) {
+  const int c = marg_chunk_bits(n);
+  return (uint64_t)8 << (n - c + (num_keep < c ? num_keep : c));
+}
+
+hipError_t launch_marginal(const void *probs, int dtype, int n, int num_keep, const int *keep,
+                           double *out, void *scratch, uint64_t scratch_bytes, hipStream_t s) {
+  if (n < 0 || n > 40 || num_keep < 0 || num_keep > 24 || num_keep > n) return hipErrorInvalidValue;
+  const int c = marg_chunk_bits(n);
+  MargArgs a{};
+  a.p = probs;
+  a.dtype = dtype;
+  a.n = n;
+  a.c = c;
+  int rlo = 0, nfl = 0;
+  int ylo_of_bin[24], yhi_bit[24], keep_hi_blockbit[24];
+  int rhi = 0;
+  // kept address bits below c, in increasing address order
+  for (int bit = 0; bit < n; ++bit) {
+    int yi = -1;
+    for (int i = 0; i < num_keep; ++i)
+      if (keep[i] == bit) yi = i;
+    if (bit < c) {
+      if (yi >= 0) {
+        a.keep_lo_pos[rlo] = bit;
+        ylo_of_bin[rlo] = yi;
+        ++rlo;
+      } else {
+        a.free_lo_pos[nfl++] = bit;
+      }
+    } else if (yi >= 0) {
+      yhi_bit[rhi] = yi;
+      keep_hi_blockbit[rhi] = bit - c;
+      ++rhi;
+    }
+  }
+  a.rlo = rlo;
+  a.nfree_lo = nfl;
+  const uint64_t nblocks = 1ull << (n - c);
+  if (scratch_bytes < (nblocks << rlo) * 8) return hipErrorInvalidValue;
+  a.partial = (double *)scratch;
+  hipLaunchKernelGGL(marg_pass1, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  Marg2Args b{};
+  b.partial = a.partial;
+  b.out = out;
+  b.rlo = rlo;
+  b.rhi = rhi;
+  b.nblk_bits = n - c;
+  int nfh = 0;
+  for (int bb = 0; bb < n - c; ++bb) {
+    bool kept = false;
+    for (int j = 0; j < rhi; ++j)
+      if (keep_hi_blockbit[j] == bb) kept = true;
+    if (!kept) b.free_hi_blockbit[nfh++] = bb;
+  }
+  b.nfree_hi = nfh;
+  for (int i = 0; i < rlo; ++i) b.ylo_of_bin[i] = ylo_of_bin[i];
+  for (int j = 0; j < rhi; ++j) {
+    b.yhi_bit[j] = yhi_bit[j];
+    b.keep_hi_blockbit[j] = keep_hi_blockbit[j];
+  }
+  hipLaunchKernelGGL(marg_pass2, dim3((unsigned)(1ull << num_keep)), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace tqc
