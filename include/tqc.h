@@ -227,6 +227,93 @@ tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
 tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
                         int32_t num_keep, const int32_t *keep, double *out, void *stream);
 
+/* -------------------------------------------------------------------- batch
+ * Many independent reconstructions in one persistent launch (one kernel
+ * whose workgroups claim transform chunks, pack chunks and GEMM tiles of all
+ * jobs from a shared queue in dependency order), captured once into a HIP
+ * graph and replayed.  Jobs are unsliced plans of one precision; outputs are
+ * bound at creation (device pointers, out_entries of each plan's out_dtype).
+ * The batch keeps pointers to the plans: destroy it before them. */
+typedef struct tqc_batch_s *tqc_batch_t;
+
+typedef struct {
+  int32_t use_graph;           /* 1: capture reset + launch in a HIP graph   */
+  int32_t grid;                /* workgroups; 0 = occupancy x compute units  */
+  uint64_t spin_limit;         /* bound of each dependency wait; 0 = default.
+                                  On overrun the item sets the batch error
+                                  flag and skips its work (the launch still
+                                  completes); tqc_batch_job_times reports it. */
+} tqc_batch_options;
+
+tqc_status tqc_batch_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                            const uint64_t *out_bytes, const tqc_batch_options *opt,
+                            void *stream, tqc_batch_t *out);
+tqc_status tqc_batch_execute(tqc_batch_t batch, void *stream);
+
+/* The same jobs as one ordinary tqc_execute each, in order, on `stream`
+ * (the baseline).  Synchronous; job_ms[2j], job_ms[2j+1] = start and end of
+ * job j in ms since the first job started (HIP events). */
+tqc_status tqc_batch_execute_sequential(tqc_batch_t batch, void *stream, double *job_ms);
+
+/* After tqc_batch_execute: waits for the stream, then gives each job's first
+ * and last item times (device wall clock, ms since the earliest start) and
+ * the error flag (nonzero if a dependency wait overran). */
+tqc_status tqc_batch_job_times(tqc_batch_t batch, double *start_ms, double *end_ms,
+                               uint32_t *error);
+tqc_status tqc_batch_info(tqc_batch_t batch, uint64_t *items, int32_t *units, int32_t *grid);
+void tqc_batch_destroy(tqc_batch_t batch);
+
+/* ----------------------------------------------------------------- autotune
+ * Time every tile shape for each step of an (unsliced) plan with HIP events,
+ * keep the fastest in the plan and in a process-wide table keyed by
+ * (precision, log2 M, log2 N, log2 K); plans created with tile_policy = 1
+ * take their tiles from that table.  Save / load keep it across processes. */
+tqc_status tqc_plan_autotune(tqc_plan_t plan, void *out, uint64_t out_bytes, int32_t reps,
+                             void *stream);
+tqc_status tqc_autotune_save(const char *path);
+tqc_status tqc_autotune_load(const char *path);
+
+/* --------------------------------------------------------------- cost model
+ * A small MLP (16 features -> 64 -> 64 -> 1, ReLU, float32) predicting the
+ * natural log of one contraction launch's device time; trained on timings
+ * of the plain contractor (tqc_execute_profiled) with the library's own
+ * forward / backward / Adam kernels, and used by tqc_plan_create with
+ * cost_kind = TQC_COST_MLP to rank num_candidates contraction orders (the
+ * roofline planner's choice, its greedy variant and randomised-greedy
+ * samples) for the roofline planner's slicing.  The flop/byte model stays
+ * the fallback (TQC_COST_FLOPBYTE).  Feature rows come from
+ * tqc_plan_step_features (raw; the model normalises with statistics taken
+ * from its training data).  Parameter vector order: W1 (16x64, row-major),
+ * b1, W2 (64x64), b2, w3, b3.  Host arrays throughout. */
+typedef struct {
+  int32_t epochs;              /* default 200                                 */
+  int32_t batch;               /* default 256                                 */
+  float lr;                    /* Adam step size, default 3e-3                */
+  uint64_t seed;               /* shuffling                                   */
+} tqc_train_options;
+
+tqc_status tqc_costmodel_create(uint64_t seed, tqc_costmodel_t *out);
+void tqc_costmodel_destroy(tqc_costmodel_t m);
+int32_t tqc_costmodel_num_params(void);
+int32_t tqc_costmodel_num_features(void);
+tqc_status tqc_costmodel_get_params(tqc_costmodel_t m, float *out, int32_t n);
+tqc_status tqc_costmodel_set_params(tqc_costmodel_t m, const float *in, int32_t n);
+/* raw network (no normalisation): y[i] = f(x[i, :]) */
+tqc_status tqc_costmodel_forward(tqc_costmodel_t m, const float *x, int64_t n, float *y, void *stream);
+/* raw gradient of mean_i (f(x_i) - t_i)^2 with respect to the parameters */
+tqc_status tqc_costmodel_gradients(tqc_costmodel_t m, const float *x, const float *t, int64_t n,
+                                   float *grad, void *stream);
+/* fit on (raw features, measured seconds); loss_per_epoch (may be NULL)
+ * receives the normalised training MSE after each epoch */
+tqc_status tqc_costmodel_train(tqc_costmodel_t m, const float *feats, const float *seconds, int64_t n,
+                               const tqc_train_options *opt, float *loss_per_epoch, void *stream);
+tqc_status tqc_costmodel_predict(tqc_costmodel_t m, const float *feats, int64_t n, double *seconds,
+                                 void *stream);
+tqc_status tqc_costmodel_save(tqc_costmodel_t m, const char *path);
+tqc_status tqc_costmodel_load(const char *path, tqc_costmodel_t *out);
+/* raw feature rows (num_steps x 16) of a plan's launches */
+tqc_status tqc_plan_step_features(tqc_plan_t plan, float *out, int32_t max_steps);
+
 /* --------------------------------------------------------------------- misc */
 const char *tqc_status_string(tqc_status s);
 const char *tqc_last_error(void);

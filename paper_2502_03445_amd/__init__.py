@@ -20,7 +20,8 @@ import os
 import numpy as np
 import torch
 
-__all__ = ["lib", "Network", "Plan", "topk", "marginal", "TqcError", "PRECISIONS"]
+__all__ = ["lib", "Network", "Plan", "Batch", "CostModel", "step_features", "topk", "marginal", "autotune", "autotune_save",
+           "autotune_load", "TqcError", "PRECISIONS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtqc.so")
@@ -72,6 +73,16 @@ class StepInfo(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("spin_limit", ctypes.c_uint64)]
+
+
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 class TqcError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -97,12 +108,38 @@ def _declare(L):
         "tqc_network_pauli_tensor": [vp, i32, vp, u64, vp],
         "tqc_topk": [vp, ctypes.c_int, u64, i32, vp, vp, vp],
         "tqc_marginal": [vp, ctypes.c_int, i32, i32, _i32p, vp, vp],
+        "tqc_batch_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64),
+                             ctypes.POINTER(BatchOptions), vp, ctypes.POINTER(vp)],
+        "tqc_batch_execute": [vp, vp],
+        "tqc_batch_execute_sequential": [vp, vp, _dp],
+        "tqc_batch_job_times": [vp, _dp, _dp, ctypes.POINTER(ctypes.c_uint32)],
+        "tqc_batch_info": [vp, ctypes.POINTER(u64), _i32p, _i32p],
+        "tqc_plan_autotune": [vp, vp, u64, i32, vp],
+        "tqc_autotune_save": [ctypes.c_char_p],
+        "tqc_autotune_load": [ctypes.c_char_p],
+        "tqc_costmodel_create": [u64, ctypes.POINTER(vp)],
+        "tqc_costmodel_get_params": [vp, ctypes.POINTER(ctypes.c_float), i32],
+        "tqc_costmodel_set_params": [vp, ctypes.POINTER(ctypes.c_float), i32],
+        "tqc_costmodel_forward": [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_float), vp],
+        "tqc_costmodel_gradients": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_float), vp],
+        "tqc_costmodel_train": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                ctypes.c_int64, ctypes.POINTER(TrainOptions),
+                                ctypes.POINTER(ctypes.c_float), vp],
+        "tqc_costmodel_predict": [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int64, _dp, vp],
+        "tqc_costmodel_save": [vp, ctypes.c_char_p],
+        "tqc_costmodel_load": [ctypes.c_char_p, ctypes.POINTER(vp)],
+        "tqc_plan_step_features": [vp, ctypes.POINTER(ctypes.c_float), i32],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
-    for name in ("tqc_network_destroy", "tqc_plan_destroy"):
+    L.tqc_costmodel_num_params.restype = ctypes.c_int32
+    L.tqc_costmodel_num_features.restype = ctypes.c_int32
+    for name in ("tqc_network_destroy", "tqc_plan_destroy", "tqc_batch_destroy",
+                 "tqc_costmodel_destroy"):
         getattr(L, name).argtypes = [vp]
         getattr(L, name).restype = None
     L.tqc_plan_options_default.argtypes = [ctypes.POINTER(PlanOptions)]
@@ -326,3 +363,160 @@ def marginal(probs, num_qubits, keep, stream=None):
                               len(keep), ctypes.cast(k, _i32p), ctypes.c_void_p(out.data_ptr()),
                               _stream_ptr(stream)))
     return out
+
+
+class Batch:
+    """Independent reconstructions run as one persistent, graph-captured launch."""
+
+    def __init__(self, plans, outs=None, use_graph=True, grid=0, spin_limit=0, stream=None):
+        L = lib()
+        if outs is None:
+            outs = [p.output_tensor() for p in plans]
+        self.plans = list(plans)
+        self.outs = list(outs)
+        n = len(self.plans)
+        ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
+        ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
+        opt = BatchOptions(int(bool(use_graph)), int(grid), int(spin_limit))
+        h = ctypes.c_void_p()
+        _check(L.tqc_batch_create(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check(lib().tqc_batch_execute(self.handle, _stream_ptr(stream)))
+
+    def execute_sequential(self, stream=None):
+        n = len(self.plans)
+        ms = (ctypes.c_double * (2 * n))()
+        _check(lib().tqc_batch_execute_sequential(self.handle, _stream_ptr(stream),
+                                                  ctypes.cast(ms, _dp)))
+        return np.array(ms[:]).reshape(n, 2)
+
+    def job_times(self):
+        n = len(self.plans)
+        a = (ctypes.c_double * n)()
+        b = (ctypes.c_double * n)()
+        err = ctypes.c_uint32()
+        _check(lib().tqc_batch_job_times(self.handle, ctypes.cast(a, _dp), ctypes.cast(b, _dp),
+                                         ctypes.byref(err)))
+        return np.array(a[:]), np.array(b[:]), err.value
+
+    def info(self):
+        items = ctypes.c_uint64()
+        units = ctypes.c_int32()
+        grid = ctypes.c_int32()
+        _check(lib().tqc_batch_info(self.handle, ctypes.byref(items), ctypes.byref(units),
+                                    ctypes.byref(grid)))
+        return {"items": items.value, "units": units.value, "grid": grid.value}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.tqc_batch_destroy(h)
+            self.handle = None
+
+
+def autotune(plan, out=None, reps=3, stream=None):
+    """Measure every tile shape per step; keep the fastest (also in the process table)."""
+    if out is None:
+        out = plan.output_tensor()
+    _check(lib().tqc_plan_autotune(plan.handle, ctypes.c_void_p(out.data_ptr()),
+                                   out.numel() * out.element_size(), int(reps), _stream_ptr(stream)))
+    return [s["tile"] for s in plan.steps]
+
+
+def autotune_save(path):
+    _check(lib().tqc_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path):
+    _check(lib().tqc_autotune_load(os.fsencode(path)))
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+def _f32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return a, a.ctypes.data_as(_fp)
+
+
+class CostModel:
+    """MLP cost model (16 -> 64 -> 64 -> 1) trained and evaluated on the GPU."""
+
+    def __init__(self, seed=1, _handle=None):
+        L = lib()
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(L.tqc_costmodel_create(int(seed), ctypes.byref(h)))
+            _handle = h
+        self.handle = _handle
+        self.num_params = L.tqc_costmodel_num_params()
+        self.num_features = L.tqc_costmodel_num_features()
+
+    @property
+    def params(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(lib().tqc_costmodel_get_params(self.handle, out.ctypes.data_as(_fp), self.num_params))
+        return out
+
+    @params.setter
+    def params(self, v):
+        a, p = _f32(v)
+        _check(lib().tqc_costmodel_set_params(self.handle, p, len(a)))
+
+    def forward(self, X, stream=None):
+        X, xp = _f32(X)
+        y = np.empty(X.shape[0], dtype=np.float32)
+        _check(lib().tqc_costmodel_forward(self.handle, xp, X.shape[0], y.ctypes.data_as(_fp),
+                                           _stream_ptr(stream)))
+        return y
+
+    def gradients(self, X, t, stream=None):
+        X, xp = _f32(X)
+        t, tp = _f32(t)
+        g = np.empty(self.num_params, dtype=np.float32)
+        _check(lib().tqc_costmodel_gradients(self.handle, xp, tp, X.shape[0], g.ctypes.data_as(_fp),
+                                             _stream_ptr(stream)))
+        return g
+
+    def train(self, feats, seconds, epochs=200, batch=256, lr=3e-3, seed=7, stream=None):
+        F, fp = _f32(feats)
+        T, tp = _f32(seconds)
+        losses = np.empty(epochs, dtype=np.float32)
+        o = TrainOptions(int(epochs), int(batch), float(lr), int(seed))
+        _check(lib().tqc_costmodel_train(self.handle, fp, tp, F.shape[0], ctypes.byref(o),
+                                         losses.ctypes.data_as(_fp), _stream_ptr(stream)))
+        return losses
+
+    def predict(self, feats, stream=None):
+        F, fp = _f32(feats)
+        out = np.empty(F.shape[0], dtype=np.float64)
+        _check(lib().tqc_costmodel_predict(self.handle, fp, F.shape[0], out.ctypes.data_as(_dp),
+                                           _stream_ptr(stream)))
+        return out
+
+    def save(self, path):
+        _check(lib().tqc_costmodel_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        _check(lib().tqc_costmodel_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.tqc_costmodel_destroy(h)
+            self.handle = None
+
+
+def step_features(plan):
+    """Raw feature rows (num_steps x 16) of a plan's contraction launches."""
+    n = plan.stats["num_steps"]
+    out = np.zeros((max(1, n), 16), dtype=np.float32)
+    _check(lib().tqc_plan_step_features(plan.handle, out.ctypes.data_as(_fp), max(1, n)))
+    return out[:n]

@@ -4,17 +4,25 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <numeric>
+#include <random>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "batch.hpp"
+#include "costmodel.hpp"
+#include "dev_ops.hpp"
 #include "kernels.hpp"
 
 namespace tqc {
@@ -171,21 +179,10 @@ static void check_device(int want) {
 }
 
 // --------------------------------------------------------------- execute
+static TransformArgs make_transform_args(const TensorIn &t, double *out);
+
 static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
-  TransformArgs a{};
-  a.raw = t.dev_raw;
-  a.out = out;
-  a.c = (int)t.cuts.size();
-  a.o = (int)t.outputs.size();
-  a.u = t.u;
-  uint64_t w = 1;
-  for (int i = a.c - 1; i >= 0; --i) {
-    a.up[i] = t.up[i];
-    a.w[i] = w;
-    w *= t.up[i] ? 3 : 4;
-  }
-  int bi = 0;
-  for (int i = 0; i < a.c; ++i) a.bbit[i] = t.up[i] ? bi++ : -1;
+  TransformArgs a = make_transform_args(t, out);
   HIP_OK(launch_transform(a, s));
 }
 
@@ -219,8 +216,8 @@ static int out_kind_for(Prec p) {
   }
 }
 
-static void pack_leaf(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
-                      uint64_t slice, hipStream_t s) {
+static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
+                               uint64_t slice) {
   Network &net = *p->net;
   const TensorIn &t = net.t[j];
   const Node &nd = p->nodes[j];
@@ -262,7 +259,31 @@ static void pack_leaf(Plan *p, int j, void *dst0, void *dst1, void *dst2, int pr
       a.inpos[i] = int(std::find(t.outputs.begin(), t.outputs.end(), q) - t.outputs.begin());
     }
   }
+  return a;
+}
+
+static void pack_leaf(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
+                      uint64_t slice, hipStream_t s) {
+  PackArgs a = make_pack_args(p, j, dst0, dst1, dst2, prec_code, slice);
   HIP_OK(launch_pack(a, s));
+}
+
+static TransformArgs make_transform_args(const TensorIn &t, double *out) {
+  TransformArgs a{};
+  a.raw = t.dev_raw;
+  a.out = out;
+  a.c = (int)t.cuts.size();
+  a.o = (int)t.outputs.size();
+  a.u = t.u;
+  uint64_t w = 1;
+  for (int i = a.c - 1; i >= 0; --i) {
+    a.up[i] = t.up[i];
+    a.w[i] = w;
+    w *= t.up[i] ? 3 : 4;
+  }
+  int bi = 0;
+  for (int i = 0; i < a.c; ++i) a.bbit[i] = t.up[i] ? bi++ : -1;
+  return a;
 }
 
 static int pick_tile(const Plan *p, const Step &st) {
@@ -271,6 +292,39 @@ static int pick_tile(const Plan *p, const Step &st) {
   if (lmn >= 7) return 0;
   if (lmn >= 6) return 1;
   return 2;
+}
+
+static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root_kind) {
+  const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
+  const Node &on = p->nodes[st.out];
+  GemmArgs g{};
+  char *pa = (char *)p->ws + na.offset, *pb = (char *)p->ws + nb.offset;
+  g.a0 = pa;
+  g.a1 = na.planes > 1 ? pa + na.plane_bytes : nullptr;
+  g.a2 = na.planes > 2 ? pa + 2 * na.plane_bytes : nullptr;
+  g.b0 = pb;
+  g.b1 = nb.planes > 1 ? pb + nb.plane_bytes : nullptr;
+  g.b2 = nb.planes > 2 ? pb + 2 * nb.plane_bytes : nullptr;
+  g.lm = st.lm;
+  g.ln = st.ln;
+  g.lk = st.lk;
+  g.kpad = st.kpad_log2;
+  if (st.lm > kMaxBits || st.ln > kMaxBits) fail(TQC_ERR_UNSUPPORTED, "step too large");
+  for (int i = 0; i < st.lm; ++i) g.posM[i] = (uint8_t)st.posM[i];
+  for (int i = 0; i < st.ln; ++i) g.posN[i] = (uint8_t)st.posN[i];
+  if (st.root) {
+    g.c0 = root_out;
+    g.scale = std::ldexp(1.0, -p->net->K);
+    g.out_kind = root_kind;
+  } else {
+    char *po = (char *)p->ws + on.offset;
+    g.c0 = po;
+    g.c1 = on.planes > 1 ? po + on.plane_bytes : nullptr;
+    g.c2 = on.planes > 2 ? po + 2 * on.plane_bytes : nullptr;
+    g.scale = 1.0;
+    g.out_kind = out_kind_for(p->prec);
+  }
+  return g;
 }
 
 // Per-phase timing with HIP events on the execution stream: phase 0 is the
@@ -319,7 +373,6 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
   Network &net = *p->net;
   const int m = net.m;
   const int pc = int(p->prec);
-  const double scale = std::ldexp(1.0, -net.K);
   if (tm) tm->begin(0);
   for (auto &t : net.t)
     if (t.basis == TQC_BASIS_RAW) transform_tensor(t, t.dev_pauli, s);
@@ -347,35 +400,8 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
       const Step &st = p->steps[si];
       Node &on = p->nodes[st.out];
       if (!first && !on.slice_dep) continue;
-      const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
-      GemmArgs g{};
-      char *pa = (char *)p->ws + na.offset, *pb = (char *)p->ws + nb.offset;
-      g.a0 = pa;
-      g.a1 = na.planes > 1 ? pa + na.plane_bytes : nullptr;
-      g.a2 = na.planes > 2 ? pa + 2 * na.plane_bytes : nullptr;
-      g.b0 = pb;
-      g.b1 = nb.planes > 1 ? pb + nb.plane_bytes : nullptr;
-      g.b2 = nb.planes > 2 ? pb + 2 * nb.plane_bytes : nullptr;
-      g.lm = st.lm;
-      g.ln = st.ln;
-      g.lk = st.lk;
-      g.kpad = st.kpad_log2;
-      if (st.lm > kMaxBits || st.ln > kMaxBits) fail(TQC_ERR_UNSUPPORTED, "step too large");
-      for (int i = 0; i < st.lm; ++i) g.posM[i] = (uint8_t)st.posM[i];
-      for (int i = 0; i < st.ln; ++i) g.posN[i] = (uint8_t)st.posN[i];
-      if (st.root) {
-        g.c0 = root_out;
-        g.scale = scale;
-        g.out_kind = root_kind;
-        if (root_kind == OUT_F64_ACC && !accumulate_first && !first_done) g.out_kind = OUT_F64;
-      } else {
-        char *po = (char *)p->ws + on.offset;
-        g.c0 = po;
-        g.c1 = on.planes > 1 ? po + on.plane_bytes : nullptr;
-        g.c2 = on.planes > 2 ? po + 2 * on.plane_bytes : nullptr;
-        g.scale = 1.0;
-        g.out_kind = out_kind_for(p->prec);
-      }
+      GemmArgs g = make_gemm_args(p, st, root_out, root_kind);
+      if (st.root && root_kind == OUT_F64_ACC && !accumulate_first && !first_done) g.out_kind = OUT_F64;
       if (tm) tm->begin(2 + (int)si);
       HIP_OK(launch_gemm(pc, g, st.tile, s));
       if (tm) tm->end();
@@ -431,6 +457,507 @@ static void *get_scratch(uint64_t bytes, hipStream_t s) {
   return g_scratch.ptr;
 }
 
+
+// ------------------------------------------------------------------ batch
+struct Batch {
+  std::vector<Plan *> plans;
+  std::vector<void *> outs;
+  int prec = 1;
+  int njobs = 0;
+  int nunits = 0;
+  int grid = 0;
+  uint64_t total = 0;
+  void *dmem = nullptr;  // one allocation for all tables and counters
+  BatchDesc desc{};
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last_stream = nullptr;
+  double tick_khz = 100000.0;
+  int device = -1;
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
+                           const tqc_batch_options &opt, hipStream_t s) {
+  if (njobs < 1) fail(TQC_ERR_INVALID_ARG, "no jobs");
+  std::unique_ptr<Batch> b(new Batch());
+  b->njobs = njobs;
+  b->use_graph = opt.use_graph != 0;
+  b->prec = int(plans[0]->prec);
+  struct TmpUnit {
+    BatchUnit u;
+    int level;
+    double cost;
+  };
+  std::vector<TmpUnit> units;
+  std::vector<TransformArgs> targs;
+  std::vector<PackArgs> pargs;
+  std::vector<GemmArgs> gargs;
+  for (int j = 0; j < njobs; ++j) {
+    Plan *p = plans[j];
+    if (!p || !outs || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
+    if (int(p->prec) != b->prec) fail(TQC_ERR_INVALID_ARG, "job %d: all jobs need one precision", j);
+    if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not batched", j);
+    const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
+    if (out_bytes && out_bytes[j] < need) fail(TQC_ERR_SHAPE, "job %d: output too small", j);
+    ensure_workspace(p, s);
+    b->plans.push_back(p);
+    b->outs.push_back(outs[j]);
+    Network &net = *p->net;
+    const int m = net.m;
+    const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+    const double job_cost = p->stats.predicted_seconds;
+    std::vector<int> tunit(m, -1), node_unit(p->nodes.size(), -1), depth(p->nodes.size(), 0);
+    for (int t = 0; t < m; ++t) {
+      const TensorIn &ti = net.t[t];
+      if (ti.basis != TQC_BASIS_RAW) continue;
+      TmpUnit u{};
+      u.u.kind = UNIT_TRANSFORM;
+      u.u.job = j;
+      u.u.dep0 = u.u.dep1 = -1;
+      u.u.arg = (int)targs.size();
+      targs.push_back(make_transform_args(ti, ti.dev_pauli));
+      u.u.ntiles = (ti.pauli_entries() + 4095) / 4096;
+      u.level = 0;
+      u.cost = job_cost;
+      tunit[t] = (int)units.size();
+      units.push_back(u);
+    }
+    for (int t = 0; t < m; ++t) {
+      const Node &nd = p->nodes[t];
+      TmpUnit u{};
+      u.u.kind = UNIT_PACK;
+      u.u.job = j;
+      u.u.dep0 = tunit[t];
+      u.u.dep1 = -1;
+      u.u.arg = (int)pargs.size();
+      if (m == 1) {
+        pargs.push_back(make_pack_args(p, t, outs[j], nullptr, nullptr,
+                                       p->out_dtype == TQC_F64 ? 0 : 1, 0));
+        u.u.is_root = 1;
+      } else {
+        char *bp = (char *)p->ws + nd.offset;
+        pargs.push_back(make_pack_args(p, t, bp, nd.planes > 1 ? bp + nd.plane_bytes : nullptr,
+                                       nd.planes > 2 ? bp + 2 * nd.plane_bytes : nullptr,
+                                       int(p->prec), 0));
+      }
+      u.u.ntiles = ((1ull << nd.labels.size()) + 4095) / 4096;
+      u.level = 1;
+      u.cost = job_cost;
+      node_unit[t] = (int)units.size();
+      units.push_back(u);
+    }
+    for (const Step &st : p->steps) {
+      TmpUnit u{};
+      u.u.kind = UNIT_GEMM;
+      u.u.job = j;
+      u.u.dep0 = node_unit[st.a];
+      u.u.dep1 = node_unit[st.b];
+      u.u.arg = (int)gargs.size();
+      u.u.tile = st.tile;
+      u.u.is_root = st.root ? 1 : 0;
+      GemmArgs g = make_gemm_args(p, st, outs[j], root_kind);
+      const int bm = tile_bm(st.tile);
+      prepare_gemm_args(g, b->prec, bm, bm);
+      g.swz = 0;  // the work queue decides placement
+      gargs.push_back(g);
+      const uint64_t tm = ((1ull << st.lm) + bm - 1) / bm, tn = ((1ull << st.ln) + bm - 1) / bm;
+      u.u.ntiles = tm * tn;
+      depth[st.out] = 1 + std::max(depth[st.a], depth[st.b]);
+      u.level = 1 + depth[st.out];
+      u.cost = job_cost;
+      node_unit[st.out] = (int)units.size();
+      units.push_back(u);
+    }
+  }
+  // level order; inside a level, the most expensive jobs first
+  std::vector<int> order(units.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (units[x].level != units[y].level) return units[x].level < units[y].level;
+    return units[x].cost > units[y].cost;
+  });
+  std::vector<int> newid(units.size());
+  for (size_t i = 0; i < order.size(); ++i) newid[order[i]] = (int)i;
+  std::vector<BatchUnit> fin(units.size());
+  uint64_t first = 0;
+  for (size_t i = 0; i < order.size(); ++i) {
+    BatchUnit u = units[order[i]].u;
+    if (u.dep0 >= 0) u.dep0 = newid[u.dep0];
+    if (u.dep1 >= 0) u.dep1 = newid[u.dep1];
+    u.first = first;
+    first += u.ntiles;
+    fin[i] = u;
+  }
+  b->nunits = (int)fin.size();
+  b->total = first;
+  // one device allocation: units, args, counters, job clocks, flags
+  auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  uint64_t off = 0;
+  const uint64_t o_units = off; off = al(off + fin.size() * sizeof(BatchUnit));
+  const uint64_t o_t = off; off = al(off + std::max<size_t>(1, targs.size()) * sizeof(TransformArgs));
+  const uint64_t o_p = off; off = al(off + pargs.size() * sizeof(PackArgs));
+  const uint64_t o_g = off; off = al(off + std::max<size_t>(1, gargs.size()) * sizeof(GemmArgs));
+  const uint64_t o_c = off; off = al(off + fin.size() * 4);
+  const uint64_t o_n = off; off = al(off + 8);
+  const uint64_t o_s = off; off = al(off + njobs * 8);
+  const uint64_t o_e = off; off = al(off + njobs * 8);
+  const uint64_t o_err = off; off = al(off + 4);
+  HIP_OK(hipMalloc(&b->dmem, off));
+  char *dm = (char *)b->dmem;
+  HIP_OK(hipMemcpy(dm + o_units, fin.data(), fin.size() * sizeof(BatchUnit), hipMemcpyHostToDevice));
+  if (!targs.empty())
+    HIP_OK(hipMemcpy(dm + o_t, targs.data(), targs.size() * sizeof(TransformArgs), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(dm + o_p, pargs.data(), pargs.size() * sizeof(PackArgs), hipMemcpyHostToDevice));
+  if (!gargs.empty())
+    HIP_OK(hipMemcpy(dm + o_g, gargs.data(), gargs.size() * sizeof(GemmArgs), hipMemcpyHostToDevice));
+  BatchDesc &d = b->desc;
+  d.units = (const BatchUnit *)(dm + o_units);
+  d.nunits = b->nunits;
+  d.targs = (const TransformArgs *)(dm + o_t);
+  d.pargs = (const PackArgs *)(dm + o_p);
+  d.gargs = (const GemmArgs *)(dm + o_g);
+  d.counters = (unsigned int *)(dm + o_c);
+  d.next = (unsigned long long *)(dm + o_n);
+  d.total = b->total;
+  d.job_start = (unsigned long long *)(dm + o_s);
+  d.job_end = (unsigned long long *)(dm + o_e);
+  d.error = (unsigned int *)(dm + o_err);
+  d.spin_limit = opt.spin_limit ? opt.spin_limit : (1ull << 30);
+  int dev = 0, cus = 0, khz = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  b->device = dev;
+  b->tick_khz = khz > 0 ? double(khz) : 100000.0;
+  const int per_cu = batch_blocks_per_cu(b->prec);
+  b->grid = opt.grid > 0 ? opt.grid : per_cu * cus;
+  return b.release();
+}
+
+static void batch_execute(Batch *b, hipStream_t s) {
+  check_device(b->device);
+  b->last_stream = s;
+  if (!b->use_graph) {
+    HIP_OK(launch_batch(b->prec, b->desc, b->njobs, b->grid, s));
+    return;
+  }
+  if (!b->exec) {
+    // capture reset + persistent launch once on a private stream
+    HIP_OK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(b->prec, b->desc, b->njobs, b->grid, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+    HIP_OK(le);
+    HIP_OK(ce);
+    b->graph = g;
+    HIP_OK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_OK(hipGraphLaunch(b->exec, s));
+}
+
+static void batch_sequential(Batch *b, hipStream_t s, double *job_ms) {
+  check_device(b->device);
+  std::vector<hipEvent_t> ev(2 * b->njobs);
+  for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+  for (int j = 0; j < b->njobs; ++j) {
+    Plan *p = b->plans[j];
+    HIP_OK(hipEventRecord(ev[2 * j], s));
+    execute(p, b->outs[j], ~0ull, s);
+    HIP_OK(hipEventRecord(ev[2 * j + 1], s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  for (int j = 0; j < b->njobs; ++j) {
+    float t0 = 0, t1 = 0;
+    HIP_OK(hipEventElapsedTime(&t0, ev[0], ev[2 * j]));
+    HIP_OK(hipEventElapsedTime(&t1, ev[0], ev[2 * j + 1]));
+    if (job_ms) {
+      job_ms[2 * j] = t0;
+      job_ms[2 * j + 1] = t1;
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+static void batch_times(Batch *b, double *start_ms, double *end_ms, uint32_t *error) {
+  HIP_OK(hipStreamSynchronize(b->last_stream));
+  std::vector<unsigned long long> st(b->njobs), en(b->njobs);
+  unsigned int err = 0;
+  HIP_OK(hipMemcpy(st.data(), b->desc.job_start, b->njobs * 8, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(en.data(), b->desc.job_end, b->njobs * 8, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&err, b->desc.error, 4, hipMemcpyDeviceToHost));
+  unsigned long long t0 = ~0ull;
+  for (auto x : st) t0 = std::min(t0, x);
+  for (int j = 0; j < b->njobs; ++j) {
+    if (start_ms) start_ms[j] = double(st[j] - t0) / b->tick_khz;
+    if (end_ms) end_ms[j] = en[j] >= t0 ? double(en[j] - t0) / b->tick_khz : -1.0;
+  }
+  if (error) *error = err;
+}
+
+// --------------------------------------------------------------- autotune
+// Measured tile choice per step shape (precision, log2 M, N, K); the table
+// is process-wide and can be saved to / loaded from a text file.
+struct TuneKey {
+  int prec, lm, ln, lk;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(prec, lm, ln, lk) < std::tie(o.prec, o.lm, o.ln, o.lk);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, double>> g_tune;
+
+static void apply_tuned_tiles(Plan *p) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (Step &st : p->steps) {
+    auto it = g_tune.find(TuneKey{int(p->prec), st.lm, st.ln, st.lk});
+    if (it != g_tune.end()) st.tile = it->second.first;
+  }
+}
+
+static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipStream_t s) {
+  if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "autotuning needs an unsliced plan");
+  execute(p, out, out_bytes, s);  // valid operands for every step
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+  for (Step &st : p->steps) {
+    GemmArgs g = make_gemm_args(p, st, out, root_kind);
+    int best = st.tile;
+    double best_ms = 1e30;
+    for (int tile = 0; tile < 3; ++tile) {
+      const int bm = tile_bm(tile);
+      if (tile != 2 && (st.lm < 5 || st.ln < 5) && bm > 32) continue;
+      HIP_OK(launch_gemm(int(p->prec), g, tile, s));  // warm
+      HIP_OK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) HIP_OK(launch_gemm(int(p->prec), g, tile, s));
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / reps;
+      if (per < best_ms) {
+        best_ms = per;
+        best = tile;
+      }
+    }
+    st.tile = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{int(p->prec), st.lm, st.ln, st.lk}] = {best, best_ms};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+
+// ------------------------------------------------------------- cost model
+struct CostModel {
+  int device = -1;
+  float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_g = nullptr, *d_partial = nullptr;
+  float fmean[kFeat], fstd[kFeat];
+  float tmean = 0.f, tstd = 1.f;
+  int adam_step = 0;
+  ~CostModel() {
+    for (float *x : {d_theta, d_m, d_v, d_g, d_partial})
+      if (x) (void)hipFree(x);
+  }
+};
+
+// Raw features of one launch of a pairwise step (log2 sizes, roofline
+// quantities, one-hot precision and tile).
+static void shape_features(const StepShape &sh, Prec prec, tqc_dtype out_dtype, uint64_t slices,
+                           float *f) {
+  const double eb = prec_bytes(prec);
+  double outb = eb;
+  if (sh.root) outb = slices > 1 ? 16.0 : (out_dtype == TQC_F64 ? 8.0 : 4.0);
+  const double bytes = eb * (std::ldexp(1.0, sh.lm) + std::ldexp(1.0, sh.ln)) * std::ldexp(1.0, sh.kpad) +
+                       outb * std::ldexp(1.0, sh.lm + sh.ln);
+  for (int i = 0; i < kFeat; ++i) f[i] = 0.f;
+  f[0] = (float)sh.lm;
+  f[1] = (float)sh.ln;
+  f[2] = (float)sh.lk;
+  f[3] = (float)sh.kpad;
+  f[4] = (float)(sh.lm + sh.ln);
+  f[5] = (float)(sh.lm + sh.ln + sh.lk);
+  f[6] = (float)std::log2(bytes);
+  f[7] = (float)sh.root;
+  f[8] = (float)std::log2(outb);
+  f[9 + int(prec)] = 1.f;
+  f[13 + std::min(2, std::max(0, sh.tile))] = 1.f;
+}
+
+static CostModel *create_costmodel(uint64_t seed) {
+  std::unique_ptr<CostModel> m(new CostModel());
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  m->device = dev;
+  for (int i = 0; i < kFeat; ++i) {
+    m->fmean[i] = 0.f;
+    m->fstd[i] = 1.f;
+  }
+  std::vector<float> th(kParams, 0.f);
+  std::mt19937_64 rng(seed ? seed : 12345);
+  std::normal_distribution<float> nd(0.f, 1.f);
+  // He initialisation of the two ReLU layers, small output layer
+  for (int i = 0; i < kFeat * kHid; ++i) th[i] = nd(rng) * std::sqrt(2.f / kFeat);
+  const int oW2 = kFeat * kHid + kHid;
+  for (int i = 0; i < kHid * kHid; ++i) th[oW2 + i] = nd(rng) * std::sqrt(2.f / kHid);
+  const int oW3 = oW2 + kHid * kHid + kHid;
+  for (int i = 0; i < kHid; ++i) th[oW3 + i] = nd(rng) * std::sqrt(1.f / kHid);
+  HIP_OK(hipMalloc((void **)&m->d_theta, kParams * 4));
+  HIP_OK(hipMalloc((void **)&m->d_m, kParams * 4));
+  HIP_OK(hipMalloc((void **)&m->d_v, kParams * 4));
+  HIP_OK(hipMalloc((void **)&m->d_g, kParams * 4));
+  HIP_OK(hipMalloc((void **)&m->d_partial, (size_t)kGradBlocks * 4 * kParams * 4));
+  HIP_OK(hipMemcpy(m->d_theta, th.data(), kParams * 4, hipMemcpyHostToDevice));
+  HIP_OK(hipMemset(m->d_m, 0, kParams * 4));
+  HIP_OK(hipMemset(m->d_v, 0, kParams * 4));
+  return m.release();
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  explicit DevBuf(size_t bytes) { HIP_OK(hipMalloc(&p, bytes ? bytes : 4)); }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+static void costmodel_forward_raw(CostModel *m, const float *X, int64_t n, float *y, hipStream_t s) {
+  check_device(m->device);
+  DevBuf dx(n * kFeat * 4), dy(n * 4);
+  HIP_OK(hipMemcpyAsync(dx.p, X, n * kFeat * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(launch_mlp_forward(m->d_theta, (const float *)dx.p, n, (float *)dy.p, s));
+  HIP_OK(hipMemcpyAsync(y, dy.p, n * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+static void costmodel_grad_raw(CostModel *m, const float *X, const float *t, int64_t n, float *g,
+                               hipStream_t s) {
+  check_device(m->device);
+  DevBuf dx(n * kFeat * 4), dt(n * 4);
+  HIP_OK(hipMemcpyAsync(dx.p, X, n * kFeat * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dt.p, t, n * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(launch_mlp_grad(m->d_theta, (const float *)dx.p, (const float *)dt.p, nullptr, n, m->d_partial,
+                         m->d_g, s));
+  HIP_OK(hipMemcpyAsync(g, m->d_g, kParams * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+static void costmodel_train(CostModel *m, const float *feats, const float *seconds, int64_t n,
+                            const tqc_train_options &o, float *loss_out, hipStream_t s) {
+  check_device(m->device);
+  if (n < 2) fail(TQC_ERR_INVALID_ARG, "need at least two samples");
+  // normalisation from the data
+  for (int f = 0; f < kFeat; ++f) {
+    double mu = 0, var = 0;
+    for (int64_t i = 0; i < n; ++i) mu += feats[i * kFeat + f];
+    mu /= n;
+    for (int64_t i = 0; i < n; ++i) var += (feats[i * kFeat + f] - mu) * (feats[i * kFeat + f] - mu);
+    var /= n;
+    m->fmean[f] = (float)mu;
+    m->fstd[f] = var > 1e-12 ? (float)std::sqrt(var) : 1.f;
+  }
+  std::vector<float> X(n * kFeat), T(n);
+  double tm = 0, tv = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(seconds[i] > 0)) fail(TQC_ERR_INVALID_ARG, "sample %lld has a non-positive time", (long long)i);
+    T[i] = (float)std::log((double)seconds[i]);
+    tm += T[i];
+  }
+  tm /= n;
+  for (int64_t i = 0; i < n; ++i) tv += (T[i] - tm) * (T[i] - tm);
+  tv /= n;
+  m->tmean = (float)tm;
+  m->tstd = tv > 1e-12 ? (float)std::sqrt(tv) : 1.f;
+  for (int64_t i = 0; i < n; ++i) {
+    T[i] = (T[i] - m->tmean) / m->tstd;
+    for (int f = 0; f < kFeat; ++f)
+      X[i * kFeat + f] = (feats[i * kFeat + f] - m->fmean[f]) / m->fstd[f];
+  }
+  DevBuf dx(n * kFeat * 4), dt(n * 4), dperm(n * 4), dy(n * 4);
+  HIP_OK(hipMemcpyAsync(dx.p, X.data(), n * kFeat * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dt.p, T.data(), n * 4, hipMemcpyHostToDevice, s));
+  const int epochs = o.epochs > 0 ? o.epochs : 200;
+  const int64_t bs = o.batch > 0 ? std::min<int64_t>(o.batch, n) : std::min<int64_t>(256, n);
+  const float lr = o.lr > 0 ? o.lr : 3e-3f;
+  std::mt19937_64 rng(o.seed ? o.seed : 7);
+  std::vector<int32_t> perm(n);
+  std::vector<float> y(n);
+  for (int ep = 0; ep < epochs; ++ep) {
+    std::iota(perm.begin(), perm.end(), 0);
+    std::shuffle(perm.begin(), perm.end(), rng);
+    HIP_OK(hipMemcpyAsync(dperm.p, perm.data(), n * 4, hipMemcpyHostToDevice, s));
+    for (int64_t b0 = 0; b0 + bs <= n; b0 += bs) {
+      HIP_OK(launch_mlp_grad(m->d_theta, (const float *)dx.p, (const float *)dt.p,
+                             (const int32_t *)dperm.p + b0, bs, m->d_partial, m->d_g, s));
+      HIP_OK(launch_adam(m->d_theta, m->d_g, m->d_m, m->d_v, lr, 0.9f, 0.999f, 1e-8f, ++m->adam_step, s));
+    }
+    if (loss_out) {
+      HIP_OK(launch_mlp_forward(m->d_theta, (const float *)dx.p, n, (float *)dy.p, s));
+      HIP_OK(hipMemcpyAsync(y.data(), dy.p, n * 4, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      double L = 0;
+      for (int64_t i = 0; i < n; ++i) L += double(y[i] - T[i]) * double(y[i] - T[i]);
+      loss_out[ep] = (float)(L / n);
+    }
+  }
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// predicted seconds of launches described by raw feature rows
+static void costmodel_predict(CostModel *m, const float *feats, int64_t n, double *sec, hipStream_t s) {
+  std::vector<float> X(n * kFeat), y(n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int f = 0; f < kFeat; ++f) X[i * kFeat + f] = (feats[i * kFeat + f] - m->fmean[f]) / m->fstd[f];
+  costmodel_forward_raw(m, X.data(), n, y.data(), s);
+  for (int64_t i = 0; i < n; ++i) sec[i] = std::exp((double)y[i] * m->tstd + m->tmean);
+}
+
+// Rank candidate orders with the model; returns the best order.
+static std::vector<int> mlp_choose_order(Network *net, Prec prec, tqc_dtype out, const std::vector<int> &sliced,
+                                         const std::vector<int> &fixed_q, CostModel *m, int count,
+                                         uint64_t seed, double *best_score, hipStream_t s) {
+  auto orders = sample_orders(net, prec, out, sliced, fixed_q, std::max(2, count), seed);
+  const uint64_t slices = 1ull << (2 * sliced.size());
+  std::vector<float> F;
+  std::vector<double> mult;
+  std::vector<size_t> row0(orders.size() + 1, 0);
+  for (size_t c = 0; c < orders.size(); ++c) {
+    auto sh = order_shapes(net, prec, sliced, fixed_q, orders[c]);
+    for (auto &x : sh) {
+      float f[kFeat];
+      shape_features(x, prec, out, slices, f);
+      F.insert(F.end(), f, f + kFeat);
+      mult.push_back(x.slice_dep ? double(slices) : 1.0);
+    }
+    row0[c + 1] = mult.size();
+  }
+  std::vector<double> sec(mult.size());
+  if (!mult.empty()) costmodel_predict(m, F.data(), (int64_t)mult.size(), sec.data(), s);
+  size_t best = 0;
+  double bs = 1e300;
+  for (size_t c = 0; c < orders.size(); ++c) {
+    double sc = 0;
+    for (size_t r = row0[c]; r < row0[c + 1]; ++r) sc += sec[r] * mult[r];
+    if (sc < bs) {
+      bs = sc;
+      best = c;
+    }
+  }
+  if (best_score) *best_score = bs;
+  return orders[best];
+}
+
 }  // namespace tqc
 
 using namespace tqc;
@@ -472,8 +999,33 @@ tqc_status tqc_plan_create(tqc_network_t net, const tqc_plan_options *opt, tqc_p
   return guarded([&] {
     if (!net || !opt || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
-    Plan *p = build_plan(reinterpret_cast<Network *>(net), *opt);
+    Plan *p = nullptr;
+    if (opt->cost_kind == TQC_COST_MLP && opt->num_order_steps <= 0) {
+      if (!opt->cost_model) fail(TQC_ERR_INVALID_ARG, "TQC_COST_MLP needs a cost model");
+      auto t0 = std::chrono::steady_clock::now();
+      // slicing from the roofline planner, order from the learned model
+      tqc_plan_options o1 = *opt;
+      o1.cost_kind = TQC_COST_FLOPBYTE;
+      std::unique_ptr<Plan> p0(build_plan(reinterpret_cast<Network *>(net), o1));
+      double score = 0;
+      std::vector<int> order = mlp_choose_order(
+          reinterpret_cast<Network *>(net), p0->prec, p0->out_dtype, p0->sliced, p0->fixed_q,
+          reinterpret_cast<CostModel *>(opt->cost_model),
+          opt->num_candidates > 0 ? opt->num_candidates : 1000, opt->seed, &score, nullptr);
+      tqc_plan_options o2 = o1;
+      o2.num_order_steps = (int32_t)order.size() / 2;
+      o2.order = order.data();
+      o2.num_sliced = (int32_t)p0->sliced.size();
+      o2.sliced_cuts = p0->sliced.data();
+      p = build_plan(reinterpret_cast<Network *>(net), o2);
+      p->stats.predicted_seconds = score;
+      p->stats.plan_seconds =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } else {
+      p = build_plan(reinterpret_cast<Network *>(net), *opt);
+    }
     for (Step &st : p->steps) st.tile = pick_tile(p, st);
+    if (opt->tile_policy == 1) apply_tuned_tiles(p);
     *out = reinterpret_cast<tqc_plan_t>(p);
   });
 }
@@ -609,6 +1161,221 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits, 
     void *sp = get_scratch(sb, (hipStream_t)stream);
     HIP_OK(launch_marginal(probs, dtype == TQC_F32 ? 1 : 0, num_qubits, num_keep, keep, out, sp, sb,
                            (hipStream_t)stream));
+  });
+}
+
+struct tqc_batch_s : Batch {};
+
+tqc_status tqc_batch_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                            const uint64_t *out_bytes, const tqc_batch_options *opt, void *stream,
+                            tqc_batch_t *out) {
+  return guarded([&] {
+    if (!plans || !outs || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    tqc_batch_options o{};
+    o.use_graph = 1;
+    if (opt) o = *opt;
+    Batch *b = create_batch(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, o,
+                            (hipStream_t)stream);
+    *out = reinterpret_cast<tqc_batch_t>(b);
+  });
+}
+
+tqc_status tqc_batch_execute(tqc_batch_t batch, void *stream) {
+  return guarded([&] {
+    if (!batch) fail(TQC_ERR_INVALID_ARG, "null batch");
+    batch_execute(reinterpret_cast<Batch *>(batch), (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_batch_execute_sequential(tqc_batch_t batch, void *stream, double *job_ms) {
+  return guarded([&] {
+    if (!batch) fail(TQC_ERR_INVALID_ARG, "null batch");
+    batch_sequential(reinterpret_cast<Batch *>(batch), (hipStream_t)stream, job_ms);
+  });
+}
+
+tqc_status tqc_batch_job_times(tqc_batch_t batch, double *start_ms, double *end_ms, uint32_t *error) {
+  return guarded([&] {
+    if (!batch) fail(TQC_ERR_INVALID_ARG, "null batch");
+    batch_times(reinterpret_cast<Batch *>(batch), start_ms, end_ms, error);
+  });
+}
+
+tqc_status tqc_batch_info(tqc_batch_t batch, uint64_t *items, int32_t *units, int32_t *grid) {
+  return guarded([&] {
+    Batch *b = reinterpret_cast<Batch *>(batch);
+    if (!b) fail(TQC_ERR_INVALID_ARG, "null batch");
+    if (items) *items = b->total;
+    if (units) *units = b->nunits;
+    if (grid) *grid = b->grid;
+  });
+}
+
+void tqc_batch_destroy(tqc_batch_t batch) { delete reinterpret_cast<Batch *>(batch); }
+
+tqc_status tqc_plan_autotune(tqc_plan_t plan, void *out, uint64_t out_bytes, int32_t reps, void *stream) {
+  return guarded([&] {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    if (reps < 1) reps = 1;
+    autotune_plan(p, out, out_bytes, reps, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_autotune_save(const char *path) {
+  return guarded([&] {
+    if (!path) fail(TQC_ERR_INVALID_ARG, "null path");
+    FILE *f = fopen(path, "w");
+    if (!f) fail(TQC_ERR_INVALID_ARG, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    fprintf(f, "# tqc autotune table: gfx950 hip-runtime %d\n# prec log2m log2n log2k tile ms\n", rt);
+    for (auto &kv : g_tune)
+      fprintf(f, "%d %d %d %d %d %.6f\n", kv.first.prec, kv.first.lm, kv.first.ln, kv.first.lk,
+              kv.second.first, kv.second.second);
+    fclose(f);
+  });
+}
+
+tqc_status tqc_autotune_load(const char *path) {
+  return guarded([&] {
+    if (!path) fail(TQC_ERR_INVALID_ARG, "null path");
+    FILE *f = fopen(path, "r");
+    if (!f) fail(TQC_ERR_INVALID_ARG, "cannot read %s", path);
+    char line[256];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    while (fgets(line, sizeof(line), f)) {
+      if (line[0] == '#') continue;
+      int pr, lm, ln, lk2, tile;
+      double ms;
+      if (sscanf(line, "%d %d %d %d %d %lf", &pr, &lm, &ln, &lk2, &tile, &ms) == 6 && tile >= 0 &&
+          tile <= 2)
+        g_tune[TuneKey{pr, lm, ln, lk2}] = {tile, ms};
+    }
+    fclose(f);
+  });
+}
+
+struct tqc_costmodel_s : CostModel {};
+
+tqc_status tqc_costmodel_create(uint64_t seed, tqc_costmodel_t *out) {
+  return guarded([&] {
+    if (!out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = reinterpret_cast<tqc_costmodel_t>(create_costmodel(seed));
+  });
+}
+
+void tqc_costmodel_destroy(tqc_costmodel_t m) { delete reinterpret_cast<CostModel *>(m); }
+
+int32_t tqc_costmodel_num_params(void) { return kParams; }
+int32_t tqc_costmodel_num_features(void) { return kFeat; }
+
+tqc_status tqc_costmodel_get_params(tqc_costmodel_t mp, float *out, int32_t n) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !out || n < kParams) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    HIP_OK(hipMemcpy(out, m->d_theta, kParams * 4, hipMemcpyDeviceToHost));
+  });
+}
+
+tqc_status tqc_costmodel_set_params(tqc_costmodel_t mp, const float *in, int32_t n) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !in || n < kParams) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    HIP_OK(hipMemcpy(m->d_theta, in, kParams * 4, hipMemcpyHostToDevice));
+  });
+}
+
+tqc_status tqc_costmodel_forward(tqc_costmodel_t mp, const float *x, int64_t n, float *y, void *stream) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !x || !y || n < 1) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    costmodel_forward_raw(m, x, n, y, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_costmodel_gradients(tqc_costmodel_t mp, const float *x, const float *t, int64_t n,
+                                   float *grad, void *stream) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !x || !t || !grad || n < 1) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    costmodel_grad_raw(m, x, t, n, grad, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_costmodel_train(tqc_costmodel_t mp, const float *feats, const float *seconds, int64_t n,
+                               const tqc_train_options *opt, float *loss_per_epoch, void *stream) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !feats || !seconds) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    tqc_train_options o{};
+    if (opt) o = *opt;
+    costmodel_train(m, feats, seconds, n, o, loss_per_epoch, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_costmodel_predict(tqc_costmodel_t mp, const float *feats, int64_t n, double *seconds,
+                                 void *stream) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !feats || !seconds || n < 1) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    costmodel_predict(m, feats, n, seconds, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_costmodel_save(tqc_costmodel_t mp, const char *path) {
+  return guarded([&] {
+    CostModel *m = reinterpret_cast<CostModel *>(mp);
+    if (!m || !path) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    std::vector<float> th(kParams);
+    HIP_OK(hipMemcpy(th.data(), m->d_theta, kParams * 4, hipMemcpyDeviceToHost));
+    FILE *f = fopen(path, "w");
+    if (!f) fail(TQC_ERR_INVALID_ARG, "cannot write %s", path);
+    fprintf(f, "tqc-costmodel %d %d %d\n", kFeat, kHid, kParams);
+    for (int i = 0; i < kFeat; ++i) fprintf(f, "%.9g %.9g\n", m->fmean[i], m->fstd[i]);
+    fprintf(f, "%.9g %.9g\n", m->tmean, m->tstd);
+    for (int i = 0; i < kParams; ++i) fprintf(f, "%.9g\n", th[i]);
+    fclose(f);
+  });
+}
+
+tqc_status tqc_costmodel_load(const char *path, tqc_costmodel_t *out) {
+  return guarded([&] {
+    if (!path || !out) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    FILE *f = fopen(path, "r");
+    if (!f) fail(TQC_ERR_INVALID_ARG, "cannot read %s", path);
+    int nf = 0, nh = 0, np = 0;
+    if (fscanf(f, "tqc-costmodel %d %d %d", &nf, &nh, &np) != 3 || nf != kFeat || nh != kHid ||
+        np != kParams) {
+      fclose(f);
+      fail(TQC_ERR_INVALID_ARG, "%s is not a cost model of this build", path);
+    }
+    std::unique_ptr<CostModel> m(create_costmodel(1));
+    bool ok = true;
+    for (int i = 0; i < kFeat; ++i) ok &= fscanf(f, "%f %f", &m->fmean[i], &m->fstd[i]) == 2;
+    ok &= fscanf(f, "%f %f", &m->tmean, &m->tstd) == 2;
+    std::vector<float> th(kParams);
+    for (int i = 0; i < kParams; ++i) ok &= fscanf(f, "%f", &th[i]) == 1;
+    fclose(f);
+    if (!ok) fail(TQC_ERR_INVALID_ARG, "%s is truncated", path);
+    HIP_OK(hipMemcpy(m->d_theta, th.data(), kParams * 4, hipMemcpyHostToDevice));
+    *out = reinterpret_cast<tqc_costmodel_t>(m.release());
+  });
+}
+
+tqc_status tqc_plan_step_features(tqc_plan_t plan, float *out, int32_t max_steps) {
+  return guarded([&] {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || !out) fail(TQC_ERR_INVALID_ARG, "bad argument");
+    if (max_steps < (int)p->steps.size()) fail(TQC_ERR_SHAPE, "need %zu rows", p->steps.size());
+    for (size_t i = 0; i < p->steps.size(); ++i) {
+      const Step &st = p->steps[i];
+      StepShape sh{st.lm, st.ln, st.lk, st.kpad_log2, st.root ? 1 : 0,
+                   p->nodes[st.out].slice_dep ? 1 : 0, st.tile};
+      shape_features(sh, p->prec, p->out_dtype, p->num_slices, out + i * kFeat);
+    }
   });
 }
 

@@ -1,0 +1,516 @@
+// Device-side building blocks shared by the per-step kernels and the
+// persistent batch kernel: float64 Pauli-basis transform, operand packing
+// and one GEMM tile of a pairwise contraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "device.hpp"
+
+namespace tqc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double double2v __attribute__((ext_vector_type(2)));
+
+// ======================================================= Pauli transform
+// Sec. II-A: the Pauli basis of a cut is a linear combination of the
+// measured / prepared variants.  Upstream end, Pauli s: the Z-basis run for
+// I and Z, the X- and Y-basis runs for X and Y, summed over the measured cut
+// bit with weight 1 (I) or (-1)^bit.  Downstream end: I = r0 + r1,
+// Z = r0 - r1, X = 2 r+ - r0 - r1, Y = 2 ri - r0 - r1 over the preparations
+// |0>, |1>, |+>, |i>.
+__device__ inline int down_opts(int s) { return (s == 1 || s == 2) ? 3 : 2; }
+// preparation used by option o of Pauli s: I {0,1}, X {+,0,1}, Y {i,0,1}, Z {0,1}
+__device__ inline int down_prep(int s, int o) {
+  if (s == 1 || s == 2) return o == 0 ? s + 1 : o - 1;
+  return o;
+}
+__device__ inline double down_coef(int s, int o) {
+  if (s == 0) return 1.0;
+  if (s == 3) return o == 0 ? 1.0 : -1.0;
+  return o == 0 ? 2.0 : -1.0;
+}
+
+__device__ inline void transform_elem(const TransformArgs &a, uint64_t e) {
+  const uint64_t cols = 1ull << (a.o + a.u);
+  const uint64_t x = e & ((1ull << a.o) - 1);
+  const uint64_t row = e >> a.o;
+  int sig[kMaxCutsT], nopt[kMaxCutsT], opt[kMaxCutsT];
+  for (int t = 0; t < a.c; ++t) {
+    sig[t] = (int)((row >> (2 * (a.c - 1 - t))) & 3);
+    nopt[t] = a.up[t] ? 2 : down_opts(sig[t]);
+    opt[t] = 0;
+  }
+  double sum = 0.0;
+  while (true) {
+    double coef = 1.0;
+    uint64_t rin = 0, b = 0;
+    for (int t = 0; t < a.c; ++t) {
+      const int s = sig[t];
+      if (a.up[t]) {
+        const int meas = (s == 3) ? 0 : s;  // I and Z share the Z-basis run
+        const int bit = opt[t];
+        if (s != 0 && bit) coef = -coef;
+        rin += (uint64_t)meas * a.w[t];
+        b |= (uint64_t)bit << a.bbit[t];
+      } else {
+        coef *= down_coef(s, opt[t]);
+        rin += (uint64_t)down_prep(s, opt[t]) * a.w[t];
+      }
+    }
+    sum += coef * a.raw[rin * cols + ((x << a.u) | b)];
+    int t = a.c - 1;
+    while (t >= 0 && ++opt[t] == nopt[t]) {
+      opt[t] = 0;
+      --t;
+    }
+    if (t < 0) break;
+  }
+  a.out[e] = sum;
+}
+
+// ================================================================= pack
+__device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
+  const uint64_t kmask = (1ull << a.lk) - 1;
+  uint64_t src = a.base;
+  for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
+  const double v = a.src[src] * a.scale;
+  const uint64_t d = ((e >> a.lk) << a.kpad) | (e & kmask);
+  switch (a.prec) {
+    case 0:
+      ((double *)a.dst0)[d] = v;
+      break;
+    case 1:
+      ((float *)a.dst0)[d] = (float)v;
+      break;
+    case 2: {
+      const uint16_t hi = f32_to_bf16_rne((float)v);
+      const double r = v - (double)bf16_to_f32(hi);
+      ((uint16_t *)a.dst0)[d] = hi;
+      ((uint16_t *)a.dst1)[d] = f32_to_bf16_rne((float)r);
+      break;
+    }
+    default: {
+      const uint16_t hi = f32_to_bf16_rne((float)v);
+      const double r1 = v - (double)bf16_to_f32(hi);
+      const uint16_t mid = f32_to_bf16_rne((float)r1);
+      const double r2 = r1 - (double)bf16_to_f32(mid);
+      ((uint16_t *)a.dst0)[d] = hi;
+      ((uint16_t *)a.dst1)[d] = mid;
+      ((uint16_t *)a.dst2)[d] = f32_to_bf16_rne((float)r2);
+      break;
+    }
+  }
+}
+
+// ================================================================= GEMM
+// One pairwise contraction C[m][n] = sum_k A[m][k] B[n][k] (Sec. III-B): the
+// shared cut digits are k, each operand's other index bits are m or n, and
+// both operands are stored as row-major [rows][2^kpad] with k contiguous.
+// The result is scattered to its consumer's layout: bit i of m lands on
+// output bit posM[i] (likewise for n), so the final step writes the
+// probability vector in qubit order and earlier steps write the next
+// step's operand directly.
+//
+// Block: 256 threads = 4 waves in a 2x2 arrangement; each wave owns a
+// (BM/2) x (BN/2) sub-tile built from 16x16 MFMA blocks.  The k index inside
+// an MFMA group is remapped so that every lane fetches one contiguous
+// 16-byte run of its row from LDS: lane group g (= lane / 16) at step t
+// holds logical k = 4g + t (fp32/fp64, 16 k per group) or k = 8g + e
+// (bfloat16, 32 k per group).
+template <int P>
+struct PrecTraits;
+template <>
+struct PrecTraits<0> {  // float64
+  using E = double;
+  static constexpr int planes = 1, kgroup = 16;
+  using Acc = doublex4;
+};
+template <>
+struct PrecTraits<1> {  // float32
+  using E = float;
+  static constexpr int planes = 1, kgroup = 16;
+  using Acc = floatx4;
+};
+template <>
+struct PrecTraits<2> {  // bf16x3
+  using E = uint16_t;
+  static constexpr int planes = 2, kgroup = 32;
+  using Acc = floatx4;
+};
+template <>
+struct PrecTraits<3> {  // bf16x6
+  using E = uint16_t;
+  static constexpr int planes = 3, kgroup = 32;
+  using Acc = floatx4;
+};
+
+__device__ inline uint64_t scatter_bits(uint64_t v, const uint8_t *pos, int nbits) {
+  uint64_t r = 0;
+  for (int i = 0; i < nbits; ++i) r |= ((v >> i) & 1ull) << pos[i];
+  return r;
+}
+
+template <typename AccT>
+__device__ inline void store_out(const GemmArgs &g, uint64_t addr, AccT v) {
+  switch (g.out_kind) {
+    case OUT_F32:
+      ((float *)g.c0)[addr] = (float)((double)v * g.scale);
+      break;
+    case OUT_F64:
+      ((double *)g.c0)[addr] = (double)v * g.scale;
+      break;
+    case OUT_F64_ACC:
+      ((double *)g.c0)[addr] += (double)v * g.scale;
+      break;
+    case OUT_SPLIT2: {
+      const float f = (float)((double)v * g.scale);
+      const uint16_t hi = f32_to_bf16_rne(f);
+      ((uint16_t *)g.c0)[addr] = hi;
+      ((uint16_t *)g.c1)[addr] = f32_to_bf16_rne(f - bf16_to_f32(hi));
+      break;
+    }
+    default: {
+      const float f = (float)((double)v * g.scale);
+      const uint16_t hi = f32_to_bf16_rne(f);
+      const float r1 = f - bf16_to_f32(hi);
+      const uint16_t mid = f32_to_bf16_rne(r1);
+      ((uint16_t *)g.c0)[addr] = hi;
+      ((uint16_t *)g.c1)[addr] = mid;
+      ((uint16_t *)g.c2)[addr] = f32_to_bf16_rne(r1 - bf16_to_f32(mid));
+      break;
+    }
+  }
+}
+
+// Tile order: with 8 XCDs, consecutive workgroup ids go round-robin to the
+// XCDs.  Remap so that each XCD owns a contiguous eighth of the tile space and
+// walks it in groups of 8 tile rows (A row-blocks) by increasing column:
+// the tiles resident on one XCD at a time share A and B blocks in its L2.
+__device__ inline void tile_of(uint64_t bid, uint64_t tilesM, uint64_t tilesN, int swz,
+                               uint64_t &tm, uint64_t &tn) {
+  const uint64_t T = tilesM * tilesN;
+  uint64_t t = bid;
+  if (swz) {
+    const uint64_t per = T >> 3;
+    t = (bid & 7) * per + (bid >> 3);
+    const uint64_t G = 8;
+    const uint64_t grp = t / (G * tilesN);
+    const uint64_t r = t % (G * tilesN);
+    tm = grp * G + (r % G);
+    tn = r / G;
+    return;
+  }
+  tm = t / tilesN;
+  tn = t % tilesN;
+}
+
+__device__ inline uint32_t deposit(uint32_t v, const uint8_t *pos, int nbits) {
+  uint32_t r = 0;
+  for (int i = 0; i < nbits; ++i) r |= ((v >> i) & 1u) << pos[i];
+  return r;
+}
+
+template <int P, int BM, int BN, int BK>
+struct GemmShape {
+  using T = PrecTraits<P>;
+  using E = typename T::E;
+  static constexpr int NP = T::planes;
+  static constexpr int ES = sizeof(E);
+  static constexpr int VE = 16 / ES;
+  static constexpr int LDR = BK + VE;
+  static constexpr int OPER_BYTES = NP * (BM + BN) * LDR * ES;
+  static constexpr int CT_BYTES = (P == 0) ? 0 : BM * BN * 4;  // staged float tile
+  static constexpr int MAIN_BYTES = OPER_BYTES > CT_BYTES ? OPER_BYTES : CT_BYTES;
+  static constexpr int LDS_BYTES = MAIN_BYTES;
+};
+
+template <int P, int BM, int BN, int BK>
+__device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
+  using T = PrecTraits<P>;
+  using E = typename T::E;
+  using Acc = typename T::Acc;
+  using S = GemmShape<P, BM, BN, BK>;
+  constexpr int NP = T::planes;
+  constexpr int VE = S::VE;
+  constexpr int LDR = S::LDR;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int VPR = BK / VE;      // vectors per row per plane
+  constexpr int AV = BM * VPR, BV = BN * VPR;
+  constexpr int AIT = (AV + 255) / 256, BIT = (BV + 255) / 256;
+  static_assert(BK % T::kgroup == 0, "BK must hold whole MFMA groups");
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+
+  E *As = (E *)smem;
+  E *Bs = As + NP * BM * LDR;
+
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  const uint64_t KP = 1ull << g.kpad;
+  const uint64_t tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  uint64_t tm, tn;
+  tile_of(bid, tilesM, tilesN, g.swz, tm, tn);
+  const uint64_t m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  const E *Ap[3] = {(const E *)g.a0, (const E *)g.a1, (const E *)g.a2};
+  const E *Bp[3] = {(const E *)g.b0, (const E *)g.b1, (const E *)g.b2};
+
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+  uint4 ra[NP][AIT], rb[NP][BIT];
+  auto load_global = [&](uint64_t k0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int v = tid + it * 256;
+        uint4 val = {0, 0, 0, 0};
+        if (v < AV) {
+          const int r = v / VPR, cv = v % VPR;
+          const uint64_t row = m0 + r;
+          if (row < M) val = *(const uint4 *)(Ap[p] + row * KP + k0 + cv * VE);
+        }
+        ra[p][it] = val;
+      }
+#pragma unroll
+      for (int it = 0; it < BIT; ++it) {
+        const int v = tid + it * 256;
+        uint4 val = {0, 0, 0, 0};
+        if (v < BV) {
+          const int r = v / VPR, cv = v % VPR;
+          const uint64_t row = n0 + r;
+          if (row < N) val = *(const uint4 *)(Bp[p] + row * KP + k0 + cv * VE);
+        }
+        rb[p][it] = val;
+      }
+    }
+  };
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int v = tid + it * 256;
+        if (v < AV) {
+          const int r = v / VPR, cv = v % VPR;
+          *(uint4 *)(As + (p * BM + r) * LDR + cv * VE) = ra[p][it];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < BIT; ++it) {
+        const int v = tid + it * 256;
+        if (v < BV) {
+          const int r = v / VPR, cv = v % VPR;
+          *(uint4 *)(Bs + (p * BN + r) * LDR + cv * VE) = rb[p][it];
+        }
+      }
+    }
+  };
+
+  const bool staged = (P != 0) && g.staged;
+
+  load_global(0);
+  for (uint64_t k0 = 0; k0 < KP; k0 += BK) {
+    __syncthreads();
+    store_lds();
+    __syncthreads();
+    if (k0 + BK < KP) load_global(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += T::kgroup) {
+      if constexpr (P == 0 || P == 1) {
+        using V4 = typename std::conditional<P == 0, doublex4, floatx4>::type;
+        V4 af[FM], bfr[FN];
+        // rows are 16-byte aligned in LDS: read 16-byte pieces
+        auto rd = [](const E *ptr) -> V4 {
+          if constexpr (P == 0) {
+            const double2v lo = *(const double2v *)ptr;
+            const double2v hi = *(const double2v *)(ptr + 2);
+            return V4{lo[0], lo[1], hi[0], hi[1]};
+          } else {
+            return *(const V4 *)ptr;
+          }
+        };
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[i] = rd(As + (wm * WM + i * 16 + lr) * LDR + kk + 4 * lg);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bfr[j] = rd(Bs + (wn * WN + j * 16 + lr) * LDR + kk + 4 * lg);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+              if constexpr (P == 0)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][t], bfr[j][t], acc[i][j], 0, 0, 0);
+              else
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][t], bfr[j][t], acc[i][j], 0, 0, 0);
+            }
+      } else {
+        bf16x8 af[NP][FM], bfr[NP][FN];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+            af[p][i] = *(const bf16x8 *)(As + (p * BM + wm * WM + i * 16 + lr) * LDR + kk + 8 * lg);
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            bfr[p][j] = *(const bf16x8 *)(Bs + (p * BN + wn * WN + j * 16 + lr) * LDR + kk + 8 * lg);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            // small terms first, then the leading product
+            if constexpr (P == 3) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], acc[i][j], 0, 0, 0);
+            }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+  // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
+  // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
+  // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
+  if (staged) {
+    // 1) accumulators -> LDS at their compact (output-order) tile index
+    float *ct = (float *)smem;
+    __syncthreads();  // operand tiles no longer needed
+    uint32_t tcol[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) tcol[j] = deposit(wn * WN + j * 16 + lr, g.rankN, g.ncompact);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t trow = deposit(wm * WM + i * 16 + 4 * lg + r, g.rankM, g.ncompact);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)acc[i][j][r];
+      }
+    __syncthreads();
+    // 2) stream the tile out in output order: compact index x maps to the
+    //    output offset sum_b bit_b(x) << lpos[b]; the bits below the stride
+    //    of the loop are fixed per thread
+    const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
+    constexpr int TT = BM * BN;
+    const float sc = (float)g.scale;
+    if (g.vec4) {
+      constexpr int LB = 10;  // log2(256 threads * 4)
+      const uint64_t lo = scatter_bits((uint64_t)tid * 4, g.lpos, LB);
+      for (int it = 0; it * 1024 < TT; ++it) {
+        const int x = it * 1024 + tid * 4;
+        const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
+        const floatx4 v = *(const floatx4 *)(ct + x);
+        switch (g.out_kind) {
+          case OUT_F32:
+            *(floatx4 *)((float *)g.c0 + addr) = v * sc;
+            break;
+          case OUT_F64_ACC: {
+            double *o = (double *)g.c0 + addr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] += (double)v[e] * g.scale;
+            break;
+          }
+          case OUT_F64: {
+            double *o = (double *)g.c0 + addr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * g.scale;
+            break;
+          }
+          default: {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) store_out(g, addr + e, v[e]);
+            break;
+          }
+        }
+      }
+    } else {
+      constexpr int LB = 8;  // log2(256 threads)
+      const uint64_t lo = scatter_bits((uint64_t)tid, g.lpos, LB);
+      for (int it = 0; it * 256 < TT; ++it) {
+        const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
+        store_out(g, addr, ct[it * 256 + tid]);
+      }
+    }
+    return;
+  }
+  // direct scatter (partial tiles, float64 form)
+  uint64_t offn[FN];
+  bool okn[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const uint64_t col = n0 + wn * WN + j * 16 + lr;
+    okn[j] = col < N;
+    offn[j] = okn[j] ? scatter_bits(col, g.posN, g.ln) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
+      const uint64_t row = m0 + wm * WM + i * 16 + rr;
+      if (row >= M) continue;
+      const uint64_t offm = scatter_bits(row, g.posM, g.lm);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        if (okn[j]) store_out(g, offm + offn[j], acc[i][j][r]);
+    }
+  }
+}
+
+// Tile-dependent epilogue parameters (host side): the tile's output bits in
+// increasing order define the compact index used to stage C through LDS.
+inline void prepare_gemm_args(GemmArgs &g, int prec, int BM, int BN) {
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  const uint64_t tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const uint64_t tiles = tilesM * tilesN;
+  const int P = prec;
+  const int bm = __builtin_ctz(BM), bn = __builtin_ctz(BN);
+  g.staged = 0;
+  g.vec4 = 0;
+  g.swz = (tiles >= 64 && tilesM >= 8 && (tiles % 64) == 0) ? 1 : 0;
+  if (P != 0 && g.lm >= bm && g.ln >= bn) {
+    // compact tile index: the tile's output bits in increasing order
+    int pos[32], n = 0;
+    for (int i = 0; i < bm; ++i) pos[n++] = g.posM[i];
+    for (int j = 0; j < bn; ++j) pos[n++] = g.posN[j];
+    for (int a = 1; a < n; ++a)
+      for (int b = a; b > 0 && pos[b - 1] > pos[b]; --b) {
+        const int t = pos[b];
+        pos[b] = pos[b - 1];
+        pos[b - 1] = t;
+      }
+    for (int b = 0; b < n; ++b) g.lpos[b] = (uint8_t)pos[b];
+    auto rank = [&](int p) {
+      for (int b = 0; b < n; ++b)
+        if (pos[b] == p) return b;
+      return -1;
+    };
+    for (int i = 0; i < bm; ++i) g.rankM[i] = (uint8_t)rank(g.posM[i]);
+    for (int j = 0; j < bn; ++j) g.rankN[j] = (uint8_t)rank(g.posN[j]);
+    g.ncompact = n;
+    g.vec4 = (n >= 10 && pos[0] == 0 && pos[1] == 1) ? 1 : 0;
+    g.staged = (n <= 16 && n >= 8) ? 1 : 0;
+  }
+}
+
+inline int tile_bm(int tile) { return tile == 0 ? 128 : (tile == 1 ? 64 : 32); }
+
+}  // namespace tqc

@@ -66,6 +66,13 @@ struct GemmArgs {
   double scale;
   uint8_t posM[kMaxBits];
   uint8_t posN[kMaxBits];
+  // filled by the launcher for the chosen tile (staged epilogue):
+  int staged;                // 1: full tiles, stage C through LDS
+  int vec4;                  // compact bits 0,1 are output bits 0,1
+  int ncompact;              // log2(BM) + log2(BN)
+  uint8_t rankM[16], rankN[16];  // compact bit of tile-local row / col bit i
+  uint8_t lpos[32];          // output bit of compact bit b
+  int swz;                   // XCD-aware tile order
 };
 
 }  // namespace tqc

@@ -101,6 +101,19 @@ struct Plan {
 // planner entry
 Plan *build_plan(Network *net, const tqc_plan_options &opt);
 
+// shapes of the steps a contraction order produces (no layouts)
+struct StepShape {
+  int lm, ln, lk, kpad, root, slice_dep, tile;
+};
+std::vector<StepShape> order_shapes(Network *net, Prec prec, const std::vector<int> &sliced,
+                                    const std::vector<int> &fixed_q, const std::vector<int> &order);
+// candidate orders: the DP / greedy choice, then randomised-greedy samples
+std::vector<std::vector<int>> sample_orders(Network *net, Prec prec, tqc_dtype out,
+                                            const std::vector<int> &sliced,
+                                            const std::vector<int> &fixed_q, int count, uint64_t seed);
+int default_tile(int lm, int ln);
+int kmin_log2(Prec p);
+
 // plan cost helpers shared with the MLP feature extraction
 double prec_peak_flops(Prec p);
 int prec_bytes(Prec p);

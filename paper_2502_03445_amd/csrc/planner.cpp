@@ -445,6 +445,61 @@ std::vector<int> choose_order(Network *net, Prec prec, tqc_dtype out, const std:
   return greedy_order(st, prec, out, slices, nullptr, 0.0);
 }
 
+int default_tile(int lm, int ln) {
+  const int lmn = std::min(lm, ln);
+  if (lmn >= 7) return 0;
+  if (lmn >= 6) return 1;
+  return 2;
+}
+
+int kmin_log2(Prec p) { return prec_kmin_log2(p); }
+
+std::vector<StepShape> order_shapes(Network *net, Prec prec, const std::vector<int> &sliced,
+                                    const std::vector<int> &fixed_q, const std::vector<int> &order) {
+  Structure st = make_structure(*net, sliced, fixed_q);
+  const int m = net->m;
+  std::vector<uint64_t> open(2 * m), dep(2 * m);
+  std::vector<int> q(2 * m);
+  for (int j = 0; j < m; ++j) {
+    open[j] = st.cutmask[j];
+    q[j] = st.qubits[j];
+    dep[j] = st.leaf_slice_dep[j];
+  }
+  std::vector<StepShape> res;
+  for (int s = 0; s + 1 < m; ++s) {
+    const int a = order[2 * s], b = order[2 * s + 1];
+    const uint64_t shared = open[a] & open[b];
+    StepShape sh{};
+    sh.lk = 2 * __builtin_popcountll(shared);
+    sh.lm = 2 * __builtin_popcountll(open[a] & ~shared) + q[a];
+    sh.ln = 2 * __builtin_popcountll(open[b] & ~shared) + q[b];
+    sh.kpad = std::max(sh.lk, prec_kmin_log2(prec));
+    sh.root = (s == m - 2);
+    sh.slice_dep = (dep[a] || dep[b]) ? 1 : 0;
+    sh.tile = default_tile(sh.lm, sh.ln);
+    res.push_back(sh);
+    open[m + s] = open[a] ^ open[b];
+    q[m + s] = q[a] + q[b];
+    dep[m + s] = dep[a] | dep[b];
+  }
+  return res;
+}
+
+std::vector<std::vector<int>> sample_orders(Network *net, Prec prec, tqc_dtype out,
+                                            const std::vector<int> &sliced,
+                                            const std::vector<int> &fixed_q, int count, uint64_t seed) {
+  std::vector<std::vector<int>> res;
+  if (net->m <= 1) return {std::vector<int>()};
+  Structure st = make_structure(*net, sliced, fixed_q);
+  const uint64_t slices = 1ull << (2 * sliced.size());
+  res.push_back(choose_order(net, prec, out, sliced, fixed_q));
+  res.push_back(greedy_order(st, prec, out, slices, nullptr, 0.0));
+  std::mt19937_64 rng(seed ? seed : 0x9e3779b97f4a7c15ull);
+  const double temps[4] = {0.3, 1.0, 3.0, 10.0};
+  for (int i = 2; i < count; ++i) res.push_back(greedy_order(st, prec, out, slices, &rng, temps[i % 4]));
+  return res;
+}
+
 // memory of a plan: workspace plus float64 accumulator
 static uint64_t plan_memory(Plan &p) {
   uint64_t acc = (p.num_slices > 1 && p.out_dtype == TQC_F32) ? (1ull << p.out_bits) * 8 : 0;

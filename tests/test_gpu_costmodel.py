@@ -1,0 +1,69 @@
+"""Cost-model MLP on the GPU: forward and gradients against the float64
+oracle (which is pinned by finite differences), training reduces the loss,
+and plans ranked by the trained model still reconstruct correctly."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2502_03445_amd as tqc
+from oracle import mlp as omlp
+from oracle.reconstruct import full_distribution
+from workloads import synthetic
+
+pytestmark = pytest.mark.gpu
+
+F, H = 16, 64
+
+
+def test_forward_and_gradients_match_oracle():
+    m = tqc.CostModel(seed=3)
+    theta = m.params.astype(np.float64)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((777, F)).astype(np.float32)
+    t = rng.standard_normal(777).astype(np.float32)
+    y = m.forward(X)
+    yr, _ = omlp.forward(theta, X.astype(np.float64), F, H)
+    assert np.abs(y - yr).max() <= 1e-5 * max(1.0, np.abs(yr).max())
+    g = m.gradients(X, t)
+    gr = omlp.gradients(theta, X.astype(np.float64), t.astype(np.float64), F, H)
+    assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+    # deterministic: the same call gives the same bits
+    assert np.array_equal(g, m.gradients(X, t))
+
+
+def test_training_fits_a_smooth_target():
+    rng = np.random.default_rng(8)
+    X = rng.uniform(0, 20, size=(2048, F)).astype(np.float32)
+    secs = np.exp(0.2 * X[:, 0] + 0.1 * X[:, 1] - 0.05 * X[:, 2] - 8).astype(np.float32)
+    m = tqc.CostModel(seed=1)
+    losses = m.train(X, secs, epochs=60, batch=128, lr=3e-3)
+    assert losses[-1] < 0.05 * losses[0]
+    pred = m.predict(X[:64])
+    assert np.median(np.abs(np.log(pred) - np.log(secs[:64]))) < 0.2
+
+
+def test_mlp_ranked_plan_is_correct(tmp_path):
+    spec = synthetic.random_network(5, 7, [3, 3, 2, 3, 3], seed=44)
+    net = tqc.Network.from_spec(spec)
+    base = tqc.Plan(net, precision="fp32")
+    feats, secs = [], []
+    # timings of the plain contractor on a few orders
+    for seed in range(6):
+        p = tqc.Plan(net, precision="fp32", order=None if seed == 0 else None, seed=seed)
+        _, ph = p.execute_profiled()
+        f = tqc.step_features(p)
+        for i, row in enumerate(f):
+            feats.append(row)
+            secs.append(max(ph[2 + i], 1e-4) * 1e-3)
+    m = tqc.CostModel(seed=2)
+    m.train(np.array(feats), np.array(secs), epochs=30, batch=8)
+    path = str(tmp_path / "cm.txt")
+    m.save(path)
+    m2 = tqc.CostModel.load(path)
+    assert np.array_equal(m2.params, m.params)
+    plan = tqc.Plan(net, precision="fp32", cost="mlp", cost_model=m2, num_candidates=64, seed=3)
+    got = plan.execute().double().cpu().numpy()
+    ref = full_distribution(spec)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert plan.stats["predicted_seconds"] > 0
+    assert base.stats["num_steps"] == plan.stats["num_steps"]

@@ -233,3 +233,24 @@ def test_worked_example_cost():
     assert plancost.bruteforce_cost(4, 4) == prior
     # Eq. (4): sum of step costs <= (m-1) 4^Kmax with Kmax = 3 here
     assert sum(got) <= 3 * 4 ** 3
+
+
+def test_mlp_oracle_gradients_match_finite_differences():
+    from oracle import mlp
+    F, H = 5, 7
+    rng = np.random.default_rng(11)
+    theta = rng.standard_normal(mlp.num_params(F, H)) * 0.5
+    X = rng.standard_normal((9, F))
+    t = rng.standard_normal(9)
+    g = mlp.gradients(theta, X, t, F, H)
+    eps = 1e-6
+    num = np.empty_like(theta)
+    for i in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        num[i] = (mlp.loss(tp, X, t, F, H) - mlp.loss(tm, X, t, F, H)) / (2 * eps)
+    assert np.abs(g - num).max() <= 1e-6 * max(1.0, np.abs(num).max())
+    # a planted mistake (ReLU gate dropped in the first layer) is caught
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta, F, H)
+    assert np.any(X @ W1 + b1 < 0)
