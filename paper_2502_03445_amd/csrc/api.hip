@@ -76,6 +76,7 @@ Network::~Network() {
 Plan::~Plan() {
   if (ws) (void)hipFree(ws);
   if (acc64) (void)hipFree(acc64);
+  if (scale_buf) (void)hipFree(scale_buf);
 }
 
 // ------------------------------------------------------------ network
@@ -217,7 +218,7 @@ static int out_kind_for(Prec p) {
 }
 
 static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
-                               uint64_t slice) {
+                               uint64_t slice, const int *dexp = nullptr) {
   Network &net = *p->net;
   const TensorIn &t = net.t[j];
   const Node &nd = p->nodes[j];
@@ -229,6 +230,7 @@ static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst
   a.dst2 = dst2;
   a.prec = prec_code;
   a.scale = 1.0;
+  a.dexp = dexp;
   a.nbits = (int)nd.labels.size();
   a.lk = nd.log2k;
   a.kpad = nd.kpad_log2;
@@ -263,9 +265,55 @@ static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst
 }
 
 static void pack_leaf(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
-                      uint64_t slice, hipStream_t s) {
-  PackArgs a = make_pack_args(p, j, dst0, dst1, dst2, prec_code, slice);
+                      uint64_t slice, hipStream_t s, const int *dexp = nullptr) {
+  PackArgs a = make_pack_args(p, j, dst0, dst1, dst2, prec_code, slice, dexp);
   HIP_OK(launch_pack(a, s));
+}
+
+// Exact power-of-two rescaling of the leaf operands: e_j makes the largest
+// gathered |value| of leaf j (over all slices) lie in [1, 2); the final
+// epilogue multiplies by 2^(-K - sum e_j) in float64.  Keeps float32 / bf16
+// operands of many-factor networks away from underflow.
+struct ScaleBuf {
+  unsigned long long *maxbits;
+  int *exps;
+  double *root_scale;
+};
+
+static ScaleBuf scale_buffers(Plan *p) {
+  const int m = p->net->m;
+  if (!p->scale_buf) HIP_OK(hipMalloc(&p->scale_buf, 256 + (size_t)m * 16));
+  char *b = (char *)p->scale_buf;
+  return ScaleBuf{(unsigned long long *)(b + 256), (int *)(b + 256 + (size_t)m * 8), (double *)b};
+}
+
+static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
+  Network &net = *p->net;
+  const int m = net.m;
+  HIP_OK(hipMemsetAsync(sb.maxbits, 0, (size_t)m * 8, s));
+  for (int j = 0; j < m; ++j) {
+    const TensorIn &t = net.t[j];
+    PackArgs pa = make_pack_args(p, j, nullptr, nullptr, nullptr, 0, 0);
+    AbsMaxArgs a{};
+    a.src = t.dev_pauli;
+    a.base = 0;
+    a.out = sb.maxbits + j;
+    const int c = (int)t.cuts.size(), o = (int)t.outputs.size();
+    for (int i = 0; i < o; ++i) {
+      auto it = std::find(p->fixed_q.begin(), p->fixed_q.end(), t.outputs[i]);
+      if (it != p->fixed_q.end()) a.base |= (uint64_t)p->fixed_v[it - p->fixed_q.begin()] << i;
+    }
+    a.nbits = pa.nbits;
+    for (int i = 0; i < pa.nbits; ++i) a.inpos[i] = pa.inpos[i];
+    for (int i = 0; i < c; ++i)
+      if (std::find(p->sliced.begin(), p->sliced.end(), t.cuts[i]) != p->sliced.end()) {
+        if (a.nbits + 2 > kMaxBits) fail(TQC_ERR_UNSUPPORTED, "operand with too many index bits");
+        a.inpos[a.nbits++] = o + 2 * (c - 1 - i);
+        a.inpos[a.nbits++] = o + 2 * (c - 1 - i) + 1;
+      }
+    HIP_OK(launch_absmax(a, s));
+  }
+  HIP_OK(launch_scale_exponents(sb.maxbits, m, net.K, sb.exps, sb.root_scale, s));
 }
 
 static TransformArgs make_transform_args(const TensorIn &t, double *out) {
@@ -294,7 +342,8 @@ static int pick_tile(const Plan *p, const Step &st) {
   return 2;
 }
 
-static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root_kind) {
+static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root_kind,
+                               const double *dscale = nullptr) {
   const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
   const Node &on = p->nodes[st.out];
   GemmArgs g{};
@@ -315,6 +364,7 @@ static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root
   if (st.root) {
     g.c0 = root_out;
     g.scale = std::ldexp(1.0, -p->net->K);
+    g.dscale = dscale;
     g.out_kind = root_kind;
   } else {
     char *po = (char *)p->ws + on.offset;
@@ -385,6 +435,10 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
     return;
   }
   bool first_done = false;
+  const ScaleBuf sb = scale_buffers(p);
+  if (tm) tm->begin(1);
+  compute_scales(p, sb, s);
+  if (tm) tm->end();
   for (uint64_t sl = s0; sl < s1; ++sl) {
     const bool first = (sl == s0);
     if (tm) tm->begin(1);
@@ -393,14 +447,14 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
       if (!first && !nd.slice_dep) continue;
       char *b = (char *)p->ws + nd.offset;
       pack_leaf(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
-                nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pc, sl, s);
+                nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pc, sl, s, sb.exps + j);
     }
     if (tm) tm->end();
     for (size_t si = 0; si < p->steps.size(); ++si) {
       const Step &st = p->steps[si];
       Node &on = p->nodes[st.out];
       if (!first && !on.slice_dep) continue;
-      GemmArgs g = make_gemm_args(p, st, root_out, root_kind);
+      GemmArgs g = make_gemm_args(p, st, root_out, root_kind, sb.root_scale);
       if (st.root && root_kind == OUT_F64_ACC && !accumulate_first && !first_done) g.out_kind = OUT_F64;
       if (tm) tm->begin(2 + (int)si);
       HIP_OK(launch_gemm(pc, g, st.tile, s));
@@ -730,8 +784,9 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+  const ScaleBuf sb = scale_buffers(p);
   for (Step &st : p->steps) {
-    GemmArgs g = make_gemm_args(p, st, out, root_kind);
+    GemmArgs g = make_gemm_args(p, st, out, root_kind, sb.root_scale);
     int best = st.tile;
     double best_ms = 1e30;
     for (int tile = 0; tile < 3; ++tile) {

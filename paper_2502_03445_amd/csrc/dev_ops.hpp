@@ -79,7 +79,8 @@ __device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
   const uint64_t kmask = (1ull << a.lk) - 1;
   uint64_t src = a.base;
   for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
-  const double v = a.src[src] * a.scale;
+  const double sc = a.dexp ? ldexp(a.scale, *a.dexp) : a.scale;
+  const double v = a.src[src] * sc;
   const uint64_t d = ((e >> a.lk) << a.kpad) | (e & kmask);
   switch (a.prec) {
     case 0:
@@ -106,6 +107,12 @@ __device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
       break;
     }
   }
+}
+
+__device__ inline double gathered_abs(const AbsMaxArgs &a, uint64_t e) {
+  uint64_t src = a.base;
+  for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
+  return fabs(a.src[src]);
 }
 
 // ================================================================= GEMM
@@ -157,26 +164,26 @@ __device__ inline uint64_t scatter_bits(uint64_t v, const uint8_t *pos, int nbit
 }
 
 template <typename AccT>
-__device__ inline void store_out(const GemmArgs &g, uint64_t addr, AccT v) {
+__device__ inline void store_out(const GemmArgs &g, double scale, uint64_t addr, AccT v) {
   switch (g.out_kind) {
     case OUT_F32:
-      ((float *)g.c0)[addr] = (float)((double)v * g.scale);
+      ((float *)g.c0)[addr] = (float)((double)v * scale);
       break;
     case OUT_F64:
-      ((double *)g.c0)[addr] = (double)v * g.scale;
+      ((double *)g.c0)[addr] = (double)v * scale;
       break;
     case OUT_F64_ACC:
-      ((double *)g.c0)[addr] += (double)v * g.scale;
+      ((double *)g.c0)[addr] += (double)v * scale;
       break;
     case OUT_SPLIT2: {
-      const float f = (float)((double)v * g.scale);
+      const float f = (float)((double)v * scale);
       const uint16_t hi = f32_to_bf16_rne(f);
       ((uint16_t *)g.c0)[addr] = hi;
       ((uint16_t *)g.c1)[addr] = f32_to_bf16_rne(f - bf16_to_f32(hi));
       break;
     }
     default: {
-      const float f = (float)((double)v * g.scale);
+      const float f = (float)((double)v * scale);
       const uint16_t hi = f32_to_bf16_rne(f);
       const float r1 = f - bf16_to_f32(hi);
       const uint16_t mid = f32_to_bf16_rne(r1);
@@ -386,6 +393,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     }
   }
 
+  const double scale = g.dscale ? *g.dscale : g.scale;
   // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
   // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
   // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
@@ -410,7 +418,6 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     //    of the loop are fixed per thread
     const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
     constexpr int TT = BM * BN;
-    const float sc = (float)g.scale;
     if (g.vec4) {
       constexpr int LB = 10;  // log2(256 threads * 4)
       const uint64_t lo = scatter_bits((uint64_t)tid * 4, g.lpos, LB);
@@ -419,24 +426,28 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
         const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
         const floatx4 v = *(const floatx4 *)(ct + x);
         switch (g.out_kind) {
-          case OUT_F32:
-            *(floatx4 *)((float *)g.c0 + addr) = v * sc;
+          case OUT_F32: {
+            floatx4 w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[e] = (float)((double)v[e] * scale);
+            *(floatx4 *)((float *)g.c0 + addr) = w;
             break;
+          }
           case OUT_F64_ACC: {
             double *o = (double *)g.c0 + addr;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] += (double)v[e] * g.scale;
+            for (int e = 0; e < 4; ++e) o[e] += (double)v[e] * scale;
             break;
           }
           case OUT_F64: {
             double *o = (double *)g.c0 + addr;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * g.scale;
+            for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * scale;
             break;
           }
           default: {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) store_out(g, addr + e, v[e]);
+            for (int e = 0; e < 4; ++e) store_out(g, scale, addr + e, v[e]);
             break;
           }
         }
@@ -446,7 +457,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       const uint64_t lo = scatter_bits((uint64_t)tid, g.lpos, LB);
       for (int it = 0; it * 256 < TT; ++it) {
         const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
-        store_out(g, addr, ct[it * 256 + tid]);
+        store_out(g, scale, addr, ct[it * 256 + tid]);
       }
     }
     return;
@@ -470,7 +481,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       const uint64_t offm = scatter_bits(row, g.posM, g.lm);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        if (okn[j]) store_out(g, offm + offn[j], acc[i][j][r]);
+        if (okn[j]) store_out(g, scale, offm + offn[j], acc[i][j][r]);
     }
   }
 }

@@ -46,6 +46,17 @@ struct PackArgs {
   int inpos[kMaxBits];       // source bit position of destination bit i
   int prec;                  // 0 f64, 1 f32, 2 bf16x2 split, 3 bf16x3 split
   double scale;              // exact power of two
+  const int *dexp;           // optional device exponent e: values scaled by 2^e
+};
+
+// Largest |value| of a leaf operand over every slice (the gathered bits plus
+// the sliced-cut bits), as the bit pattern of a non-negative double.
+struct AbsMaxArgs {
+  const double *src;
+  uint64_t base;             // fixed-qubit bits
+  int nbits;
+  int inpos[kMaxBits];
+  unsigned long long *out;
 };
 
 // ---------------------------------------------------------------- GEMM
@@ -64,6 +75,7 @@ struct GemmArgs {
   int lm, ln, lk, kpad;
   int out_kind;
   double scale;
+  const double *dscale;      // optional device scale (overrides scale)
   uint8_t posM[kMaxBits];
   uint8_t posN[kMaxBits];
   // filled by the launcher for the chosen tile (staged epilogue):

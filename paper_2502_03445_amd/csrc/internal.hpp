@@ -95,6 +95,7 @@ struct Plan {
   void *ws = nullptr;
   uint64_t ws_bytes = 0;
   double *acc64 = nullptr;       // float64 accumulator for sliced runs (when out is f32)
+  void *scale_buf = nullptr;     // per-leaf |max| bits, exponents, output scale
   ~Plan();
 };
 

@@ -34,6 +34,38 @@ __global__ void __launch_bounds__(256) scale_f64_kernel(double *buf, uint64_t n,
     buf[i] *= s;
 }
 
+__global__ void __launch_bounds__(256) absmax_kernel(AbsMaxArgs a) {
+  __shared__ double red[256];
+  const uint64_t total = 1ull << a.nbits;
+  double mx = 0.0;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    mx = fmax(mx, gathered_abs(a, e));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  // non-negative doubles order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(a.out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// exponents e_j = -floor(log2 max_j) (0 for an all-zero operand) and the
+// output scale 2^(-K - sum e_j)
+__global__ void scale_exponents_kernel(const unsigned long long *maxbits, int m, int K, int *exps,
+                                       double *root_scale) {
+  if (threadIdx.x != 0) return;
+  int sum = 0;
+  for (int j = 0; j < m; ++j) {
+    const double mx = __longlong_as_double((long long)maxbits[j]);
+    const int e = mx > 0.0 ? -ilogb(mx) : 0;
+    exps[j] = e;
+    sum += e;
+  }
+  *root_scale = ldexp(1.0, -K - sum);
+}
+
 template <int P, int BM, int BN, int BK>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) char smem[GemmShape<P, BM, BN, BK>::LDS_BYTES];
@@ -60,6 +92,19 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
 
 hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s) {
   hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s) {
+  uint64_t total = 1ull << a.nbits;
+  unsigned g = grid_for(total, 1024);
+  hipLaunchKernelGGL(absmax_kernel, dim3(g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
+                                  double *root_scale, hipStream_t s) {
+  hipLaunchKernelGGL(scale_exponents_kernel, dim3(1), dim3(64), 0, s, maxbits, m, K, exps, root_scale);
   return hipGetLastError();
 }
 

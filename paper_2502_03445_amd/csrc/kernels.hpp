@@ -11,6 +11,9 @@ hipError_t launch_transform(const TransformArgs &a, hipStream_t s);
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s);
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
+hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s);
+hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
+                                  double *root_scale, hipStream_t s);
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
 hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s);
 

@@ -81,3 +81,73 @@ def random_network(num_tensors, num_cuts, outputs_per_tensor, seed, alpha=0.1,
         edges.append((int(a), int(b)))
     n = int(sum(outputs_per_tensor))
     return network_from_edges(n, num_tensors, edges[:num_cuts], outputs_per_tensor, rng, alpha)
+
+
+def grid_patch_network(seed=None, rows=2, cols=6, patch_h=5, patch_w=2, num_cuts=40,
+                       free_per_patch=2):
+    """Cut network of a 10x12 grid circuit split into a 2x6 arrangement of
+    5x2-qubit patches (120 qubits, 12 subcircuits).  Cut edges join adjacent
+    patches only; multiplicities are seeded so that corner patches carry 6 cuts
+    and the other patches 7 (40 cuts, 80 endpoints).  Tensors are synthetic
+    (Dirichlet(0.1) all-I row, uniform [-p, p] elsewhere); 2 seeded qubits per
+    patch stay free and the other 96 are fixed to a seeded bitstring."""
+    from .configs import rng_for
+    rng = rng_for(5, 0, seed)
+    P = rows * cols
+    pid = lambda r, c: r * cols + c
+    pairs = []
+    for r in range(rows):
+        for c in range(cols):
+            if c + 1 < cols:
+                pairs.append((pid(r, c), pid(r, c + 1)))
+            if r + 1 < rows:
+                pairs.append((pid(r, c), pid(r + 1, c)))
+    corners = {pid(0, 0), pid(0, cols - 1), pid(rows - 1, 0), pid(rows - 1, cols - 1)}
+    target = [6 if j in corners else 7 for j in range(P)]
+    assert sum(target) == 2 * num_cuts
+    for _ in range(10000):
+        mult = {e: 1 for e in pairs}
+        deg = [0] * P
+        for a, b in pairs:
+            deg[a] += 1
+            deg[b] += 1
+        ok = True
+        while sum(deg) < 2 * num_cuts:
+            cand = [e for e in pairs if deg[e[0]] < target[e[0]] and deg[e[1]] < target[e[1]]]
+            if not cand:
+                ok = False
+                break
+            a, b = cand[int(rng.integers(len(cand)))]
+            mult[(a, b)] += 1
+            deg[a] += 1
+            deg[b] += 1
+        if ok and deg == target:
+            break
+    else:
+        raise RuntimeError("no multiplicity assignment")
+    edges = []
+    for e in pairs:
+        edges += [e] * mult[e]
+    order = rng.permutation(len(edges))
+    edges = [edges[i] for i in order]
+    cuts = [(a, b) if rng.integers(2) else (b, a) for a, b in edges]
+    n = rows * patch_h * cols * patch_w
+    width = cols * patch_w
+    tensors = []
+    free = []
+    for r in range(rows):
+        for c in range(cols):
+            j = pid(r, c)
+            qs = sorted((r * patch_h + i) * width + (c * patch_w + k)
+                        for i in range(patch_h) for k in range(patch_w))
+            cids = [ci for ci, (u, d) in enumerate(cuts) if j in (u, d)]
+            T = tensor_values(len(cids), len(qs), rng)
+            tensors.append(TensorSpec(cut_ids=cids, outputs=qs, basis="pauli", data=T))
+            free += [int(q) for q in rng.choice(qs, size=free_per_patch, replace=False)]
+    free = sorted(free)
+    fixed_q = [q for q in range(n) if q not in set(free)]
+    fixed_v = [int(v) for v in rng.integers(0, 2, size=len(fixed_q))]
+    net = Network(n=n, cuts=cuts, tensors=tensors)
+    net.meta.update(name="grid10x12_12patch_40cut_2^24", fixed_qubits=fixed_q, fixed_values=fixed_v,
+                    free_qubits=free)
+    return net
