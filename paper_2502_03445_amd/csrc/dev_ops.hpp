@@ -157,6 +157,17 @@ struct PrecTraits<3> {  // bf16x6
   using Acc = floatx4;
 };
 
+// Bit deposit with a compile-time bound: every pos[] index is a constant, so
+// the positions are loaded once (scalar) instead of once per bit and lane.
+template <int MAXB, int OFF = 0, typename A>
+__device__ inline uint64_t deposit_c(uint64_t v, const A &pos, int nbits) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i)
+    if (i < nbits) r |= ((v >> i) & 1ull) << pos[OFF + i];
+  return r;
+}
+
 __device__ inline uint64_t scatter_bits(uint64_t v, const uint8_t *pos, int nbits) {
   uint64_t r = 0;
   for (int i = 0; i < nbits; ++i) r |= ((v >> i) & 1ull) << pos[i];
@@ -401,14 +412,15 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     // 1) accumulators -> LDS at their compact (output-order) tile index
     float *ct = (float *)smem;
     __syncthreads();  // operand tiles no longer needed
+    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
     uint32_t tcol[FN];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) tcol[j] = deposit(wn * WN + j * 16 + lr, g.rankN, g.ncompact);
+    for (int j = 0; j < FN; ++j) tcol[j] = (uint32_t)deposit_c<LBN>(wn * WN + j * 16 + lr, g.rankN, LBN);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const uint32_t trow = deposit(wm * WM + i * 16 + 4 * lg + r, g.rankM, g.ncompact);
+        const uint32_t trow = (uint32_t)deposit_c<LBM>(wm * WM + i * 16 + 4 * lg + r, g.rankM, LBM);
 #pragma unroll
         for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)acc[i][j][r];
       }
@@ -416,14 +428,16 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     // 2) stream the tile out in output order: compact index x maps to the
     //    output offset sum_b bit_b(x) << lpos[b]; the bits below the stride
     //    of the loop are fixed per thread
-    const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
+    const uint64_t base = deposit_c<kMaxBits>(m0, g.posM, g.lm) + deposit_c<kMaxBits>(n0, g.posN, g.ln);
     constexpr int TT = BM * BN;
+    constexpr int NCB = LBM + LBN;
     if (g.vec4) {
       constexpr int LB = 10;  // log2(256 threads * 4)
-      const uint64_t lo = scatter_bits((uint64_t)tid * 4, g.lpos, LB);
+      const uint64_t lo = deposit_c<LB>((uint64_t)tid * 4, g.lpos, LB);
+#pragma unroll 4
       for (int it = 0; it * 1024 < TT; ++it) {
         const int x = it * 1024 + tid * 4;
-        const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
+        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
         const floatx4 v = *(const floatx4 *)(ct + x);
         switch (g.out_kind) {
           case OUT_F32: {
@@ -454,34 +468,41 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       }
     } else {
       constexpr int LB = 8;  // log2(256 threads)
-      const uint64_t lo = scatter_bits((uint64_t)tid, g.lpos, LB);
+      const uint64_t lo = deposit_c<LB>((uint64_t)tid, g.lpos, LB);
       for (int it = 0; it * 256 < TT; ++it) {
-        const uint64_t addr = base + lo + scatter_bits((uint64_t)it, g.lpos + LB, g.ncompact - LB);
+        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
         store_out(g, scale, addr, ct[it * 256 + tid]);
       }
     }
     return;
   }
-  // direct scatter (partial tiles, float64 form)
-  uint64_t offn[FN];
-  bool okn[FN];
+  // direct scatter (partial tiles, float64 form): row = m0 | local row, the
+  // tile base and the tile-local bits deposit separately
+  {
+    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
+    const int lbm = g.lm < LBM ? g.lm : LBM, lbn = g.ln < LBN ? g.ln : LBN;
+    const uint64_t basem = deposit_c<kMaxBits>(m0, g.posM, g.lm);
+    const uint64_t basen = deposit_c<kMaxBits>(n0, g.posN, g.ln);
+    uint64_t offn[FN];
+    bool okn[FN];
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const uint64_t col = n0 + wn * WN + j * 16 + lr;
-    okn[j] = col < N;
-    offn[j] = okn[j] ? scatter_bits(col, g.posN, g.ln) : 0;
-  }
+    for (int j = 0; j < FN; ++j) {
+      const int cl = wn * WN + j * 16 + lr;
+      okn[j] = n0 + cl < N;
+      offn[j] = basen + deposit_c<LBN>((uint64_t)cl, g.posN, lbn);
+    }
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
+    for (int i = 0; i < FM; ++i) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
-      const uint64_t row = m0 + wm * WM + i * 16 + rr;
-      if (row >= M) continue;
-      const uint64_t offm = scatter_bits(row, g.posM, g.lm);
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
+        const int rl = wm * WM + i * 16 + rr;
+        if (m0 + rl >= M) continue;
+        const uint64_t offm = basem + deposit_c<LBM>((uint64_t)rl, g.posM, lbm);
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        if (okn[j]) store_out(g, scale, offm + offn[j], acc[i][j][r]);
+        for (int j = 0; j < FN; ++j)
+          if (okn[j]) store_out(g, scale, offm + offn[j], acc[i][j][r]);
+      }
     }
   }
 }
