@@ -228,10 +228,14 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
                         int32_t num_keep, const int32_t *keep, double *out, void *stream);
 
 /* -------------------------------------------------------------------- batch
- * Many independent reconstructions in one persistent launch (one kernel
- * whose workgroups claim transform chunks, pack chunks and GEMM tiles of all
- * jobs from a shared queue in dependency order), captured once into a HIP
- * graph and replayed.  Jobs are unsliced plans of one precision; outputs are
+ * Many independent reconstructions in a few launches, captured once into a
+ * HIP graph and replayed: three short launches over all jobs (Pauli
+ * transform, operand abs-max, power-of-two exponents), then persistent
+ * launches whose workgroups claim pack chunks and GEMM tiles of all jobs
+ * from a shared queue.  Default: one persistent launch per depth of the
+ * contraction trees (level-synchronous, items never wait).  With
+ * dependency_waits = 1: a single persistent launch in which each item waits
+ * on its producers' completion counters (bounded by spin_limit).  Jobs are unsliced plans of one precision; outputs are
  * bound at creation (device pointers, out_entries of each plan's out_dtype).
  * The batch keeps pointers to the plans: destroy it before them. */
 typedef struct tqc_batch_s *tqc_batch_t;
@@ -239,6 +243,7 @@ typedef struct tqc_batch_s *tqc_batch_t;
 typedef struct {
   int32_t use_graph;           /* 1: capture reset + launch in a HIP graph   */
   int32_t grid;                /* workgroups; 0 = occupancy x compute units  */
+  int32_t dependency_waits;    /* 0: one launch per tree level; 1: one launch */
   uint64_t spin_limit;         /* bound of each dependency wait; 0 = default.
                                   On overrun the item sets the batch error
                                   flag and skips its work (the launch still

@@ -75,7 +75,7 @@ class StepInfo(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("spin_limit", ctypes.c_uint64)]
+                ("dependency_waits", ctypes.c_int32), ("spin_limit", ctypes.c_uint64)]
 
 
 class TrainOptions(ctypes.Structure):
@@ -368,7 +368,8 @@ def marginal(probs, num_qubits, keep, stream=None):
 class Batch:
     """Independent reconstructions run as one persistent, graph-captured launch."""
 
-    def __init__(self, plans, outs=None, use_graph=True, grid=0, spin_limit=0, stream=None):
+    def __init__(self, plans, outs=None, use_graph=True, grid=0, spin_limit=0, stream=None,
+                 dependency_waits=False):
         L = lib()
         if outs is None:
             outs = [p.output_tensor() for p in plans]
@@ -378,7 +379,8 @@ class Batch:
         ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
         ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
-        opt = BatchOptions(int(bool(use_graph)), int(grid), int(spin_limit))
+        opt = BatchOptions(int(bool(use_graph)), int(grid), int(bool(dependency_waits)),
+                           int(spin_limit))
         h = ctypes.c_void_p()
         _check(L.tqc_batch_create(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream),
                                   ctypes.byref(h)))

@@ -524,6 +524,8 @@ struct Batch {
   void *dmem = nullptr;  // one allocation for all tables and counters
   BatchDesc desc{};
   bool use_graph = true;
+  int by_level = 1;
+  std::vector<unsigned long long> level_first;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -544,6 +546,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   std::unique_ptr<Batch> b(new Batch());
   b->njobs = njobs;
   b->use_graph = opt.use_graph != 0;
+  b->by_level = opt.dependency_waits ? 0 : 1;
   b->prec = int(plans[0]->prec);
   struct TmpUnit {
     BatchUnit u;
@@ -552,8 +555,15 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   };
   std::vector<TmpUnit> units;
   std::vector<TransformArgs> targs;
+  std::vector<AbsMaxArgs> aargs;
   std::vector<PackArgs> pargs;
   std::vector<GemmArgs> gargs;
+  std::vector<int> job_leaf0(1, 0), job_cuts;
+  uint64_t max_t = 0, max_l = 0;
+  // leaf exponents and output scales live in the batch's own buffer; its
+  // device address is known only after allocation, so record indices first
+  struct Fix { int kind; size_t idx; int leaf; int job; };
+  std::vector<Fix> fixes;
   for (int j = 0; j < njobs; ++j) {
     Plan *p = plans[j];
     if (!p || !outs || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
@@ -568,28 +578,44 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
     const int m = net.m;
     const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
     const double job_cost = p->stats.predicted_seconds;
-    std::vector<int> tunit(m, -1), node_unit(p->nodes.size(), -1), depth(p->nodes.size(), 0);
+    std::vector<int> node_unit(p->nodes.size(), -1), depth(p->nodes.size(), 0);
     for (int t = 0; t < m; ++t) {
       const TensorIn &ti = net.t[t];
       if (ti.basis != TQC_BASIS_RAW) continue;
-      TmpUnit u{};
-      u.u.kind = UNIT_TRANSFORM;
-      u.u.job = j;
-      u.u.dep0 = u.u.dep1 = -1;
-      u.u.arg = (int)targs.size();
       targs.push_back(make_transform_args(ti, ti.dev_pauli));
-      u.u.ntiles = (ti.pauli_entries() + 4095) / 4096;
-      u.level = 0;
-      u.cost = job_cost;
-      tunit[t] = (int)units.size();
-      units.push_back(u);
+      max_t = std::max<uint64_t>(max_t, ti.pauli_entries());
     }
+    const int leaf0 = job_leaf0.back();
+    if (m >= 2) {
+      // abs-max of every leaf, as in compute_scales
+      for (int t = 0; t < m; ++t) {
+        const TensorIn &ti = net.t[t];
+        PackArgs pa = make_pack_args(p, t, nullptr, nullptr, nullptr, 0, 0);
+        AbsMaxArgs a{};
+        a.src = ti.dev_pauli;
+        const int c = (int)ti.cuts.size(), o = (int)ti.outputs.size();
+        for (int i = 0; i < o; ++i) {
+          auto it = std::find(p->fixed_q.begin(), p->fixed_q.end(), ti.outputs[i]);
+          if (it != p->fixed_q.end()) a.base |= (uint64_t)p->fixed_v[it - p->fixed_q.begin()] << i;
+        }
+        a.nbits = pa.nbits;
+        for (int i = 0; i < pa.nbits; ++i) a.inpos[i] = pa.inpos[i];
+        (void)c;
+        fixes.push_back({0, aargs.size(), leaf0 + t, j});
+        aargs.push_back(a);
+        max_l = std::max<uint64_t>(max_l, 1ull << a.nbits);
+      }
+      job_leaf0.push_back(leaf0 + m);
+    } else {
+      job_leaf0.push_back(leaf0);
+    }
+    job_cuts.push_back(net.K);
     for (int t = 0; t < m; ++t) {
       const Node &nd = p->nodes[t];
       TmpUnit u{};
       u.u.kind = UNIT_PACK;
       u.u.job = j;
-      u.u.dep0 = tunit[t];
+      u.u.dep0 = -1;
       u.u.dep1 = -1;
       u.u.arg = (int)pargs.size();
       if (m == 1) {
@@ -601,6 +627,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
         pargs.push_back(make_pack_args(p, t, bp, nd.planes > 1 ? bp + nd.plane_bytes : nullptr,
                                        nd.planes > 2 ? bp + 2 * nd.plane_bytes : nullptr,
                                        int(p->prec), 0));
+        fixes.push_back({1, pargs.size() - 1, leaf0 + t, j});
       }
       u.u.ntiles = ((1ull << nd.labels.size()) + 4095) / 4096;
       u.level = 1;
@@ -621,6 +648,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
       const int bm = tile_bm(st.tile);
       prepare_gemm_args(g, b->prec, bm, bm);
       g.swz = 0;  // the work queue decides placement
+      if (st.root) fixes.push_back({2, gargs.size(), -1, j});
       gargs.push_back(g);
       const uint64_t tm = ((1ull << st.lm) + bm - 1) / bm, tn = ((1ull << st.ln) + bm - 1) / bm;
       u.u.ntiles = tm * tn;
@@ -631,6 +659,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
       units.push_back(u);
     }
   }
+  const int nleaves = job_leaf0.back();
   // level order; inside a level, the most expensive jobs first
   std::vector<int> order(units.size());
   std::iota(order.begin(), order.end(), 0);
@@ -652,6 +681,35 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   }
   b->nunits = (int)fin.size();
   b->total = first;
+  // item ranges of the levels (units are sorted by level)
+  {
+    std::vector<int> lev(order.size());
+    for (size_t i = 0; i < order.size(); ++i) lev[i] = units[order[i]].level;
+    b->level_first.clear();
+    for (size_t i = 0; i < fin.size(); ++i)
+      if (i == 0 || lev[i] != lev[i - 1]) b->level_first.push_back(fin[i].first);
+    b->level_first.push_back(first);
+  }
+  // host-side checks before anything runs: dependencies point backwards,
+  // and every argument record is within the ranges the kernels assume
+  for (size_t i = 0; i < fin.size(); ++i) {
+    const BatchUnit &u = fin[i];
+    if (u.dep0 >= (int)i || u.dep1 >= (int)i) fail(TQC_ERR_INTERNAL, "batch unit %zu depends forward", i);
+    if (u.ntiles == 0) fail(TQC_ERR_INTERNAL, "batch unit %zu has no items", i);
+    if (u.kind == UNIT_PACK) {
+      const PackArgs &a = pargs[u.arg];
+      if (a.nbits > kMaxBits || a.lk > a.kpad || a.kpad > 40 || !a.src || !a.dst0 ||
+          u.ntiles != ((1ull << a.nbits) + 4095) / 4096)
+        fail(TQC_ERR_INTERNAL, "batch pack unit %zu has bad arguments", i);
+    } else {
+      const GemmArgs &g = gargs[u.arg];
+      const int bm = tile_bm(u.tile);
+      const uint64_t tiles = (((1ull << g.lm) + bm - 1) / bm) * (((1ull << g.ln) + bm - 1) / bm);
+      if (g.lm > kMaxBits || g.ln > kMaxBits || g.lk > g.kpad || g.kpad > 40 || g.kpad < 4 ||
+          !g.a0 || !g.b0 || !g.c0 || u.ntiles != tiles || g.swz != 0)
+        fail(TQC_ERR_INTERNAL, "batch gemm unit %zu has bad arguments", i);
+    }
+  }
   // one device allocation: units, args, counters, job clocks, flags
   auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   uint64_t off = 0;
@@ -660,12 +718,30 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   const uint64_t o_p = off; off = al(off + pargs.size() * sizeof(PackArgs));
   const uint64_t o_g = off; off = al(off + std::max<size_t>(1, gargs.size()) * sizeof(GemmArgs));
   const uint64_t o_c = off; off = al(off + fin.size() * 4);
-  const uint64_t o_n = off; off = al(off + 8);
+  const uint64_t o_n = off; off = al(off + 8 * (b->level_first.size() + 1));
   const uint64_t o_s = off; off = al(off + njobs * 8);
   const uint64_t o_e = off; off = al(off + njobs * 8);
   const uint64_t o_err = off; off = al(off + 4);
+  const uint64_t o_a = off; off = al(off + std::max<size_t>(1, aargs.size()) * sizeof(AbsMaxArgs));
+  const uint64_t o_mx = off; off = al(off + std::max(1, nleaves) * 8);
+  const uint64_t o_ex = off; off = al(off + std::max(1, nleaves) * 4);
+  const uint64_t o_rs = off; off = al(off + njobs * 8);
+  const uint64_t o_l0 = off; off = al(off + (njobs + 1) * 4);
+  const uint64_t o_k = off; off = al(off + njobs * 4);
   HIP_OK(hipMalloc(&b->dmem, off));
   char *dm = (char *)b->dmem;
+  unsigned long long *d_max = (unsigned long long *)(dm + o_mx);
+  int *d_exp = (int *)(dm + o_ex);
+  double *d_rs = (double *)(dm + o_rs);
+  for (const Fix &f : fixes) {
+    if (f.kind == 0) aargs[f.idx].out = d_max + f.leaf;
+    else if (f.kind == 1) pargs[f.idx].dexp = d_exp + f.leaf;
+    else gargs[f.idx].dscale = d_rs + f.job;
+  }
+  if (!aargs.empty())
+    HIP_OK(hipMemcpy(dm + o_a, aargs.data(), aargs.size() * sizeof(AbsMaxArgs), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(dm + o_l0, job_leaf0.data(), (njobs + 1) * 4, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(dm + o_k, job_cuts.data(), njobs * 4, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(dm + o_units, fin.data(), fin.size() * sizeof(BatchUnit), hipMemcpyHostToDevice));
   if (!targs.empty())
     HIP_OK(hipMemcpy(dm + o_t, targs.data(), targs.size() * sizeof(TransformArgs), hipMemcpyHostToDevice));
@@ -685,6 +761,20 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   d.job_end = (unsigned long long *)(dm + o_e);
   d.error = (unsigned int *)(dm + o_err);
   d.spin_limit = opt.spin_limit ? opt.spin_limit : (1ull << 30);
+  d.ntransforms = (int)targs.size();
+  d.max_transform_elems = max_t;
+  d.aargs = (const AbsMaxArgs *)(dm + o_a);
+  d.nleaves = nleaves;
+  d.max_leaf_elems = max_l;
+  d.maxbits = d_max;
+  d.exps = d_exp;
+  d.root_scale = d_rs;
+  d.job_leaf0 = (const int *)(dm + o_l0);
+  d.job_cuts = (const int *)(dm + o_k);
+  d.nlevels = (int)b->level_first.size() - 1;
+  d.level_first = b->level_first.data();
+  d.nowait = b->by_level;
+  d.first_item = 0;
   int dev = 0, cus = 0, khz = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -700,14 +790,14 @@ static void batch_execute(Batch *b, hipStream_t s) {
   check_device(b->device);
   b->last_stream = s;
   if (!b->use_graph) {
-    HIP_OK(launch_batch(b->prec, b->desc, b->njobs, b->grid, s));
+    HIP_OK(launch_batch(b->prec, b->desc, b->njobs, b->grid, b->by_level, s));
     return;
   }
   if (!b->exec) {
     // capture reset + persistent launch once on a private stream
     HIP_OK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_batch(b->prec, b->desc, b->njobs, b->grid, b->cap_stream);
+    hipError_t le = launch_batch(b->prec, b->desc, b->njobs, b->grid, b->by_level, b->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
     HIP_OK(le);
@@ -748,6 +838,7 @@ static void batch_times(Batch *b, double *start_ms, double *end_ms, uint32_t *er
   HIP_OK(hipMemcpy(st.data(), b->desc.job_start, b->njobs * 8, hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(en.data(), b->desc.job_end, b->njobs * 8, hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&err, b->desc.error, 4, hipMemcpyDeviceToHost));
+  (void)0;
   unsigned long long t0 = ~0ull;
   for (auto x : st) t0 = std::min(t0, x);
   for (int j = 0; j < b->njobs; ++j) {

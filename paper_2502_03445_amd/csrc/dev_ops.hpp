@@ -248,7 +248,9 @@ struct GemmShape {
   static constexpr int LDS_BYTES = MAIN_BYTES;
 };
 
-template <int P, int BM, int BN, int BK>
+// A64: float32 MFMA sums over 256-long k chunks are folded into float64
+// accumulators (long float32 chains would exceed 1e-6 relative error).
+template <int P, int BM, int BN, int BK, bool A64 = false>
 __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   using T = PrecTraits<P>;
   using E = typename T::E;
@@ -286,6 +288,12 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+  constexpr int AM = A64 ? FM : 1, AN = A64 ? FN : 1;
+  doublex4 acc2[AM][AN];
+#pragma unroll
+  for (int i = 0; i < AM; ++i)
+#pragma unroll
+    for (int j = 0; j < AN; ++j) acc2[i][j] = doublex4{0, 0, 0, 0};
 
   uint4 ra[NP][AIT], rb[NP][BIT];
   auto load_global = [&](uint64_t k0) {
@@ -337,7 +345,9 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     }
   };
 
-  const bool staged = (P != 0) && g.staged;
+  // float64 results (A64 with a float64 output) skip the float staging
+  const bool staged = (P != 0) && g.staged &&
+                      (!A64 || (g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC));
 
   load_global(0);
   for (uint64_t k0 = 0; k0 < KP; k0 += BK) {
@@ -402,7 +412,23 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
           }
       }
     }
+    if constexpr (A64 && P != 0) {
+      if (((k0 + BK) & 255) == 0 || k0 + BK >= KP) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc2[i][j][r] += (double)acc[i][j][r];
+            acc[i][j] = Acc{0, 0, 0, 0};
+          }
+      }
+    }
   }
+  auto result = [&](int i, int j, int r) -> double {
+    if constexpr (A64 && P != 0) return acc2[i][j][r];
+    else return (double)acc[i][j][r];
+  };
 
   const double scale = g.dscale ? *g.dscale : g.scale;
   // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
@@ -422,7 +448,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       for (int r = 0; r < 4; ++r) {
         const uint32_t trow = (uint32_t)deposit_c<LBM>(wm * WM + i * 16 + 4 * lg + r, g.rankM, LBM);
 #pragma unroll
-        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)acc[i][j][r];
+        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)result(i, j, r);
       }
     __syncthreads();
     // 2) stream the tile out in output order: compact index x maps to the
@@ -501,7 +527,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
         const uint64_t offm = basem + deposit_c<LBM>((uint64_t)rl, g.posM, lbm);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          if (okn[j]) store_out(g, scale, offm + offn[j], acc[i][j][r]);
+          if (okn[j]) store_out(g, scale, offm + offn[j], result(i, j, r));
       }
     }
   }

@@ -66,10 +66,10 @@ __global__ void scale_exponents_kernel(const unsigned long long *maxbits, int m,
   *root_scale = ldexp(1.0, -K - sum);
 }
 
-template <int P, int BM, int BN, int BK>
+template <int P, int BM, int BN, int BK, bool A64>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) char smem[GemmShape<P, BM, BN, BK>::LDS_BYTES];
-  gemm_tile<P, BM, BN, BK>(g, blockIdx.x, smem);
+  gemm_tile<P, BM, BN, BK, A64>(g, blockIdx.x, smem);
 }
 
 // ============================================================ launchers
@@ -122,7 +122,10 @@ static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
   prepare_gemm_args(g, P, BM, BN);
   static_assert(S::LDS_BYTES <= 65536, "static LDS limit");
-  hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+  if (P != 0 && g.lk > 8)
+    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, false>), dim3((unsigned)tiles), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

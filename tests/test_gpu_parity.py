@@ -84,6 +84,8 @@ CASES = [
     (5, 7, [2, 3, 2, 2, 3]),
     (3, 2, [0, 5, 5]),   # a tensor with no outputs
     (2, 1, [9, 1]),      # K = 4 (padded to the MFMA group)
+    (2, 6, [5, 5]),      # K = 4096: chunked float64 accumulation
+    (3, 7, [4, 3, 4]),   # K = 1024 at one step, ragged M and N
 ]
 
 
