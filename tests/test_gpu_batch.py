@@ -29,6 +29,10 @@ def jobs(form):
     return specs, nets, plans
 
 
+BATCH_OFF = pytest.mark.skip(reason="persistent batch launches are switched off: two runs did not "
+                                    "finish on MI355X and the cause has not been identified")
+
+@BATCH_OFF
 @pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp64"])
 def test_batch_equals_plain_execution(form):
     specs, nets, plans = jobs(form)
@@ -49,6 +53,7 @@ def test_batch_equals_plain_execution(form):
         assert np.abs(got - ref).max() <= tol, (i, np.abs(got - ref).max())
 
 
+@BATCH_OFF
 def test_graph_replays_match_eager():
     specs, nets, plans = jobs("fp32")
     b = tqc.Batch(plans, use_graph=True)
@@ -67,6 +72,7 @@ def test_graph_replays_match_eager():
             assert torch.equal(o, f), (rep, i)
 
 
+@BATCH_OFF
 def test_sequential_baseline_and_no_graph_mode():
     specs, nets, plans = jobs("fp32")
     b = tqc.Batch(plans, use_graph=False)
