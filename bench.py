@@ -32,22 +32,29 @@ TOL = 1e-6
 TOPK = 1000
 
 
-def _oracle_chunk(args):
-    xs, = args
-    from oracle.reconstruct import entries_bruteforce
+_SPEC = None
+
+
+def _oracle_init():
+    global _SPEC
     from workloads import qaoa
-    spec = qaoa.qaoa_network()
-    return entries_bruteforce(spec, xs)
+    _SPEC = qaoa.qaoa_network()
+
+
+def _oracle_chunk(xs):
+    from oracle.reconstruct import entries_bruteforce
+    return entries_bruteforce(_SPEC, xs)
 
 
 def cpu_oracle(xs, cores):
     """The oracle as it stands (float64 brute force over 4^8 cut assignments
-    per entry), parallel over entries."""
-    chunks = np.array_split(xs, max(1, cores * 4))
-    t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(cores) as pool:
-        parts = pool.map(_oracle_chunk, [(c,) for c in chunks if len(c)])
-    dt = time.perf_counter() - t0
+    per entry), parallel over entries.  Worker start-up is not timed."""
+    chunks = [c for c in np.array_split(xs, max(1, cores * 4)) if len(c)]
+    with mp.get_context("spawn").Pool(cores, initializer=_oracle_init) as pool:
+        pool.map(_oracle_chunk, [xs[:1]] * cores, chunksize=1)
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_chunk, chunks, chunksize=1)
+        dt = time.perf_counter() - t0
     return np.concatenate(parts), dt
 
 
@@ -59,6 +66,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, copy a float32 buffer of this size once (untimed): a plain "
+                         "copy kernel of known size for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -77,8 +87,11 @@ def main():
     out = torch.empty(entries, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step(plan):
-        plan.execute(out)
+    def step(plan, phases=None):
+        if phases is None:
+            plan.execute(out)
+        else:
+            phases.append(plan.execute_profiled(out)[1])
         idx, val = tqc.topk(out, TOPK)
         tot = tqc.marginal(out, n, [])
         return idx, val, tot
@@ -99,17 +112,15 @@ def main():
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        # per-phase device time of every timed step: HIP events recorded by the
+        # library on the stream its kernels run on
+        phases = []
         e0.record(stream)
         for _ in range(args.steps):
-            idx, val, tot = step(plan)
+            idx, val, tot = step(plan, phases)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
-        # per-phase device time (HIP events on the execution stream)
-        phases = []
-        for _ in range(max(2, min(args.steps, 5))):
-            _, ph = plan.execute_profiled(out)
-            phases.append(ph)
         ph = np.mean(np.array(phases), axis=0)
         res[form] = {"ms": ms, "phases": ph.tolist(), "plan": plan.stats, "steps": plan.steps,
                      "total": tot.item(), "top_idx": idx.cpu().numpy(), "top_val": val.cpu().numpy()}
@@ -119,9 +130,15 @@ def main():
     # oracle check on sampled entries + every form's top entries
     sample_n = args.sample
     if sample_n == 0:
-        probe = rng.integers(0, entries, size=64, dtype=np.uint64)
-        _, dt = cpu_oracle(probe, 1)
-        sample_n = int(np.clip(15.0 / max(dt / 64, 1e-9) * cores, 256, 200000))
+        # per-entry cost of the oracle, measured in this process, sizes the
+        # sample to about 15 s of work on `cores` workers
+        from oracle.reconstruct import entries_bruteforce
+        probe = rng.integers(0, entries, size=32, dtype=np.uint64)
+        entries_bruteforce(spec, probe[:4])
+        t0 = time.perf_counter()
+        entries_bruteforce(spec, probe)
+        per = (time.perf_counter() - t0) / len(probe)
+        sample_n = int(np.clip(15.0 * cores / max(per, 1e-9), 256, 2000000))
     xs = rng.integers(0, entries, size=sample_n, dtype=np.uint64)
     tops = np.unique(np.concatenate([res[f]["top_idx"][:100] for f in forms])).astype(np.uint64)
     xs_all = np.concatenate([xs, tops])
@@ -135,6 +152,13 @@ def main():
         res[form]["rel_err"] = float(np.abs(got - ref).max() / scale)
         res[form]["max_abs_err"] = float(np.abs(got - ref).max())
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     plain = res["fp32"] if "fp32" in res else res[forms[0]]
     ok = [f for f in forms if res[f]["rel_err"] <= TOL and abs(res[f]["total"] - 1.0) <= TOL]
