@@ -4,7 +4,8 @@ p=1) cut into 4 subcircuits with 8 cuts, full 2^32 output, on one MI355X.
 One step = the whole hot path over resident inputs: float64 Pauli-basis
 transform of the measured subcircuit variants, operand packing, every
 pairwise contraction, the output distribution (float32, 16 GiB), its top-1000
-entries and its total probability (float64 sum).
+entries and its total probability (float64 sum).  The last two come from
+per-tile statistics written by the final contraction (tqc_execute_summary).
 
 The plain FP32 contractor and the other contraction forms are timed on the
 same GPU; the reported value is the fastest form whose error against the CPU
@@ -66,6 +67,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the oracle check (profiling runs): errors are reported as null")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, copy a float32 buffer of this size once (untimed): a plain "
                          "copy kernel of known size for scaling hardware byte counters")
@@ -88,12 +91,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(plan, phases=None):
-        if phases is None:
-            plan.execute(out)
-        else:
-            phases.append(plan.execute_profiled(out)[1])
-        idx, val = tqc.topk(out, TOPK)
-        tot = tqc.marginal(out, n, [])
+        # contraction + top-k + total in one call: the root contraction writes
+        # per-tile maxima and sums, so no extra pass reads the 2^32 vector
+        _, idx, val, tot, ph = plan.execute_summary(out, k=TOPK, profile=phases is not None)
+        if phases is not None:
+            phases.append(ph)
         return idx, val, tot
 
     # sample of output entries checked against the oracle
@@ -128,29 +130,34 @@ def main():
               file=sys.stderr, flush=True)
 
     # oracle check on sampled entries + every form's top entries
-    sample_n = args.sample
-    if sample_n == 0:
-        # per-entry cost of the oracle, measured in this process, sizes the
-        # sample to about 15 s of work on `cores` workers
-        from oracle.reconstruct import entries_bruteforce
-        probe = rng.integers(0, entries, size=32, dtype=np.uint64)
-        entries_bruteforce(spec, probe[:4])
-        t0 = time.perf_counter()
-        entries_bruteforce(spec, probe)
-        per = (time.perf_counter() - t0) / len(probe)
-        sample_n = int(np.clip(15.0 * cores / max(per, 1e-9), 256, 2000000))
-    xs = rng.integers(0, entries, size=sample_n, dtype=np.uint64)
-    tops = np.unique(np.concatenate([res[f]["top_idx"][:100] for f in forms])).astype(np.uint64)
-    xs_all = np.concatenate([xs, tops])
-    ref, cpu_dt = cpu_oracle(xs_all, cores)
-    scale = float(np.abs(ref).max())
-    xt = torch.from_numpy(xs_all.astype(np.int64)).cuda()
-    for form in forms:
-        res[form]["plan_obj"] = plans[form]
-        plans[form].execute(out)
-        got = out[xt].double().cpu().numpy()
-        res[form]["rel_err"] = float(np.abs(got - ref).max() / scale)
-        res[form]["max_abs_err"] = float(np.abs(got - ref).max())
+    cpu_dt, xs_all, sample_n, tops = None, None, 0, None
+    if args.no_check:
+        for form in forms:
+            res[form]["rel_err"] = None
+            res[form]["max_abs_err"] = None
+    else:
+        sample_n = args.sample
+        if sample_n == 0:
+            # per-entry cost of the oracle, measured in this process, sizes the
+            # sample to about 15 s of work on `cores` workers
+            from oracle.reconstruct import entries_bruteforce
+            probe = rng.integers(0, entries, size=32, dtype=np.uint64)
+            entries_bruteforce(spec, probe[:4])
+            t0 = time.perf_counter()
+            entries_bruteforce(spec, probe)
+            per = (time.perf_counter() - t0) / len(probe)
+            sample_n = int(np.clip(15.0 * cores / max(per, 1e-9), 256, 2000000))
+        xs = rng.integers(0, entries, size=sample_n, dtype=np.uint64)
+        tops = np.unique(np.concatenate([res[f]["top_idx"][:100] for f in forms])).astype(np.uint64)
+        xs_all = np.concatenate([xs, tops])
+        ref, cpu_dt = cpu_oracle(xs_all, cores)
+        scale = float(np.abs(ref).max())
+        xt = torch.from_numpy(xs_all.astype(np.int64)).cuda()
+        for form in forms:
+            plans[form].execute(out)
+            got = out[xt].double().cpu().numpy()
+            res[form]["rel_err"] = float(np.abs(got - ref).max() / scale)
+            res[form]["max_abs_err"] = float(np.abs(got - ref).max())
     torch.cuda.synchronize()
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
@@ -161,7 +168,8 @@ def main():
         del src, dst
 
     plain = res["fp32"] if "fp32" in res else res[forms[0]]
-    ok = [f for f in forms if res[f]["rel_err"] <= TOL and abs(res[f]["total"] - 1.0) <= TOL]
+    ok = [f for f in forms if (args.no_check or res[f]["rel_err"] <= TOL) and
+          abs(res[f]["total"] - 1.0) <= TOL]
     chosen = min(ok, key=lambda f: res[f]["ms"]) if ok else "fp32"
     R = res[chosen]
 
@@ -217,7 +225,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and cpu_dt is not None:
         line["cpu_baseline"] = {"value": len(xs_all) / cpu_dt, "unit": "probs/s", "cores": cores,
                                 "kind": "oracle",
                                 "sample": f"{len(xs_all)} entries ({sample_n} seeded uniform + "

@@ -227,6 +227,24 @@ tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
 tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
                         int32_t num_keep, const int32_t *keep, double *out, void *stream);
 
+/* One reconstruction and its summary: tqc_execute into out, then the k
+ * largest entries of out (as tqc_topk: top_idx / top_val, device arrays of k
+ * elements; k = 0 skips them) and the float64 total of out (as tqc_marginal
+ * with num_keep = 0; *total is a device double).  Eq. (1) for the vector,
+ * Eq. (10) for the top entries.  For a single-slice plan of two or more
+ * tensors the root contraction also writes, for each output tile it stores,
+ * the largest value and the float64 sum; the top-k then gathers only the
+ * tiles whose maximum reaches the k-th largest tile maximum, and the total
+ * adds the tile sums, so no extra pass reads the 2^n vector.  Other plans run
+ * the standalone scans.  Top-k results equal tqc_topk's bit for bit; the
+ * total differs from tqc_marginal's only in summation order.  phase_ms (may
+ * be NULL): as tqc_execute_profiled, with the top-k and total in the last
+ * phase; with it the call is synchronous.  0 <= k <= 4096, k <= out_entries.
+ * Errors: INVALID_ARG, SHAPE, OUT_OF_MEMORY, DEVICE. */
+tqc_status tqc_execute_summary(tqc_plan_t plan, void *out, uint64_t out_bytes, int32_t k,
+                               uint64_t *top_idx, double *top_val, double *total,
+                               double *phase_ms, int32_t num_phases, void *stream);
+
 /* -------------------------------------------------------------------- batch
  * Many independent reconstructions in a few launches, captured once into a
  * HIP graph and replayed: three short launches over all jobs (Pauli

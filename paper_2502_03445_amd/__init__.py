@@ -105,6 +105,7 @@ def _declare(L):
         "tqc_execute": [vp, vp, u64, vp],
         "tqc_execute_slices": [vp, vp, u64, u64, u64, i32, vp],
         "tqc_execute_profiled": [vp, vp, u64, vp, _dp, i32],
+        "tqc_execute_summary": [vp, vp, u64, i32, vp, vp, vp, _dp, i32, vp],
         "tqc_network_pauli_tensor": [vp, i32, vp, u64, vp],
         "tqc_topk": [vp, ctypes.c_int, u64, i32, vp, vp, vp],
         "tqc_marginal": [vp, ctypes.c_int, i32, i32, _i32p, vp, vp],
@@ -320,6 +321,26 @@ class Plan:
                                           out.numel() * out.element_size(), _stream_ptr(stream),
                                           ctypes.cast(ms, _dp), n))
         return out, [ms[i] for i in range(n)]
+
+    def execute_summary(self, out=None, k=0, profile=False, stream=None):
+        """Execute, then the k largest entries and the float64 total of the
+        output.  Returns (out, idx, val, total, phase_ms or None); idx int64,
+        val and total float64, on the output's device."""
+        if out is None:
+            out = self.output_tensor()
+        dev = out.device
+        idx = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+        val = torch.empty(max(k, 1), dtype=torch.float64, device=dev)
+        tot = torch.empty(1, dtype=torch.float64, device=dev)
+        n = 3 + self.stats["num_steps"]
+        ms = (ctypes.c_double * n)() if profile else None
+        _check(lib().tqc_execute_summary(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                         out.numel() * out.element_size(), int(k),
+                                         ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                         ctypes.c_void_p(tot.data_ptr()),
+                                         ctypes.cast(ms, _dp) if profile else None, n if profile else 0,
+                                         _stream_ptr(stream)))
+        return out, idx[:k], val[:k], tot, ([ms[i] for i in range(n)] if profile else None)
 
     def execute_slices(self, out, begin, end, accumulate=True, stream=None):
         assert out.dtype == torch.float64

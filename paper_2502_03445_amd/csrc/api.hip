@@ -77,6 +77,7 @@ Plan::~Plan() {
   if (ws) (void)hipFree(ws);
   if (acc64) (void)hipFree(acc64);
   if (scale_buf) (void)hipFree(scale_buf);
+  if (stats_buf) (void)hipFree(stats_buf);
 }
 
 // ------------------------------------------------------------ network
@@ -419,7 +420,8 @@ struct Timing {
 
 // run slices [s0, s1); root output goes to `root_out` (dtype per kind)
 static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint64_t s1,
-                       bool accumulate_first, hipStream_t s, Timing *tm = nullptr) {
+                       bool accumulate_first, hipStream_t s, Timing *tm = nullptr,
+                       unsigned long long *tkey = nullptr, double *tsum = nullptr) {
   Network &net = *p->net;
   const int m = net.m;
   const int pc = int(p->prec);
@@ -456,6 +458,10 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
       if (!first && !on.slice_dep) continue;
       GemmArgs g = make_gemm_args(p, st, root_out, root_kind, sb.root_scale);
       if (st.root && root_kind == OUT_F64_ACC && !accumulate_first && !first_done) g.out_kind = OUT_F64;
+      if (st.root && tkey) {
+        g.tkey = tkey;
+        g.tsum = tsum;
+      }
       if (tm) tm->begin(2 + (int)si);
       HIP_OK(launch_gemm(pc, g, st.tile, s));
       if (tm) tm->end();
@@ -486,6 +492,70 @@ static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timin
   }
 }
 
+// The full vector plus its k largest entries and its float64 total.  A
+// single-slice plan with at least two tensors gets them from per-tile
+// statistics that the root contraction writes while storing its tiles (no
+// extra pass over the 2^n output); otherwise the standalone scans run after
+// the contraction.  Top-k results are identical either way; the totals differ
+// only in float64 summation order.
+static void *get_scratch(uint64_t bytes, hipStream_t s);
+static std::mutex &scratch_mutex();
+
+static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint64_t *idx_out,
+                            double *val_out, double *total, hipStream_t s, Timing *tm) {
+  const uint64_t entries = 1ull << p->out_bits;
+  if (k < 0 || k > 4096 || (uint64_t)k > entries) fail(TQC_ERR_INVALID_ARG, "k = %d", k);
+  if (!total || (k > 0 && (!idx_out || !val_out))) fail(TQC_ERR_INVALID_ARG, "null argument");
+  const int dtype = p->out_dtype == TQC_F64 ? 0 : 1;
+  const int fin_phase = 2 + (int)p->steps.size();
+  const Step *root = nullptr;
+  for (const Step &st : p->steps)
+    if (st.root) root = &st;
+  if (p->num_slices != 1 || p->net->m < 2 || !root) {
+    execute(p, out, out_bytes, s, tm);
+    std::lock_guard<std::mutex> lk(scratch_mutex());
+    const uint64_t sb = std::max(marginal_scratch_bytes(p->out_bits, 0),
+                                 k > 0 ? topk_scratch_bytes(entries, k) : 0);
+    void *sp = get_scratch(sb, s);
+    if (tm) tm->begin(fin_phase);
+    HIP_OK(launch_marginal(out, dtype, p->out_bits, 0, nullptr, total, sp, sb, s));
+    if (k > 0) HIP_OK(launch_topk(out, dtype, entries, k, idx_out, val_out, sp, sb, s));
+    if (tm) tm->end();
+    return;
+  }
+  const uint64_t need = entries * (p->out_dtype == TQC_F64 ? 8 : 4);
+  if (!out) fail(TQC_ERR_INVALID_ARG, "output pointer is null");
+  if (out_bytes < need) fail(TQC_ERR_SHAPE, "output holds %llu bytes, needs %llu",
+                             (unsigned long long)out_bytes, (unsigned long long)need);
+  ensure_workspace(p, s);
+  const int bm = tile_bm(root->tile);
+  const int lb = __builtin_ctz(bm);
+  const uint64_t tilesM = ((1ull << root->lm) + bm - 1) / bm, tilesN = ((1ull << root->ln) + bm - 1) / bm;
+  const uint64_t ntiles = tilesM * tilesN;
+  const uint64_t tbytes = (ntiles * 16 + 255) & ~uint64_t(255);
+  const uint64_t sbytes = tbytes + topk_tiles_scratch_bytes(entries, ntiles, std::max(k, 1));
+  if (p->stats_bytes < sbytes) {
+    if (p->stats_buf) {
+      HIP_OK(hipStreamSynchronize(s));
+      HIP_OK(hipFree(p->stats_buf));
+      p->stats_buf = nullptr;
+    }
+    HIP_OK(hipMalloc(&p->stats_buf, sbytes));
+    p->stats_bytes = sbytes;
+  }
+  unsigned long long *tkey = (unsigned long long *)p->stats_buf;
+  double *tsum = (double *)(tkey + ntiles);
+  char *tscratch = (char *)p->stats_buf + tbytes;
+  run_slices(p, out, dtype == 0 ? OUT_F64 : OUT_F32, 0, 1, false, s, tm, tkey, tsum);
+  GemmArgs g = make_gemm_args(p, *root, out, dtype == 0 ? OUT_F64 : OUT_F32);
+  if (tm) tm->begin(fin_phase);
+  HIP_OK(launch_sum_tiles(tsum, ntiles, total, s));
+  if (k > 0)
+    HIP_OK(launch_topk_tiles(out, dtype, entries, g, lb, lb, tkey, ntiles, k, idx_out, val_out, tscratch,
+                             sbytes - tbytes, s));
+  if (tm) tm->end();
+}
+
 // ----------------------------------------------------------- scratch
 struct Scratch {
   std::mutex mu;
@@ -494,6 +564,7 @@ struct Scratch {
   int device = -1;
 };
 static Scratch g_scratch;
+static std::mutex &scratch_mutex() { return g_scratch.mu; }
 
 static void *get_scratch(uint64_t bytes, hipStream_t s) {
   int dev = 0;
@@ -1243,6 +1314,25 @@ tqc_status tqc_execute_profiled(tqc_plan_t plan, void *out, uint64_t out_bytes, 
     tm.s = (hipStream_t)stream;
     execute(p, out, out_bytes, (hipStream_t)stream, &tm);
     tm.collect(phase_ms, num_phases);
+  });
+}
+
+tqc_status tqc_execute_summary(tqc_plan_t plan, void *out, uint64_t out_bytes, int32_t k,
+                               uint64_t *top_idx, double *top_val, double *total, double *phase_ms,
+                               int32_t num_phases, void *stream) {
+  return guarded([&] {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) fail(TQC_ERR_INVALID_ARG, "null plan");
+    if (phase_ms) {
+      const int need = 3 + (int)p->steps.size();
+      if (num_phases < need) fail(TQC_ERR_SHAPE, "phase_ms needs %d entries", need);
+      Timing tm;
+      tm.s = (hipStream_t)stream;
+      execute_summary(p, out, out_bytes, k, top_idx, top_val, total, (hipStream_t)stream, &tm);
+      tm.collect(phase_ms, num_phases);
+    } else {
+      execute_summary(p, out, out_bytes, k, top_idx, top_val, total, (hipStream_t)stream, nullptr);
+    }
   });
 }
 

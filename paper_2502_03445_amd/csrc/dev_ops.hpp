@@ -245,8 +245,20 @@ struct GemmShape {
   static constexpr int OPER_BYTES = NP * (BM + BN) * LDR * ES;
   static constexpr int CT_BYTES = (P == 0) ? 0 : BM * BN * 4;  // staged float tile
   static constexpr int MAIN_BYTES = OPER_BYTES > CT_BYTES ? OPER_BYTES : CT_BYTES;
-  static constexpr int LDS_BYTES = MAIN_BYTES;
+  static constexpr int STAT_OFF = MAIN_BYTES;  // 4 waves x (sum, key) of the tile statistics
+  static constexpr int LDS_BYTES = MAIN_BYTES + 64;
 };
+
+// order-preserving unsigned keys of stored output values (larger value,
+// larger key); the float32 key is the one the top-k kernels use
+__device__ inline uint64_t out_key_f32(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+}
+__device__ inline uint64_t out_key_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
 
 // A64: float32 MFMA sums over 256-long k chunks are folded into float64
 // accumulators (long float32 chains would exceed 1e-6 relative error).
@@ -431,6 +443,45 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   };
 
   const double scale = g.dscale ? *g.dscale : g.scale;
+  // tile statistics of the stored values (float32 / float64 outputs only)
+  const bool want_stats = g.tkey != nullptr;
+  double st_sum = 0.0;
+  uint64_t st_key = 0;
+  auto note = [&](double y) {  // y = accumulator * scale, before the store's rounding
+    if (g.out_kind == OUT_F32) {
+      const float f = (float)y;
+      st_sum += (double)f;
+      const uint64_t k = out_key_f32(f);
+      st_key = k > st_key ? k : st_key;
+    } else {
+      st_sum += y;
+      const uint64_t k = out_key_f64(y);
+      st_key = k > st_key ? k : st_key;
+    }
+  };
+  auto finish_stats = [&]() {
+    // fixed-order reduction: lanes by xor butterfly, then waves 0..3
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      st_sum += __shfl_xor(st_sum, off);
+      const uint64_t o = __shfl_xor(st_key, off);
+      st_key = o > st_key ? o : st_key;
+    }
+    double *rs = (double *)(smem + S::STAT_OFF);
+    uint64_t *rk = (uint64_t *)(smem + S::STAT_OFF + 32);
+    if (lane == 0) {
+      rs[wave] = st_sum;
+      rk[wave] = st_key;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
+      uint64_t k = rk[0];
+      for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
+      g.tsum[tm * tilesN + tn] = t;
+      g.tkey[tm * tilesN + tn] = k;
+    }
+  };
   // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
   // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
   // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
@@ -471,6 +522,9 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) w[e] = (float)((double)v[e] * scale);
             *(floatx4 *)((float *)g.c0 + addr) = w;
+            if (want_stats)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
             break;
           }
           case OUT_F64_ACC: {
@@ -483,6 +537,9 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
             double *o = (double *)g.c0 + addr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * scale;
+            if (want_stats)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
             break;
           }
           default: {
@@ -497,9 +554,12 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       const uint64_t lo = deposit_c<LB>((uint64_t)tid, g.lpos, LB);
       for (int it = 0; it * 256 < TT; ++it) {
         const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
-        store_out(g, scale, addr, ct[it * 256 + tid]);
+        const float v = ct[it * 256 + tid];
+        store_out(g, scale, addr, v);
+        if (want_stats) note((double)v * scale);
       }
     }
+    if (want_stats) finish_stats();
     return;
   }
   // direct scatter (partial tiles, float64 form): row = m0 | local row, the
@@ -527,10 +587,15 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
         const uint64_t offm = basem + deposit_c<LBM>((uint64_t)rl, g.posM, lbm);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          if (okn[j]) store_out(g, scale, offm + offn[j], result(i, j, r));
+          if (okn[j]) {
+            const double v = result(i, j, r);
+            store_out(g, scale, offm + offn[j], v);
+            if (want_stats) note(v * scale);
+          }
       }
     }
   }
+  if (want_stats) finish_stats();
 }
 
 // Tile-dependent epilogue parameters (host side): the tile's output bits in

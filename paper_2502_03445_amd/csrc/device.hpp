@@ -85,6 +85,10 @@ struct GemmArgs {
   uint8_t rankM[16], rankN[16];  // compact bit of tile-local row / col bit i
   uint8_t lpos[32];          // output bit of compact bit b
   int swz;                   // XCD-aware tile order
+  // optional per-tile statistics of the stored values (root step only):
+  // largest order-preserving key and float64 sum, at tile tm * tilesN + tn
+  unsigned long long *tkey;
+  double *tsum;
 };
 
 }  // namespace tqc

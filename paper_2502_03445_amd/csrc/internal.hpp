@@ -96,6 +96,8 @@ struct Plan {
   uint64_t ws_bytes = 0;
   double *acc64 = nullptr;       // float64 accumulator for sliced runs (when out is f32)
   void *scale_buf = nullptr;     // per-leaf |max| bits, exponents, output scale
+  void *stats_buf = nullptr;     // per-tile statistics of the root step + top-k scratch
+  uint64_t stats_bytes = 0;
   ~Plan();
 };
 

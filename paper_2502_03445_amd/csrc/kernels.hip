@@ -121,7 +121,7 @@ static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
   const uint64_t tiles = tilesM * tilesN;
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
   prepare_gemm_args(g, P, BM, BN);
-  static_assert(S::LDS_BYTES <= 65536, "static LDS limit");
+  static_assert(S::LDS_BYTES <= 81920, "two workgroups per CU need at most 80 KiB of LDS each");
   if (P != 0 && g.lk > 8)
     hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
   else

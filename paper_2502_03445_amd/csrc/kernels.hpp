@@ -24,5 +24,13 @@ uint64_t topk_scratch_bytes(uint64_t len, int k);
 hipError_t launch_marginal(const void *probs, int dtype, int n, int num_keep, const int *keep,
                            double *out, void *scratch, uint64_t scratch_bytes, hipStream_t s);
 uint64_t marginal_scratch_bytes(int n, int num_keep);
+// fused forms over the per-tile statistics of a root GEMM (tiles of
+// 2^lbm x 2^lbn, see GemmArgs::tkey / tsum)
+uint64_t topk_tiles_scratch_bytes(uint64_t len, uint64_t ntiles, int k);
+hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const GemmArgs &g, int lbm,
+                             int lbn, const unsigned long long *tkey, uint64_t ntiles, int k,
+                             uint64_t *idx_out, double *val_out, void *scratch, uint64_t scratch_bytes,
+                             hipStream_t s);
+hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *out, hipStream_t s);
 
 }  // namespace tqc

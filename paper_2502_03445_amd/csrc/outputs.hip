@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dev_ops.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -423,6 +424,110 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   // exact passes, skipped on the device unless the fast path gave up
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx,
              &fast->fallback, s);
+  return hipGetLastError();
+}
+
+// ---- fused form: the root contraction wrote, per output tile, the largest
+// key of the values it stored.  The k-th largest tile maximum tau0 is a lower
+// bound of the k-th largest entry (k tiles each hold an entry >= tau0), and
+// every entry >= tau0 lies in a tile whose maximum reaches tau0, so only those
+// tiles are gathered.  Tile t covers rows [tm*bm, tm*bm + bm) and columns
+// [tn*bn, tn*bn + bn) of the root GEMM, t = tm * tilesN + tn; entry (m, n) is
+// at output index deposit(m, posM) + deposit(n, posN).
+__global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dtype, GemmArgs g, int lbm,
+                                                          int lbn, uint64_t tilesN,
+                                                          const unsigned long long *tkey,
+                                                          const TopkState *sel, TopkState *fast,
+                                                          uint64_t *cand_key, uint64_t *cand_idx) {
+  const uint64_t t = blockIdx.x;
+  const uint64_t tau0 = sel->prefix;
+  if (tkey[t] < tau0) return;
+  const uint64_t tm = t / tilesN, tn = t % tilesN;
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  const uint64_t m0 = tm << lbm, n0 = tn << lbn;
+  const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
+  const int bm_bits = g.lm < lbm ? g.lm : lbm, bn_bits = g.ln < lbn ? g.ln : lbn;
+  const uint32_t nel = 1u << (lbm + lbn);
+  for (uint32_t e = threadIdx.x; e < nel; e += 256) {
+    const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
+    if (m0 + rl >= M || n0 + cl >= N) continue;
+    const uint64_t i = base + scatter_bits(rl, g.posM, bm_bits) + scatter_bits(cl, g.posN, bn_bits);
+    const uint64_t key = sort_key(p, dtype, i);
+    if (key >= tau0) {
+      const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
+      if (slot < (unsigned long long)kMaxK) {
+        cand_key[slot] = key;
+        cand_idx[slot] = i;
+      }
+    }
+  }
+}
+
+uint64_t topk_tiles_scratch_bytes(uint64_t len, uint64_t ntiles, int k) {
+  const uint64_t nblocks = (len + kChunk - 1) / kChunk;
+  (void)ntiles;
+  return 3 * 256 + kBins * 8 + nblocks * 8 + 2 * (uint64_t)kMaxK * 8 + 2 * (uint64_t)k * 8 + 1024;
+}
+
+hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const GemmArgs &g, int lbm,
+                             int lbn, const unsigned long long *tkey, uint64_t ntiles, int k,
+                             uint64_t *idx_out, double *val_out, void *scratch, uint64_t scratch_bytes,
+                             hipStream_t s) {
+  if (k < 1 || k > kMaxK || (uint64_t)k > len) return hipErrorInvalidValue;
+  if (scratch_bytes < topk_tiles_scratch_bytes(len, ntiles, k) || ntiles > 0x7fffffffull)
+    return hipErrorInvalidValue;
+  const uint64_t tilesN = ((1ull << g.ln) + (1ull << lbn) - 1) >> lbn;
+  char *sp = (char *)scratch;
+  TopkState *st = (TopkState *)sp;
+  TopkState *sel = (TopkState *)(sp + 256);
+  TopkState *fast = (TopkState *)(sp + 512);
+  unsigned long long *hist = (unsigned long long *)(sp + 768);
+  const uint64_t nblocks = (len + kChunk - 1) / kChunk;
+  unsigned long long *blockcnt = hist + kBins;
+  uint64_t *fkey = (uint64_t *)(blockcnt + nblocks);
+  uint64_t *fidx = fkey + kMaxK;
+  uint64_t *cand_key = fidx + kMaxK;
+  uint64_t *cand_idx = cand_key + k;
+  if (ntiles < (uint64_t)k) {
+    exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, nullptr, s);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(topk_fast_init, dim3(1), dim3(64), 0, s, fast);
+  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, sel, hist, 64, k, (const unsigned int *)nullptr);
+  uint64_t hb = (ntiles + 255) / 256;
+  if (hb > 8192) hb = 8192;
+  for (int resolved = 0; resolved < 64;) {
+    const int bits = (64 - resolved) < kDigitBits ? (64 - resolved) : kDigitBits;
+    hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb), dim3(256), 0, s, (const void *)tkey, 2, ntiles, sel,
+                       hist, bits, (const unsigned int *)nullptr);
+    hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, sel, hist, bits, (const unsigned int *)nullptr);
+    resolved += bits;
+  }
+  hipLaunchKernelGGL(topk_collect_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, probs, dtype, g, lbm, lbn,
+                     tilesN, tkey, sel, fast, fkey, fidx);
+  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, fkey, fidx, k, dtype, idx_out, val_out, fast,
+                     (const unsigned int *)nullptr);
+  exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, &fast->fallback,
+             s);
+  return hipGetLastError();
+}
+
+// total of the per-tile float64 sums: fixed strided split, fixed tree
+__global__ void __launch_bounds__(1024) sum_tiles_kernel(const double *ts, uint64_t n, double *out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (uint64_t i = threadIdx.x; i < n; i += 1024) acc += ts[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_tiles_kernel, dim3(1), dim3(1024), 0, s, tsum, ntiles, out);
   return hipGetLastError();
 }
 

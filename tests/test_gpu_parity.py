@@ -245,3 +245,56 @@ def test_ghz32_and_aqft32_full_closed_form():
             assert dev <= 1e-6 * 2.0 ** -32
         del out
         torch.cuda.empty_cache()
+
+
+# ------------------------------------------------- fused summary (top-k, total)
+SUMMARY_CASES = [
+    ("fp32", dict(), (2, 3, [6, 7])),            # full 128 tiles, staged epilogue
+    ("fp32", dict(), (3, 4, [1, 5, 4])),         # ragged tiles (direct epilogue)
+    ("fp64", dict(), (4, 6, [3, 3, 2, 3])),      # float64 output, direct epilogue
+    ("bf16x6", dict(), (5, 7, [2, 3, 2, 2, 3])),
+    ("fp32", dict(fixed={1: 1, 4: 0}), (4, 5, [3, 4, 3, 3])),
+    ("fp32", dict(sliced=[0, 2]), (4, 6, [3, 3, 2, 3])),   # sliced: standalone scans
+    ("fp64", dict(), (1, 0, [9])),                          # one tensor: standalone scans
+]
+
+
+@pytest.mark.parametrize("case", range(len(SUMMARY_CASES)))
+def test_summary_equals_standalone_scans(case):
+    form, kw, (m, K, outs) = SUMMARY_CASES[case]
+    spec = synthetic.random_network(m, K, outs, seed=700 + case)
+    N = tqc.Network.from_spec(spec)
+    P = tqc.Plan(N, precision=form, out_dtype="f64" if form == "fp64" else "f32", **kw)
+    plain = P.execute().clone()
+    n_out = P.stats["out_qubits"]
+    for k in (1, min(37, P.out_entries), min(1000, P.out_entries)):
+        out, idx, val, tot, ph = P.execute_summary(k=k, profile=(k == 1))
+        torch.cuda.synchronize()
+        assert torch.equal(out, plain)  # the statistics do not change the stored values
+        ri, rv = tqc.topk(out, k)
+        assert torch.equal(idx, ri) and torch.equal(val, rv), (case, k)
+        rt = tqc.marginal(out, n_out, []).item()
+        assert abs(tot.item() - rt) <= 1e-12 * max(1.0, out.double().abs().sum().item())
+        if ph is not None:
+            assert len(ph) == 3 + P.stats["num_steps"] and all(x >= 0 for x in ph)
+    # k = 0: total only
+    _, _, _, tot0, _ = P.execute_summary(k=0)
+    assert tot0.item() == tot.item()
+
+
+def test_summary_qaoa32_full_size():
+    """The benchmark's step at its full size: 2^32 float32 entries, top-1000."""
+    spec = qaoa.qaoa_network()
+    N = tqc.Network.from_spec(spec)
+    for form in ("fp32", "bf16x6"):
+        P = tqc.Plan(N, precision=form)
+        out, idx, val, tot, _ = P.execute_summary(k=1000)
+        ri, rv = tqc.topk(out, 1000)
+        assert torch.equal(idx, ri) and torch.equal(val, rv), form
+        rt = tqc.marginal(out, 32, []).item()
+        assert abs(tot.item() - rt) <= 1e-12 and abs(tot.item() - 1.0) <= 1e-6
+        xs = idx[:50].cpu().numpy().astype(np.uint64)
+        ref = entries_bruteforce(spec, xs)
+        assert np.abs(val[:50].cpu().numpy() - ref).max() <= 1e-6 * ref.max()
+        del out
+        torch.cuda.empty_cache()
