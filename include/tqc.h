@@ -145,7 +145,9 @@ typedef struct {
   tqc_costmodel_t cost_model;  /* required for TQC_COST_MLP                  */
   int32_t num_candidates;      /* randomised-greedy candidates (0 = default) */
   uint64_t seed;
-  int32_t tile_policy;         /* 0 fixed default tiles, 1 autotuned table   */
+  int32_t tile_policy;         /* 0 fixed default tiles, 1 autotuned table,
+                                  2 fixed tiles and no persistent final-step
+                                  kernel (the general GEMM for every step)  */
 } tqc_plan_options;
 
 void tqc_plan_options_default(tqc_plan_options *opt);

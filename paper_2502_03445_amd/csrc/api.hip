@@ -463,7 +463,9 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
         g.tsum = tsum;
       }
       if (tm) tm->begin(2 + (int)si);
-      HIP_OK(launch_gemm(pc, g, st.tile, s));
+      if (st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(pc, g))
+        HIP_OK(launch_root_gemm(pc, g, s));
+      else HIP_OK(launch_gemm(pc, g, st.tile, s));
       if (tm) tm->end();
     }
     first_done = true;
@@ -532,7 +534,7 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
   const int lb = __builtin_ctz(bm);
   const uint64_t tilesM = ((1ull << root->lm) + bm - 1) / bm, tilesN = ((1ull << root->ln) + bm - 1) / bm;
   const uint64_t ntiles = tilesM * tilesN;
-  const uint64_t tbytes = (ntiles * 16 + 255) & ~uint64_t(255);
+  const uint64_t tbytes = ((ntiles * 16 + 255) & ~uint64_t(255)) + 256 * 8;
   const uint64_t sbytes = tbytes + topk_tiles_scratch_bytes(entries, ntiles, std::max(k, 1));
   if (p->stats_bytes < sbytes) {
     if (p->stats_buf) {
@@ -549,7 +551,7 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
   run_slices(p, out, dtype == 0 ? OUT_F64 : OUT_F32, 0, 1, false, s, tm, tkey, tsum);
   GemmArgs g = make_gemm_args(p, *root, out, dtype == 0 ? OUT_F64 : OUT_F32);
   if (tm) tm->begin(fin_phase);
-  HIP_OK(launch_sum_tiles(tsum, ntiles, total, s));
+  HIP_OK(launch_sum_tiles(tsum, ntiles, (double *)(tscratch - 256 * 8), total, s));
   if (k > 0)
     HIP_OK(launch_topk_tiles(out, dtype, entries, g, lb, lb, tkey, ntiles, k, idx_out, val_out, tscratch,
                              sbytes - tbytes, s));

@@ -447,12 +447,14 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   const bool want_stats = g.tkey != nullptr;
   double st_sum = 0.0;
   uint64_t st_key = 0;
+  uint32_t st_k32 = 0;
   auto note = [&](double y) {  // y = accumulator * scale, before the store's rounding
     if (g.out_kind == OUT_F32) {
       const float f = (float)y;
       st_sum += (double)f;
-      const uint64_t k = out_key_f32(f);
-      st_key = k > st_key ? k : st_key;
+      const uint32_t u = __float_as_uint(f);
+      const uint32_t k = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);  // out_key_f32
+      st_k32 = k > st_k32 ? k : st_k32;
     } else {
       st_sum += y;
       const uint64_t k = out_key_f64(y);
@@ -460,6 +462,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     }
   };
   auto finish_stats = [&]() {
+    if (g.out_kind == OUT_F32) st_key = st_k32;
     // fixed-order reduction: lanes by xor butterfly, then waves 0..3
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

@@ -16,6 +16,11 @@ hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int 
                                   double *root_scale, hipStream_t s);
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
 hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s);
+// persistent final-step GEMM (128 x 128 tiles, K <= 256, float32 output in a
+// layout whose two lowest output bits fall in every tile); hipErrorNotSupported
+// when the step does not qualify
+bool root_gemm_eligible(int prec, const GemmArgs &g);
+hipError_t launch_root_gemm(int prec, const GemmArgs &g, hipStream_t s);
 
 // output forms
 hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
@@ -31,6 +36,8 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
                              int lbn, const unsigned long long *tkey, uint64_t ntiles, int k,
                              uint64_t *idx_out, double *val_out, void *scratch, uint64_t scratch_bytes,
                              hipStream_t s);
-hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *out, hipStream_t s);
+// partial: 256 doubles of device scratch
+hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *partial, double *out,
+                            hipStream_t s);
 
 }  // namespace tqc

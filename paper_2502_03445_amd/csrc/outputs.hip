@@ -104,25 +104,53 @@ __global__ void __launch_bounds__(256) topk_hist(const void *p, int dtype, uint6
     if (lh[b]) atomicAdd(&hist[b], (unsigned long long)lh[b]);
 }
 
-__global__ void topk_select(TopkState *st, unsigned long long *hist, int bits,
-                            const unsigned int *gate) {
+// Walks the bins from the top: thread t owns the t-th group of `per`
+// consecutive bins (from the largest down); group totals are scanned in LDS
+// and the one thread whose group holds the kr-th entry resolves the digit.
+__global__ void __launch_bounds__(256) topk_select(TopkState *st, unsigned long long *hist, int bits,
+                                                   const unsigned int *gate) {
   if (gated_off(gate)) return;
-  if (threadIdx.x == 0) {
-    const int shift = st->hi_shift - bits;
-    unsigned long long cum = 0;
-    for (int b = (1 << bits) - 1; b >= 0; --b) {
+  __shared__ unsigned long long grp[256];
+  const int nb = 1 << bits;
+  const int per = (nb + 255) / 256;
+  const int t = threadIdx.x;
+  const int shift = st->hi_shift - bits;
+  const unsigned long long kr = st->kr;
+  unsigned long long mine = 0;
+  for (int j = 0; j < per; ++j) {
+    const int r = t * per + j;  // rank from the top
+    if (r < nb) mine += hist[nb - 1 - r];
+  }
+  grp[t] = mine;
+  __syncthreads();
+  if (t == 0) {  // exclusive scan of 256 group totals
+    unsigned long long run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const unsigned long long v = grp[i];
+      grp[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  const unsigned long long before = grp[t];
+  if (before < kr && before + mine >= kr) {
+    unsigned long long cum = before;
+    for (int j = 0; j < per; ++j) {
+      const int r = t * per + j;
+      if (r >= nb) break;
+      const int b = nb - 1 - r;
       const unsigned long long h = hist[b];
-      if (cum + h >= st->kr) {
+      if (cum + h >= kr) {
         st->prefix |= (unsigned long long)b << shift;
-        st->kr -= cum;
+        st->kr = kr - cum;
         break;
       }
       cum += h;
     }
-    st->hi_shift = shift;
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+  if (t == 0) st->hi_shift = shift;
+  for (int b = t; b < kBins; b += blockDim.x) hist[b] = 0;
 }
 
 // entries strictly above the threshold go to candidate slots [0, n_gt);
@@ -435,29 +463,30 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
 // [tn*bn, tn*bn + bn) of the root GEMM, t = tm * tilesN + tn; entry (m, n) is
 // at output index deposit(m, posM) + deposit(n, posN).
 __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dtype, GemmArgs g, int lbm,
-                                                          int lbn, uint64_t tilesN,
+                                                          int lbn, uint64_t tilesN, uint64_t ntiles,
                                                           const unsigned long long *tkey,
                                                           const TopkState *sel, TopkState *fast,
                                                           uint64_t *cand_key, uint64_t *cand_idx) {
-  const uint64_t t = blockIdx.x;
   const uint64_t tau0 = sel->prefix;
-  if (tkey[t] < tau0) return;
-  const uint64_t tm = t / tilesN, tn = t % tilesN;
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
-  const uint64_t m0 = tm << lbm, n0 = tn << lbn;
-  const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
   const int bm_bits = g.lm < lbm ? g.lm : lbm, bn_bits = g.ln < lbn ? g.ln : lbn;
   const uint32_t nel = 1u << (lbm + lbn);
-  for (uint32_t e = threadIdx.x; e < nel; e += 256) {
-    const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
-    if (m0 + rl >= M || n0 + cl >= N) continue;
-    const uint64_t i = base + scatter_bits(rl, g.posM, bm_bits) + scatter_bits(cl, g.posN, bn_bits);
-    const uint64_t key = sort_key(p, dtype, i);
-    if (key >= tau0) {
-      const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
-      if (slot < (unsigned long long)kMaxK) {
-        cand_key[slot] = key;
-        cand_idx[slot] = i;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (tkey[t] < tau0) continue;  // uniform over the block
+    const uint64_t tm = t / tilesN, tn = t % tilesN;
+    const uint64_t m0 = tm << lbm, n0 = tn << lbn;
+    const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
+    for (uint32_t e = threadIdx.x; e < nel; e += 256) {
+      const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
+      if (m0 + rl >= M || n0 + cl >= N) continue;
+      const uint64_t i = base + scatter_bits(rl, g.posM, bm_bits) + scatter_bits(cl, g.posN, bn_bits);
+      const uint64_t key = sort_key(p, dtype, i);
+      if (key >= tau0) {
+        const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
+        if (slot < (unsigned long long)kMaxK) {
+          cand_key[slot] = key;
+          cand_idx[slot] = i;
+        }
       }
     }
   }
@@ -503,8 +532,9 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
     hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, sel, hist, bits, (const unsigned int *)nullptr);
     resolved += bits;
   }
-  hipLaunchKernelGGL(topk_collect_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, probs, dtype, g, lbm, lbn,
-                     tilesN, tkey, sel, fast, fkey, fidx);
+  const unsigned cgrid = (unsigned)(ntiles < 2048 ? ntiles : 2048);
+  hipLaunchKernelGGL(topk_collect_tiles, dim3(cgrid), dim3(256), 0, s, probs, dtype, g, lbm, lbn, tilesN,
+                     ntiles, tkey, sel, fast, fkey, fidx);
   hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, fkey, fidx, k, dtype, idx_out, val_out, fast,
                      (const unsigned int *)nullptr);
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, &fast->fallback,
@@ -512,22 +542,41 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
   return hipGetLastError();
 }
 
-// total of the per-tile float64 sums: fixed strided split, fixed tree
-__global__ void __launch_bounds__(1024) sum_tiles_kernel(const double *ts, uint64_t n, double *out) {
-  __shared__ double red[1024];
-  double acc = 0.0;
-  for (uint64_t i = threadIdx.x; i < n; i += 1024) acc += ts[i];
-  red[threadIdx.x] = acc;
+// total of the per-tile float64 sums: block b adds the contiguous range
+// [b*chunk, (b+1)*chunk) by a fixed strided split and a fixed tree, then one
+// block adds the block partials the same way
+constexpr int kSumBlocks = 256;
+
+__device__ inline double block_sum_fixed(double v, double *red) {
+  red[threadIdx.x] = v;
   __syncthreads();
-  for (int w = 512; w >= 1; w >>= 1) {
+  for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  return red[0];
 }
 
-hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_tiles_kernel, dim3(1), dim3(1024), 0, s, tsum, ntiles, out);
+__global__ void __launch_bounds__(256) sum_tiles_pass1(const double *ts, uint64_t n, double *partial) {
+  __shared__ double red[256];
+  const uint64_t chunk = (n + kSumBlocks - 1) / kSumBlocks;
+  const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double acc = 0.0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) acc += ts[i];
+  const double t = block_sum_fixed(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) sum_tiles_pass2(const double *partial, double *out) {
+  __shared__ double red[256];
+  const double t = block_sum_fixed(partial[threadIdx.x], red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+hipError_t launch_sum_tiles(const double *tsum, uint64_t ntiles, double *partial, double *out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(sum_tiles_pass1, dim3(kSumBlocks), dim3(256), 0, s, tsum, ntiles, partial);
+  hipLaunchKernelGGL(sum_tiles_pass2, dim3(1), dim3(kSumBlocks), 0, s, (const double *)partial, out);
   return hipGetLastError();
 }
 

@@ -516,6 +516,7 @@ Plan *build_plan(Network *net, const tqc_plan_options &opt) {
   if (int(opt.precision) < 0 || int(opt.precision) > 3) fail(TQC_ERR_INVALID_ARG, "precision");
   if (opt.out_dtype != TQC_F32 && opt.out_dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "out_dtype");
   p->out_dtype = opt.out_dtype;
+  if (opt.tile_policy < 0 || opt.tile_policy > 2) fail(TQC_ERR_INVALID_ARG, "tile_policy %d", opt.tile_policy);
   p->tile_policy = opt.tile_policy;
   if (opt.num_fixed < 0 || (opt.num_fixed > 0 && (!opt.fixed_qubits || !opt.fixed_values)))
     fail(TQC_ERR_INVALID_ARG, "fixed qubits");

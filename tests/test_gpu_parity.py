@@ -256,6 +256,8 @@ SUMMARY_CASES = [
     ("fp32", dict(fixed={1: 1, 4: 0}), (4, 5, [3, 4, 3, 3])),
     ("fp32", dict(sliced=[0, 2]), (4, 6, [3, 3, 2, 3])),   # sliced: standalone scans
     ("fp64", dict(), (1, 0, [9])),                          # one tensor: standalone scans
+    ("fp32", dict(), (2, 3, [9, 9])),                       # persistent final-step kernel
+    ("bf16x6", dict(), (3, 5, [8, 3, 8])),                  # persistent final-step kernel
 ]
 
 
@@ -298,3 +300,32 @@ def test_summary_qaoa32_full_size():
         assert np.abs(val[:50].cpu().numpy() - ref).max() <= 1e-6 * ref.max()
         del out
         torch.cuda.empty_cache()
+
+
+# ------------------------------------------ persistent final-step kernel
+# roots with 128 x 128 tiles, K <= 256 and float32 output run on the
+# persistent kernel; tile_policy = 2 forces the general kernel for comparison
+ROOT_CASES = [
+    (2, 3, [9, 9]),      # K = 64, 16 tiles (fewer tiles than CUs)
+    (2, 4, [8, 9]),      # K = 256
+    (2, 2, [10, 8]),     # K = 16 (padded to 32 for the bf16 forms)
+    (3, 5, [8, 3, 8]),   # final step after a first contraction
+    (4, 6, [5, 5, 4, 5]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ROOT_CASES)))
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6"])
+def test_final_step_kernel(case, form):
+    m, K, outs = ROOT_CASES[case]
+    spec = synthetic.random_network(m, K, outs, seed=900 + case)
+    N = tqc.Network.from_spec(spec)
+    P0 = tqc.Plan(N, precision=form)
+    P2 = tqc.Plan(N, precision=form, tile_policy=2)
+    a = P0.execute().clone()
+    b = P2.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b), (case, form)  # same arithmetic per accumulator
+    ref = oracle_full(spec)
+    ok, e = tol_ok(form, a.double().cpu().numpy(), ref)
+    assert ok, (case, form, e)
