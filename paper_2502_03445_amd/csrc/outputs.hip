@@ -31,6 +31,8 @@ struct TopkState {
   unsigned long long n_gt;    // slots used by entries strictly above the threshold
   unsigned long long ncand;   // fast path: candidates >= the chunk-max threshold
   unsigned int fallback;      // fast path could not decide: run the exact passes
+  unsigned int pad2;
+  unsigned long long nq;      // tile form: tiles whose maximum reaches the threshold
 };
 
 // keys of an already-keyed array (dtype 2)
@@ -370,6 +372,7 @@ __global__ void topk_fast_init(TopkState *fast) {
   if (threadIdx.x == 0) {
     fast->ncand = 0;
     fast->fallback = 0;
+    fast->nq = 0;
   }
 }
 
@@ -462,31 +465,45 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
 // tiles are gathered.  Tile t covers rows [tm*bm, tm*bm + bm) and columns
 // [tn*bn, tn*bn + bn) of the root GEMM, t = tm * tilesN + tn; entry (m, n) is
 // at output index deposit(m, posM) + deposit(n, posN).
-__global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dtype, GemmArgs g, int lbm,
-                                                          int lbn, uint64_t tilesN, uint64_t ntiles,
-                                                          const unsigned long long *tkey,
-                                                          const TopkState *sel, TopkState *fast,
-                                                          uint64_t *cand_key, uint64_t *cand_idx) {
+// 1) list the tiles whose maximum reaches tau0 (more than kMaxK of them
+//    means more than kMaxK candidates: mark the overflow instead)
+__global__ void __launch_bounds__(256) topk_list_tiles(const unsigned long long *tkey, uint64_t ntiles,
+                                                       const TopkState *sel, TopkState *fast,
+                                                       uint64_t *qlist) {
   const uint64_t tau0 = sel->prefix;
+  for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < ntiles; t += (uint64_t)gridDim.x * 256) {
+    if (tkey[t] < tau0) continue;
+    const unsigned long long q = atomicAdd(&fast->nq, 1ull);
+    if (q < (unsigned long long)kMaxK) qlist[q] = t;
+    else atomicAdd(&fast->ncand, (unsigned long long)kMaxK + 1);
+  }
+}
+
+// 2) every entry >= tau0 of the listed tiles; work items are (tile, run of
+//    256 entries), spread over the whole grid
+__global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dtype, GemmArgs g, int lbm,
+                                                          int lbn, uint64_t tilesN,
+                                                          const uint64_t *qlist, const TopkState *sel,
+                                                          TopkState *fast, uint64_t *cand_key,
+                                                          uint64_t *cand_idx) {
+  const uint64_t tau0 = sel->prefix;
+  const uint64_t nq = fast->nq < (unsigned long long)kMaxK ? fast->nq : (unsigned long long)kMaxK;
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
-  const int bm_bits = g.lm < lbm ? g.lm : lbm, bn_bits = g.ln < lbn ? g.ln : lbn;
-  const uint32_t nel = 1u << (lbm + lbn);
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (tkey[t] < tau0) continue;  // uniform over the block
+  const uint32_t runs = (1u << (lbm + lbn)) / 256u;  // tiles hold >= 1024 entries
+  for (uint64_t w = blockIdx.x; w < nq * runs; w += gridDim.x) {
+    const uint64_t t = qlist[w / runs];
+    const uint32_t e = (uint32_t)(w % runs) * 256u + threadIdx.x;
     const uint64_t tm = t / tilesN, tn = t % tilesN;
     const uint64_t m0 = tm << lbm, n0 = tn << lbn;
-    const uint64_t base = scatter_bits(m0, g.posM, g.lm) + scatter_bits(n0, g.posN, g.ln);
-    for (uint32_t e = threadIdx.x; e < nel; e += 256) {
-      const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
-      if (m0 + rl >= M || n0 + cl >= N) continue;
-      const uint64_t i = base + scatter_bits(rl, g.posM, bm_bits) + scatter_bits(cl, g.posN, bn_bits);
-      const uint64_t key = sort_key(p, dtype, i);
-      if (key >= tau0) {
-        const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
-        if (slot < (unsigned long long)kMaxK) {
-          cand_key[slot] = key;
-          cand_idx[slot] = i;
-        }
+    const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
+    if (m0 + rl >= M || n0 + cl >= N) continue;
+    const uint64_t i = scatter_bits(m0 | rl, g.posM, g.lm) + scatter_bits(n0 | cl, g.posN, g.ln);
+    const uint64_t key = sort_key(p, dtype, i);
+    if (key >= tau0) {
+      const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
+      if (slot < (unsigned long long)kMaxK) {
+        cand_key[slot] = key;
+        cand_idx[slot] = i;
       }
     }
   }
@@ -495,7 +512,7 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
 uint64_t topk_tiles_scratch_bytes(uint64_t len, uint64_t ntiles, int k) {
   const uint64_t nblocks = (len + kChunk - 1) / kChunk;
   (void)ntiles;
-  return 3 * 256 + kBins * 8 + nblocks * 8 + 2 * (uint64_t)kMaxK * 8 + 2 * (uint64_t)k * 8 + 1024;
+  return 3 * 256 + kBins * 8 + nblocks * 8 + 3 * (uint64_t)kMaxK * 8 + 2 * (uint64_t)k * 8 + 1024;
 }
 
 hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const GemmArgs &g, int lbm,
@@ -515,7 +532,8 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
   unsigned long long *blockcnt = hist + kBins;
   uint64_t *fkey = (uint64_t *)(blockcnt + nblocks);
   uint64_t *fidx = fkey + kMaxK;
-  uint64_t *cand_key = fidx + kMaxK;
+  uint64_t *qlist = fidx + kMaxK;
+  uint64_t *cand_key = qlist + kMaxK;
   uint64_t *cand_idx = cand_key + k;
   if (ntiles < (uint64_t)k) {
     exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, nullptr, s);
@@ -532,9 +550,11 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
     hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, sel, hist, bits, (const unsigned int *)nullptr);
     resolved += bits;
   }
-  const unsigned cgrid = (unsigned)(ntiles < 2048 ? ntiles : 2048);
-  hipLaunchKernelGGL(topk_collect_tiles, dim3(cgrid), dim3(256), 0, s, probs, dtype, g, lbm, lbn, tilesN,
-                     ntiles, tkey, sel, fast, fkey, fidx);
+  uint64_t lg = (ntiles + 255) / 256;
+  if (lg > 1024) lg = 1024;
+  hipLaunchKernelGGL(topk_list_tiles, dim3((unsigned)lg), dim3(256), 0, s, tkey, ntiles, sel, fast, qlist);
+  hipLaunchKernelGGL(topk_collect_tiles, dim3(4096), dim3(256), 0, s, probs, dtype, g, lbm, lbn, tilesN,
+                     (const uint64_t *)qlist, sel, fast, fkey, fidx);
   hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, fkey, fidx, k, dtype, idx_out, val_out, fast,
                      (const unsigned int *)nullptr);
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, &fast->fallback,

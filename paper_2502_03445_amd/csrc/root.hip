@@ -65,8 +65,15 @@ struct RootTraits<3> {
   using Frag = bf16x8;
 };
 
+// OR of v over the 64 lanes of the wave (the result is wave-uniform)
+__device__ inline uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+  return v;
+}
+
 template <int P, int KP, bool STATS>
-__global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t ntiles, uint64_t tilesN) {
+__global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint32_t ntiles, int lgtn) {
   using RT = RootTraits<P>;
   using Frag = typename RT::Frag;
   constexpr int KG = RT::KG, NP = RT::NP, ES = RT::ES;
@@ -85,12 +92,13 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t nti
   const uint32_t G = gridDim.x, b = blockIdx.x;
   const uint32_t xcd = b & 7u, slot = b >> 3;
   const uint32_t nslots = (G - xcd + 7u) >> 3;
-  const uint64_t per = (ntiles + 7) >> 3;
-  const uint64_t r0 = xcd * per;
-  const uint64_t r1 = r0 + per < ntiles ? r0 + per : ntiles;
-  const uint64_t mine = r1 > r0 + slot ? (r1 - r0 - slot + nslots - 1) / nslots : 0;
+  const uint32_t per = (ntiles + 7u) >> 3;
+  const uint32_t r0 = xcd * per;
+  const uint32_t r1 = r0 + per < ntiles ? r0 + per : ntiles;
+  const uint32_t mine = r1 > r0 + slot ? (r1 - r0 - slot + nslots - 1) / nslots : 0;
   if (mine == 0) return;  // whole workgroup, before any barrier
-  auto tile_at = [&](uint64_t i) { return r0 + slot + i * nslots; };
+  auto tile_at = [&](uint32_t i) { return r0 + slot + i * nslots; };
+  const uint32_t tnmask = (1u << lgtn) - 1;
 
   const double scale = g.dscale ? *g.dscale : g.scale;
   const char *Ap[3] = {(const char *)g.a0, (const char *)g.a1, (const char *)g.a2};
@@ -99,21 +107,22 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t nti
   Frag fa[R][NP][FM], fb[R][NP][FN];
   floatx4 acc[FM][FN];
 
-  auto load_group = [&](uint64_t tile, int kg, int q) {
-    const uint64_t tm = tile / tilesN, tn = tile % tilesN;
-    const uint64_t kofs = (uint64_t)kg * KG + (P == 1 ? 4 * lg : 8 * lg);
+  // byte offsets of this lane's first A / B fragment row of a tile
+  auto a_off = [&](uint32_t tile) {
+    return ((uint64_t)(tile >> lgtn) * kRT + wm * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+  };
+  auto b_off = [&](uint32_t tile) {
+    return ((uint64_t)(tile & tnmask) * kRT + wn * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+  };
+  auto load_group = [&](uint64_t ao, uint64_t bo, int kg, int q) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i) {
-        const uint64_t row = tm * kRT + wm * 64 + i * 16 + lr;
-        fa[q][p][i] = *(const Frag *)(Ap[p] + (row * KP + kofs) * ES);
-      }
+      for (int i = 0; i < FM; ++i)
+        fa[q][p][i] = *(const Frag *)(Ap[p] + ao + (uint64_t)(i * 16 * KP + kg * KG) * ES);
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const uint64_t row = tn * kRT + wn * 64 + j * 16 + lr;
-        fb[q][p][j] = *(const Frag *)(Bp[p] + (row * KP + kofs) * ES);
-      }
+      for (int j = 0; j < FN; ++j)
+        fb[q][p][j] = *(const Frag *)(Bp[p] + bo + (uint64_t)(j * 16 * KP + kg * KG) * ES);
     }
   };
 
@@ -179,20 +188,33 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t nti
     }
   };
 
-  auto tile_base = [&](uint64_t tile) {
-    const uint64_t tm = tile / tilesN, tn = tile % tilesN;
-    return deposit_c<kMaxBits>(tm * kRT, g.posM, g.lm) + deposit_c<kMaxBits>(tn * kRT, g.posN, g.ln);
+  // output offset of a tile's first entry: the tile-row bits (M bits >= 7)
+  // and tile-column bits deposit to their output positions; lane l handles
+  // bit 7 + l of each, then the wave ORs them together
+  const int pm = 7 + lane < g.lm ? g.posM[7 + lane] : 0;
+  const int pn = 7 + lane < g.ln ? g.posN[7 + lane] : 0;
+  const bool hm = 7 + lane < g.lm, hn = 7 + lane < g.ln;
+  auto tile_base = [&](uint32_t tile) {
+    const uint32_t tm = tile >> lgtn, tn = tile & tnmask;
+    uint64_t v = 0;
+    if (hm && lane < 32 && ((tm >> lane) & 1u)) v |= 1ull << pm;
+    if (hn && lane < 32 && ((tn >> lane) & 1u)) v |= 1ull << pn;
+    return wave_or(v);
   };
 
   // One pass: MFMAs of tile `cur` (prefetching ahead, the last groups for
-  // tile `next`) interleaved with the stores of the staged tile `prev`.
-  auto body = [&](auto MF, auto ST, uint64_t cur, uint64_t next, uint64_t prev, int par) {
+  // tile `next`) interleaved with the stores of the staged tile `prev`
+  // (output offset pbase).
+  auto body = [&](auto MF, auto ST, uint32_t cur, uint32_t next, uint32_t prev, uint64_t pbase, int par) {
     constexpr bool DO_MF = decltype(MF)::value, DO_ST = decltype(ST)::value;
     char *ct_cur = smem + par * kCtBytes;
     const char *ct_prev = smem + (par ^ 1) * kCtBytes;
-    uint64_t pbase = 0;
-    if constexpr (DO_ST) pbase = tile_base(prev);
+    uint64_t ca = 0, cb = 0, na = 0, nb = 0;
     if constexpr (DO_MF) {
+      ca = a_off(cur);
+      cb = b_off(cur);
+      na = a_off(next);
+      nb = b_off(next);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -203,8 +225,8 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t nti
       if constexpr (DO_MF) {
         const int q = kg % R;
         mfma_group(q);
-        if (kg + R < NKG) load_group(cur, kg + R, q);
-        else load_group(next, kg + R - NKG, q);
+        if (kg + R < NKG) load_group(ca, cb, kg + R, q);
+        else load_group(na, nb, kg + R - NKG, q);
       }
       if constexpr (DO_ST) {
 #pragma unroll
@@ -246,42 +268,48 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint64_t nti
         const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
         uint32_t k = rk[0];
         for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
-        const uint64_t tm = prev / tilesN, tn = prev % tilesN;
-        g.tsum[tm * tilesN + tn] = t;
-        g.tkey[tm * tilesN + tn] = k;
+        g.tsum[prev] = t;
+        g.tkey[prev] = k;
       }
     }
   };
 
   using T1 = std::true_type;
   using F0 = std::false_type;
+  {
+    const uint64_t ao = a_off(tile_at(0)), bo = b_off(tile_at(0));
 #pragma unroll
-  for (int q = 0; q < R; ++q) load_group(tile_at(0), q, q);
-  body(T1{}, F0{}, tile_at(0), tile_at(mine > 1 ? 1 : 0), 0, 0);
-  for (uint64_t i = 1; i < mine; ++i)
-    body(T1{}, T1{}, tile_at(i), tile_at(i + 1 < mine ? i + 1 : i), tile_at(i - 1), (int)(i & 1));
-  body(F0{}, T1{}, 0, 0, tile_at(mine - 1), (int)(mine & 1));
+    for (int q = 0; q < R; ++q) load_group(ao, bo, q, q);
+  }
+  uint64_t base = tile_base(tile_at(0));
+  body(T1{}, F0{}, tile_at(0), tile_at(mine > 1 ? 1 : 0), 0, 0, 0);
+  for (uint32_t i = 1; i < mine; ++i) {
+    const uint64_t nbase = tile_base(tile_at(i));
+    body(T1{}, T1{}, tile_at(i), tile_at(i + 1 < mine ? i + 1 : i), tile_at(i - 1), base, (int)(i & 1));
+    base = nbase;
+  }
+  body(F0{}, T1{}, 0, 0, tile_at(mine - 1), base, (int)(mine & 1));
 }
 
 template <int P, int KP>
-hipError_t launch_root_kp(const GemmArgs &g, uint64_t ntiles, uint64_t tilesN, int grid, hipStream_t s) {
+hipError_t launch_root_kp(const GemmArgs &g, uint32_t ntiles, int lgtn, int grid, hipStream_t s) {
   if (g.tkey)
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true>), dim3(grid), dim3(256), 0, s, g, ntiles, tilesN);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true>), dim3(grid), dim3(256), 0, s, g, ntiles, lgtn);
   else
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false>), dim3(grid), dim3(256), 0, s, g, ntiles, tilesN);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false>), dim3(grid), dim3(256), 0, s, g, ntiles, lgtn);
   return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_root_p(const GemmArgs &g, uint64_t ntiles, uint64_t tilesN, int grid, hipStream_t s) {
+hipError_t launch_root_p(const GemmArgs &g, uint32_t ntiles, int lgtn, int grid, hipStream_t s) {
   switch (g.kpad) {
     case 4:
-      if constexpr (P == 1) return launch_root_kp<P, 16>(g, ntiles, tilesN, grid, s);
+      if constexpr (P == 1) return launch_root_kp<P, 16>(g, ntiles, lgtn, grid, s);
       return hipErrorNotSupported;
-    case 5: return launch_root_kp<P, 32>(g, ntiles, tilesN, grid, s);
-    case 6: return launch_root_kp<P, 64>(g, ntiles, tilesN, grid, s);
-    case 7: return launch_root_kp<P, 128>(g, ntiles, tilesN, grid, s);
-    case 8: return launch_root_kp<P, 256>(g, ntiles, tilesN, grid, s);
+    case 5: return launch_root_kp<P, 32>(g, ntiles, lgtn, grid, s);
+    case 6: return launch_root_kp<P, 64>(g, ntiles, lgtn, grid, s);
+    case 7: return launch_root_kp<P, 128>(g, ntiles, lgtn, grid, s);
+    case 8: return launch_root_kp<P, 256>(g, ntiles, lgtn, grid, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -303,6 +331,7 @@ int cu_count() {
 bool root_gemm_eligible(int prec, const GemmArgs &g) {
   if (prec < 1 || prec > 3 || g.out_kind != OUT_F32) return false;
   if (g.lm < 7 || g.ln < 7 || g.lm > kMaxBits || g.ln > kMaxBits) return false;
+  if (g.lm + g.ln - 14 > 30) return false;  // tile ids in 31 bits; 32 tile bits per side at most
   if (g.kpad < (prec == 1 ? 4 : 5) || g.kpad > 8 || g.lk > g.kpad) return false;
   GemmArgs h = g;
   prepare_gemm_args(h, prec, kRT, kRT);
@@ -313,15 +342,16 @@ hipError_t launch_root_gemm(int prec, const GemmArgs &g_in, hipStream_t s) {
   if (!root_gemm_eligible(prec, g_in)) return hipErrorNotSupported;
   GemmArgs g = g_in;
   prepare_gemm_args(g, prec, kRT, kRT);
-  const uint64_t tilesM = (1ull << g.lm) / kRT, tilesN = (1ull << g.ln) / kRT;
-  const uint64_t ntiles = tilesM * tilesN;
+  // both tile counts are powers of two; tile t is (t >> lgtn, t & (2^lgtn - 1))
+  const int lgtn = g.ln - 7;
+  const uint32_t ntiles = 1u << (g.lm - 7 + lgtn);
   const int cus = cu_count();
   if (cus <= 0) return hipErrorNoDevice;
-  const int grid = (uint64_t)cus < ntiles ? cus : (int)ntiles;
+  const int grid = (uint32_t)cus < ntiles ? cus : (int)ntiles;
   switch (prec) {
-    case 1: return launch_root_p<1>(g, ntiles, tilesN, grid, s);
-    case 2: return launch_root_p<2>(g, ntiles, tilesN, grid, s);
-    default: return launch_root_p<3>(g, ntiles, tilesN, grid, s);
+    case 1: return launch_root_p<1>(g, ntiles, lgtn, grid, s);
+    case 2: return launch_root_p<2>(g, ntiles, lgtn, grid, s);
+    default: return launch_root_p<3>(g, ntiles, lgtn, grid, s);
   }
 }
 
