@@ -3,18 +3,20 @@
 //
 // The last step of a reconstruction is a GEMM with a huge M x N (the output)
 // and a short K (4^c for the c cuts it closes), so its cost is storing the
-// output plus the MFMA work, and both must run at once.  One workgroup per CU
-// loops over 128 x 128 output tiles:
-//   * operand fragments are loaded from global memory straight into the MFMA
-//     register layout (no LDS), up to a whole tile ahead of their use;
-//   * the accumulators of tile t are written to a staged tile in LDS (two of
-//     them alternate), and the stores of tile t-1 to HBM are interleaved with
-//     the MFMAs of tile t, so the store stream never waits for the math;
-//   * one barrier per tile orders the staged buffers.
+// output plus the MFMA work, and both must run at once.  One workgroup of
+// eight waves per CU loops over 128 x 128 output tiles; the waves split the
+// work by role, one of each role per SIMD:
+//   * four MFMA waves load operand fragments from global memory straight into
+//     the MFMA register layout (no LDS), a fragment group ahead of their use,
+//     and write the accumulators of tile i to staged tile buffer i & 1 in LDS;
+//   * four store waves convert staged tile i - 1, store it to HBM in output
+//     order (float4 runs) and reduce its per-tile statistics;
+//   * one barrier per tile hands the buffers over.
+// So the MFMA pipe and the store stream run at the same time on every SIMD.
 // Tiles are split into eight contiguous ranges, one per XCD (workgroup ids
 // go round-robin over the XCDs); the workgroups of one XCD walk their range
-// in row-major tile order, so the tiles in flight on an XCD share their A
-// rows in its L2.  The arithmetic per accumulator is the same sequence as in
+// in groups of eight tile rows, column by column, so the tiles in flight on
+// an XCD share A and B blocks in its L2.  The arithmetic per accumulator is the same sequence as in
 // the general GEMM kernel, so results agree bit for bit.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -65,6 +67,16 @@ struct RootTraits<3> {
   using Frag = bf16x8;
 };
 
+// Workgroup barrier ordering LDS only.  __syncthreads() also waits for every
+// outstanding global store of the wave, which would drain the output store
+// stream at each tile; nothing here reads global memory written by another
+// wave of the kernel.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // OR of v over the 64 lanes of the wave (the result is wave-uniform)
 __device__ inline uint64_t wave_or(uint64_t v) {
 #pragma unroll
@@ -73,20 +85,19 @@ __device__ inline uint64_t wave_or(uint64_t v) {
 }
 
 template <int P, int KP, bool STATS>
-__global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint32_t ntiles, int lgtn) {
+__global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t ntiles, int lgtm, int lgtn) {
   using RT = RootTraits<P>;
   using Frag = typename RT::Frag;
   constexpr int KG = RT::KG, NP = RT::NP, ES = RT::ES;
   constexpr int NKG = KP / KG;
-  constexpr int RMAX = (P == 1) ? 4 : 2;
-  constexpr int R = NKG < RMAX ? NKG : RMAX;  // fragment groups in flight
+  constexpr int RMAX = (P == 3) ? 1 : 2;      // fragment groups in flight (256 VGPRs per lane)
+  constexpr int R = NKG < RMAX ? NKG : RMAX;
   static_assert(NKG >= 1 && NKG % R == 0, "k groups");
-  constexpr int FM = 4, FN = 4;  // 16 x 16 blocks per wave (64 x 64 sub-tile)
+  constexpr int FM = 4, FN = 4;  // 16 x 16 blocks per MFMA wave (64 x 64 sub-tile)
 
   __shared__ __attribute__((aligned(16))) char smem[kRootLds];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform role
 
   // this workgroup's tiles: XCD range [r0, r1), every nslots-th from slot
   const uint32_t G = gridDim.x, b = blockIdx.x;
@@ -97,206 +108,240 @@ __global__ void __launch_bounds__(256) root_gemm_kernel(GemmArgs g, uint32_t nti
   const uint32_t r1 = r0 + per < ntiles ? r0 + per : ntiles;
   const uint32_t mine = r1 > r0 + slot ? (r1 - r0 - slot + nslots - 1) / nslots : 0;
   if (mine == 0) return;  // whole workgroup, before any barrier
-  auto tile_at = [&](uint32_t i) { return r0 + slot + i * nslots; };
+  // walk order: groups of GM tile rows, column by column inside a group, so
+  // the tiles in flight on an XCD share GM A row-blocks (kept in its L2) and
+  // each B column-block is fetched once per group
   const uint32_t tnmask = (1u << lgtn) - 1;
-
-  const double scale = g.dscale ? *g.dscale : g.scale;
-  const char *Ap[3] = {(const char *)g.a0, (const char *)g.a1, (const char *)g.a2};
-  const char *Bp[3] = {(const char *)g.b0, (const char *)g.b1, (const char *)g.b2};
-
-  Frag fa[R][NP][FM], fb[R][NP][FN];
-  floatx4 acc[FM][FN];
-
-  // byte offsets of this lane's first A / B fragment row of a tile
-  auto a_off = [&](uint32_t tile) {
-    return ((uint64_t)(tile >> lgtn) * kRT + wm * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
-  };
-  auto b_off = [&](uint32_t tile) {
-    return ((uint64_t)(tile & tnmask) * kRT + wn * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
-  };
-  auto load_group = [&](uint64_t ao, uint64_t bo, int kg, int q) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-        fa[q][p][i] = *(const Frag *)(Ap[p] + ao + (uint64_t)(i * 16 * KP + kg * KG) * ES);
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-        fb[q][p][j] = *(const Frag *)(Bp[p] + bo + (uint64_t)(j * 16 * KP + kg * KG) * ES);
-    }
+  const int lgm = lgtm < 3 ? lgtm : 3;
+  auto tile_at = [&](uint32_t i) {
+    const uint32_t idx = r0 + slot + i * nslots;
+    const uint32_t grp = idx >> (lgm + lgtn), r = idx & ((1u << (lgm + lgtn)) - 1);
+    const uint32_t tm = (grp << lgm) | (r & ((1u << lgm) - 1)), tn = r >> lgm;
+    return (tm << lgtn) | tn;
   };
 
-  // tile-local row / column -> compact (output-ordered) tile index
-  uint32_t tcol[FN], trow[FM][4];
+  if (wave < 4) {
+    // ---------------- MFMA waves: tile i into staged buffer i & 1
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    const char *Ap[3] = {(const char *)g.a0, (const char *)g.a1, (const char *)g.a2};
+    const char *Bp[3] = {(const char *)g.b0, (const char *)g.b1, (const char *)g.b2};
+    // A row-blocks repeat along a walk (the same tile row for many tiles):
+    // when they fit, all k groups of A stay in registers and only B streams
+    constexpr bool HOLD_A = (P != 3) && (NKG * NP * FM * 4 <= 64);
+    constexpr int NA = HOLD_A ? NKG : R;
+    Frag fa[NA][NP][FM], fb[R][NP][FN];
+    floatx4 acc[FM][FN];
+    auto a_off = [&](uint32_t tile) {
+      return ((uint64_t)(tile >> lgtn) * kRT + wm * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+    };
+    auto b_off = [&](uint32_t tile) {
+      return ((uint64_t)(tile & tnmask) * kRT + wn * 64 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+    };
+    auto load_a = [&](uint64_t ao, int kg, int q) {
 #pragma unroll
-  for (int j = 0; j < FN; ++j) tcol[j] = (uint32_t)deposit_c<7>(wn * 64 + j * 16 + lr, g.rankN, 7);
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      trow[i][r] = (uint32_t)deposit_c<7>(wm * 64 + i * 16 + 4 * lg + r, g.rankM, 7);
-  // compact index x = c * 1024 + tid * 4 + e lands at base + lo + hi(c) + e
-  const uint64_t lo = deposit_c<10>((uint64_t)tid * 4, g.lpos, 10);
-
-  double st_sum = 0.0;
-  uint32_t st_k32 = 0;
-
-  auto mfma_group = [&](int q) {
-    if constexpr (P == 1) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int i = 0; i < FM; ++i)
+          fa[q][p][i] = *(const Frag *)(Ap[p] + ao + (uint64_t)(i * 16 * KP + kg * KG) * ES);
+    };
+    auto load_b = [&](uint64_t bo, int kg, int q) {
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
-    } else {
-      // products smallest first, the same order per accumulator as the
-      // general kernel; all 16 accumulators between dependent MFMAs
-      constexpr int NPR = (P == 3) ? 6 : 3;
-      constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
-      constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int pr = 0; pr < NPR; ++pr) {
-        const int x = (P == 3) ? pa3[pr] : pa2[pr];
-        const int y = (P == 3) ? pb3[pr] : pb2[pr];
+        for (int j = 0; j < FN; ++j)
+          fb[q][p][j] = *(const Frag *)(Bp[p] + bo + (uint64_t)(j * 16 * KP + kg * KG) * ES);
+    };
+    auto mfma_group = [&](int qa, int q) {
+      if constexpr (P == 1) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q][x][i], fb[q][y][j], acc[i][j], 0, 0, 0);
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[qa][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
+      } else {
+        // products smallest first, the same order per accumulator as the
+        // general kernel; all 16 accumulators between dependent MFMAs
+        constexpr int NPR = (P == 3) ? 6 : 3;
+        constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
+        constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
+#pragma unroll
+        for (int pr = 0; pr < NPR; ++pr) {
+          const int x = (P == 3) ? pa3[pr] : pa2[pr];
+          const int y = (P == 3) ? pb3[pr] : pb2[pr];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[qa][x][i], fb[q][y][j], acc[i][j], 0, 0, 0);
+        }
+      }
+    };
+    // tile-local row / column -> swizzled compact (output-ordered) index
+    // (the swizzle is XOR-linear and row / column bits are disjoint, so the
+    // swizzled index is the XOR of a row part and a column part)
+    uint32_t tcol[FN], trow[FM][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) tcol[j] = 4 * ct_swz((uint32_t)deposit_c<7>(wn * 64 + j * 16 + lr, g.rankN, 7));
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        trow[i][r] = 4 * ct_swz((uint32_t)deposit_c<7>(wm * 64 + i * 16 + 4 * lg + r, g.rankM, 7));
+    {
+      const uint64_t bo = b_off(tile_at(0));
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if constexpr (!HOLD_A) load_a(a_off(tile_at(0)), q, q);
+        load_b(bo, q, q);
       }
     }
-  };
-
-  auto stream_chunk = [&](const char *ct, uint64_t base, int c) {
-    const uint32_t x = (uint32_t)c * 1024u + (uint32_t)tid * 4u;
-    const floatx4 v = *(const floatx4 *)(ct + 4 * ct_swz(x));
-    const uint64_t addr = base + lo + deposit_c<4, 10>((uint64_t)c, g.lpos, 4);
-    floatx4 w;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) w[e] = (float)((double)v[e] * scale);
-    *(floatx4 *)((float *)g.c0 + addr) = w;
-    if constexpr (STATS) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        st_sum += (double)w[e];
-        const uint32_t u = __float_as_uint(w[e]);
-        const uint32_t k = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
-        st_k32 = k > st_k32 ? k : st_k32;
-      }
-    }
-  };
-
-  // output offset of a tile's first entry: the tile-row bits (M bits >= 7)
-  // and tile-column bits deposit to their output positions; lane l handles
-  // bit 7 + l of each, then the wave ORs them together
-  const int pm = 7 + lane < g.lm ? g.posM[7 + lane] : 0;
-  const int pn = 7 + lane < g.ln ? g.posN[7 + lane] : 0;
-  const bool hm = 7 + lane < g.lm, hn = 7 + lane < g.ln;
-  auto tile_base = [&](uint32_t tile) {
-    const uint32_t tm = tile >> lgtn, tn = tile & tnmask;
-    uint64_t v = 0;
-    if (hm && lane < 32 && ((tm >> lane) & 1u)) v |= 1ull << pm;
-    if (hn && lane < 32 && ((tn >> lane) & 1u)) v |= 1ull << pn;
-    return wave_or(v);
-  };
-
-  // One pass: MFMAs of tile `cur` (prefetching ahead, the last groups for
-  // tile `next`) interleaved with the stores of the staged tile `prev`
-  // (output offset pbase).
-  auto body = [&](auto MF, auto ST, uint32_t cur, uint32_t next, uint32_t prev, uint64_t pbase, int par) {
-    constexpr bool DO_MF = decltype(MF)::value, DO_ST = decltype(ST)::value;
-    char *ct_cur = smem + par * kCtBytes;
-    const char *ct_prev = smem + (par ^ 1) * kCtBytes;
-    uint64_t ca = 0, cb = 0, na = 0, nb = 0;
-    if constexpr (DO_MF) {
-      ca = a_off(cur);
-      cb = b_off(cur);
-      na = a_off(next);
-      nb = b_off(next);
+    // one tile: MFMAs of `cur` while the next fragment groups (the last ones
+    // for tile `next`) load, then its accumulators to staged buffer `it & 1`
+    auto tile_step = [&](uint32_t it) {
+      const uint32_t cur = tile_at(it), next = tile_at(it + 1 < mine ? it + 1 : it);
+      const uint64_t ca = a_off(cur), cb = b_off(cur), na = a_off(next), nb = b_off(next);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-    }
 #pragma unroll
-    for (int kg = 0; kg < NKG; ++kg) {
-      if constexpr (DO_MF) {
+      for (int kg = 0; kg < NKG; ++kg) {
         const int q = kg % R;
-        mfma_group(q);
-        if (kg + R < NKG) load_group(ca, cb, kg + R, q);
-        else load_group(na, nb, kg + R - NKG, q);
+        mfma_group(HOLD_A ? kg : q, q);
+        if (kg + R < NKG) {
+          if constexpr (!HOLD_A) load_a(ca, kg + R, q);
+          load_b(cb, kg + R, q);
+        } else {
+          if constexpr (!HOLD_A) load_a(na, kg + R - NKG, q);
+          load_b(nb, kg + R - NKG, q);
+        }
+        // keep the prefetch here: the scheduler would otherwise sink the
+        // loads next to their use and expose their latency
+        __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (DO_ST) {
-#pragma unroll
-        for (int c = kg * 16 / NKG; c < (kg + 1) * 16 / NKG; ++c) stream_chunk(ct_prev, pbase, c);
-      }
-    }
-    if constexpr (DO_ST && STATS) {
-      double s = st_sum;
-      uint32_t k = st_k32;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        s += __shfl_xor(s, off);
-        const uint32_t o = __shfl_xor(k, off);
-        k = o > k ? o : k;
-      }
-      if (lane == 0) {
-        double *rs = (double *)(smem + kStatOff + (par ^ 1) * 64);
-        uint32_t *rk = (uint32_t *)(smem + kStatOff + 128 + (par ^ 1) * 64);
-        rs[wave] = s;
-        rk[wave] = k;
-      }
-      st_sum = 0.0;
-      st_k32 = 0;
-    }
-    if constexpr (DO_MF) {
+      char *ct = smem + (it & 1) * kCtBytes;
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            *(float *)(ct_cur + 4 * ct_swz(trow[i][r] | tcol[j])) = acc[i][j][r];
-    }
-    __syncthreads();
-    if constexpr (DO_ST && STATS) {
-      if (tid == 0) {
-        const double *rs = (const double *)(smem + kStatOff + (par ^ 1) * 64);
-        const uint32_t *rk = (const uint32_t *)(smem + kStatOff + 128 + (par ^ 1) * 64);
-        const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
-        uint32_t k = rk[0];
-        for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
-        g.tsum[prev] = t;
-        g.tkey[prev] = k;
-      }
-    }
-  };
-
-  using T1 = std::true_type;
-  using F0 = std::false_type;
-  {
-    const uint64_t ao = a_off(tile_at(0)), bo = b_off(tile_at(0));
+            *(float *)(ct + (trow[i][r] ^ tcol[j])) = acc[i][j][r];
+      lds_barrier();
+    };
+    if constexpr (HOLD_A) {
+      // runs of consecutive tiles in one tile row: A loaded once per run,
+      // outside the inner loop, so the inner loop has no conditional loads
+      uint32_t it = 0;
+      while (it < mine) {
+        const uint32_t tm_run = tile_at(it) >> lgtn;
+        const uint64_t ao = a_off(tile_at(it));
 #pragma unroll
-    for (int q = 0; q < R; ++q) load_group(ao, bo, q, q);
+        for (int q = 0; q < NA; ++q) load_a(ao, q, q);
+        do {
+          tile_step(it);
+          ++it;
+        } while (it < mine && (tile_at(it) >> lgtn) == tm_run);
+      }
+    } else {
+      for (uint32_t it = 0; it < mine; ++it) tile_step(it);
+    }
+    lds_barrier();
+  } else {
+    // ---------------- store waves: staged tile i - 1 to the output
+    const int et = tid - 256, ew = wave - 4;
+    // the output scale is a power of two (2^-K times the operand exponents):
+    // ldexp rounds once, like the float64 product rounded to float32
+    const int sexp = ilogb(g.dscale ? *g.dscale : g.scale);
+    // compact index x = c * 1024 + et * 4 + e lands at base + lo + hi(c) + e
+    const uint64_t lo = deposit_c<10>((uint64_t)et * 4, g.lpos, 10);
+    const uint32_t xlo = 4 * ct_swz((uint32_t)et * 4u);
+    // output offset of a tile's first entry: lane l deposits bit 7 + l of
+    // the tile row and of the tile column, then the wave ORs them together
+    const int pm = 7 + lane < g.lm ? g.posM[7 + lane] : 0;
+    const int pn = 7 + lane < g.ln ? g.posN[7 + lane] : 0;
+    const bool hm = 7 + lane < g.lm, hn = 7 + lane < g.ln;
+    auto tile_base = [&](uint32_t tile) {
+      const uint32_t tm = tile >> lgtn, tn = tile & tnmask;
+      uint64_t v = 0;
+      if (hm && lane < 32 && ((tm >> lane) & 1u)) v |= 1ull << pm;
+      if (hn && lane < 32 && ((tn >> lane) & 1u)) v |= 1ull << pn;
+      return wave_or(v);
+    };
+    auto combine = [&](uint32_t tile, int par) {
+      const double *rs = (const double *)(smem + kStatOff + par * 64);
+      const uint32_t *rk = (const uint32_t *)(smem + kStatOff + 128 + par * 64);
+      const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
+      uint32_t k = rk[0];
+      for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
+      g.tsum[tile] = t;
+      g.tkey[tile] = k;
+    };
+    for (uint32_t it = 0; it <= mine; ++it) {
+      if constexpr (STATS) {
+        if (it >= 2 && et == 0) combine(tile_at(it - 2), (it - 2) & 1);
+      }
+      if (it >= 1) {
+        const uint32_t prev = tile_at(it - 1);
+        const uint64_t base = tile_base(prev);
+        const char *ct = smem + ((it - 1) & 1) * kCtBytes;
+        double st_sum = 0.0;
+        int32_t st_hi = INT32_MIN, st_lo = INT32_MAX;  // signed max / min of the float bits
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const floatx4 v = *(const floatx4 *)(ct + (xlo ^ (4 * ct_swz((uint32_t)c * 1024u))));
+          const uint64_t addr = base + lo + deposit_c<4, 10>((uint64_t)c, g.lpos, 4);
+          floatx4 w;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[e] = __builtin_amdgcn_ldexpf(v[e], sexp);
+          // streaming store: the output is not read again by this kernel,
+          // and keeping it out of L2 keeps the operand blocks resident
+          __builtin_nontemporal_store(w, (floatx4 *)((float *)g.c0 + addr));
+          if constexpr (STATS) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              st_sum += (double)w[e];
+              const int32_t u = (int32_t)__float_as_uint(w[e]);
+              st_hi = u > st_hi ? u : st_hi;
+              st_lo = u < st_lo ? u : st_lo;
+            }
+          }
+        }
+        if constexpr (STATS) {
+          // largest value: the largest non-negative pattern if there is one
+          // (non-negative floats order like their signed bits), else the
+          // negative pattern with the smallest signed bits; as a top-k key
+          uint32_t st_k32 = st_hi >= 0 ? ((uint32_t)st_hi | 0x80000000u) : ~(uint32_t)st_lo;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            st_sum += __shfl_xor(st_sum, off);
+            const uint32_t o = __shfl_xor(st_k32, off);
+            st_k32 = o > st_k32 ? o : st_k32;
+          }
+          if (lane == 0) {
+            ((double *)(smem + kStatOff + ((it - 1) & 1) * 64))[ew] = st_sum;
+            ((uint32_t *)(smem + kStatOff + 128 + ((it - 1) & 1) * 64))[ew] = st_k32;
+          }
+        }
+      }
+      lds_barrier();
+    }
+    if constexpr (STATS) {
+      if (et == 0) combine(tile_at(mine - 1), (mine - 1) & 1);
+    }
   }
-  uint64_t base = tile_base(tile_at(0));
-  body(T1{}, F0{}, tile_at(0), tile_at(mine > 1 ? 1 : 0), 0, 0, 0);
-  for (uint32_t i = 1; i < mine; ++i) {
-    const uint64_t nbase = tile_base(tile_at(i));
-    body(T1{}, T1{}, tile_at(i), tile_at(i + 1 < mine ? i + 1 : i), tile_at(i - 1), base, (int)(i & 1));
-    base = nbase;
-  }
-  body(F0{}, T1{}, 0, 0, tile_at(mine - 1), base, (int)(mine & 1));
 }
 
 template <int P, int KP>
 hipError_t launch_root_kp(const GemmArgs &g, uint32_t ntiles, int lgtn, int grid, hipStream_t s) {
+  const int lgtm = g.lm - 7;
   if (g.tkey)
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true>), dim3(grid), dim3(256), 0, s, g, ntiles, lgtn);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn);
   else
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false>), dim3(grid), dim3(256), 0, s, g, ntiles, lgtn);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn);
   return hipGetLastError();
 }
 
