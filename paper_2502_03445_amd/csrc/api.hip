@@ -426,8 +426,12 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
   const int m = net.m;
   const int pc = int(p->prec);
   if (tm) tm->begin(0);
-  for (auto &t : net.t)
-    if (t.basis == TQC_BASIS_RAW) transform_tensor(t, t.dev_pauli, s);
+  {
+    std::vector<TransformArgs> ta;
+    for (auto &t : net.t)
+      if (t.basis == TQC_BASIS_RAW) ta.push_back(make_transform_args(t, t.dev_pauli));
+    if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
+  }
   if (tm) tm->end();
   if (m == 1) {
     // a single tensor: its (fixed-qubit) slice is the output
@@ -550,6 +554,7 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
   char *tscratch = (char *)p->stats_buf + tbytes;
   run_slices(p, out, dtype == 0 ? OUT_F64 : OUT_F32, 0, 1, false, s, tm, tkey, tsum);
   GemmArgs g = make_gemm_args(p, *root, out, dtype == 0 ? OUT_F64 : OUT_F32);
+  prepare_gemm_args(g, int(p->prec), bm, bm);  // compact tile order for the gather
   if (tm) tm->begin(fin_phase);
   HIP_OK(launch_sum_tiles(tsum, ntiles, (double *)(tscratch - 256 * 8), total, s));
   if (k > 0)

@@ -36,38 +36,41 @@ __device__ inline double down_coef(int s, int o) {
   return o == 0 ? 2.0 : -1.0;
 }
 
+// The options of all cuts are enumerated like an odometer (last cut
+// fastest); the option digits are packed two bits per cut in a register.
 __device__ inline void transform_elem(const TransformArgs &a, uint64_t e) {
   const uint64_t cols = 1ull << (a.o + a.u);
   const uint64_t x = e & ((1ull << a.o) - 1);
-  const uint64_t row = e >> a.o;
-  int sig[kMaxCutsT], nopt[kMaxCutsT], opt[kMaxCutsT];
-  for (int t = 0; t < a.c; ++t) {
-    sig[t] = (int)((row >> (2 * (a.c - 1 - t))) & 3);
-    nopt[t] = a.up[t] ? 2 : down_opts(sig[t]);
-    opt[t] = 0;
-  }
+  const uint64_t row = e >> a.o;  // Pauli digit of cut t at bits 2 (c - 1 - t)
+  uint32_t opt = 0;               // option of cut t at bits 2 t
   double sum = 0.0;
   while (true) {
     double coef = 1.0;
     uint64_t rin = 0, b = 0;
     for (int t = 0; t < a.c; ++t) {
-      const int s = sig[t];
+      const int s = (int)((row >> (2 * (a.c - 1 - t))) & 3);
+      const int o = (int)((opt >> (2 * t)) & 3u);
       if (a.up[t]) {
         const int meas = (s == 3) ? 0 : s;  // I and Z share the Z-basis run
-        const int bit = opt[t];
-        if (s != 0 && bit) coef = -coef;
+        if (s != 0 && o) coef = -coef;
         rin += (uint64_t)meas * a.w[t];
-        b |= (uint64_t)bit << a.bbit[t];
+        b |= (uint64_t)o << a.bbit[t];
       } else {
-        coef *= down_coef(s, opt[t]);
-        rin += (uint64_t)down_prep(s, opt[t]) * a.w[t];
+        coef *= down_coef(s, o);
+        rin += (uint64_t)down_prep(s, o) * a.w[t];
       }
     }
     sum += coef * a.raw[rin * cols + ((x << a.u) | b)];
     int t = a.c - 1;
-    while (t >= 0 && ++opt[t] == nopt[t]) {
-      opt[t] = 0;
-      --t;
+    for (; t >= 0; --t) {
+      const int s = (int)((row >> (2 * (a.c - 1 - t))) & 3);
+      const uint32_t n = a.up[t] ? 2u : (uint32_t)down_opts(s);
+      const uint32_t o = ((opt >> (2 * t)) & 3u) + 1u;
+      opt &= ~(3u << (2 * t));
+      if (o < n) {
+        opt |= o << (2 * t);
+        break;
+      }
     }
     if (t < 0) break;
   }

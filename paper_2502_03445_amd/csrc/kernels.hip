@@ -15,6 +15,18 @@ __global__ void __launch_bounds__(256) transform_kernel(TransformArgs a) {
     transform_elem(a, e);
 }
 
+// several tensors per launch (blockIdx.y selects the tensor)
+struct TransformBatch {
+  TransformArgs a[4];
+};
+__global__ void __launch_bounds__(256) transform_multi_kernel(TransformBatch tb) {
+  const TransformArgs &a = tb.a[blockIdx.y];
+  const uint64_t total = (1ull << (2 * a.c)) << a.o;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    transform_elem(a, e);
+}
+
 __global__ void __launch_bounds__(256) pack_kernel(PackArgs a) {
   const uint64_t total = 1ull << a.nbits;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
@@ -82,6 +94,21 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u) {
 hipError_t launch_transform(const TransformArgs &a, hipStream_t s) {
   const uint64_t total = (1ull << (2 * a.c)) << a.o;
   hipLaunchKernelGGL(transform_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transforms(const TransformArgs *args, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    TransformBatch tb{};
+    const int cnt = n - i0 < 4 ? n - i0 : 4;
+    uint64_t most = 1;
+    for (int i = 0; i < cnt; ++i) {
+      tb.a[i] = args[i0 + i];
+      const uint64_t total = (1ull << (2 * args[i0 + i].c)) << args[i0 + i].o;
+      most = total > most ? total : most;
+    }
+    hipLaunchKernelGGL(transform_multi_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, tb);
+  }
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 namespace tqc {
 
 hipError_t launch_transform(const TransformArgs &a, hipStream_t s);
+hipError_t launch_transforms(const TransformArgs *args, int n, hipStream_t s);  // n tensors
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s);
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);

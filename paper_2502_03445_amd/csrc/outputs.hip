@@ -489,6 +489,34 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
   const uint64_t tau0 = sel->prefix;
   const uint64_t nq = fast->nq < (unsigned long long)kMaxK ? fast->nq : (unsigned long long)kMaxK;
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  if (g.vec4 && g.ncompact == lbm + lbn && dtype == 1) {
+    // full tile whose two lowest output bits are tile bits: compact index x
+    // (tile entries in output order) lands at base + deposit(x, lpos), and
+    // x, x+1, x+2, x+3 are adjacent in the output
+    const uint32_t runs4 = (1u << (lbm + lbn)) / 1024u;
+    for (uint64_t w = blockIdx.x; w < nq * runs4; w += gridDim.x) {
+      const uint64_t t = qlist[w / runs4];
+      const uint32_t x = (uint32_t)(w % runs4) * 1024u + threadIdx.x * 4u;
+      const uint64_t tm = t / tilesN, tn = t % tilesN;
+      const uint64_t base = scatter_bits(tm << lbm, g.posM, g.lm) + scatter_bits(tn << lbn, g.posN, g.ln);
+      const uint64_t i0 = base + deposit_c<16>((uint64_t)x, g.lpos, lbm + lbn);
+      const float4 v = *(const float4 *)((const float *)p + i0);
+      const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t u = __float_as_uint(e[q]);
+        const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+        if (key >= tau0) {
+          const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
+          if (slot < (unsigned long long)kMaxK) {
+            cand_key[slot] = key;
+            cand_idx[slot] = i0 + q;
+          }
+        }
+      }
+    }
+    return;
+  }
   const uint32_t runs = (1u << (lbm + lbn)) / 256u;  // tiles hold >= 1024 entries
   for (uint64_t w = blockIdx.x; w < nq * runs; w += gridDim.x) {
     const uint64_t t = qlist[w / runs];
@@ -539,12 +567,14 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
     exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, nullptr, s);
     return hipGetLastError();
   }
+  // float32 keys occupy the low 32 bits
+  const int tbits = dtype == 1 ? 32 : 64;
   hipLaunchKernelGGL(topk_fast_init, dim3(1), dim3(64), 0, s, fast);
-  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, sel, hist, 64, k, (const unsigned int *)nullptr);
+  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, sel, hist, tbits, k, (const unsigned int *)nullptr);
   uint64_t hb = (ntiles + 255) / 256;
   if (hb > 8192) hb = 8192;
-  for (int resolved = 0; resolved < 64;) {
-    const int bits = (64 - resolved) < kDigitBits ? (64 - resolved) : kDigitBits;
+  for (int resolved = 0; resolved < tbits;) {
+    const int bits = (tbits - resolved) < kDigitBits ? (tbits - resolved) : kDigitBits;
     hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb), dim3(256), 0, s, (const void *)tkey, 2, ntiles, sel,
                        hist, bits, (const unsigned int *)nullptr);
     hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, sel, hist, bits, (const unsigned int *)nullptr);
