@@ -329,3 +329,38 @@ def test_final_step_kernel(case, form):
     ref = oracle_full(spec)
     ok, e = tol_ok(form, a.double().cpu().numpy(), ref)
     assert ok, (case, form, e)
+
+
+# --------------------------------------------- precision study (2^30 slice)
+def test_precision_network_slice_full_size():
+    """6 synthetic tensors, 18 cuts, 34 qubits, 4 fixed: the 2^30 slice in
+    every form.  float64 against the oracle on sampled and top entries; the
+    reduced forms against the float64 result over all 2^30 entries."""
+    spec = synthetic.precision_network()
+    fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+    N = tqc.Network.from_spec(spec)
+    P64 = tqc.Plan(N, precision="fp64", out_dtype="f64", fixed=fixed)
+    ref = P64.execute()
+    torch.cuda.synchronize()
+    del P64
+    free = [q for q in range(spec.n) if q not in fixed]
+    rng = np.random.default_rng(33)
+    top = torch.topk(ref.abs(), 20).indices.cpu().numpy().astype(np.uint64)
+    local = np.concatenate([rng.integers(0, 1 << len(free), size=300, dtype=np.uint64), top])
+    full = np.zeros(len(local), dtype=np.uint64)
+    for i, q in enumerate(free):
+        full |= ((local >> np.uint64(i)) & np.uint64(1)) << np.uint64(q)
+    for q, v in fixed.items():
+        full |= np.uint64(v) << np.uint64(q)
+    want = entries_variable_elimination(spec, full)
+    got = ref[torch.from_numpy(local.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12, np.abs(got - want).max()
+    scale = ref.abs().max().item()
+    bounds = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5}
+    for form, bound in bounds.items():
+        P = tqc.Plan(N, precision=form, out_dtype="f32", fixed=fixed)
+        out = P.execute()
+        err = (out.double() - ref).abs().max().item() / scale
+        del out, P
+        torch.cuda.empty_cache()
+        assert err <= bound, (form, err)
