@@ -88,6 +88,111 @@ def measured_traffic(form):
     return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
 
 
+def _median_ms(plan, out, reps=7):
+    """Median device time of one execute (sum of its HIP-event phases)."""
+    plan.execute_profiled(out)
+    return float(np.median([sum(plan.execute_profiled(out)[1]) for _ in range(reps)]))
+
+
+def precision_study(tqc, torch):
+    """18-cut synthetic network, 34 qubits, 4 fixed (a 2^30 slice): device time
+    and max error of every form against the float64 form over all 2^30
+    entries (the float64 form itself is checked against the oracle in the GPU
+    tests)."""
+    from workloads import synthetic
+    spec = synthetic.precision_network()
+    fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+    net = tqc.Network.from_spec(spec)
+    res, ref = {}, None
+    for form in ("fp64", "fp32", "bf16x6", "bf16x3"):
+        plan = tqc.Plan(net, precision=form, out_dtype="f64" if form == "fp64" else "f32", fixed=fixed)
+        out = plan.output_tensor()
+        ms = _median_ms(plan, out)
+        if ref is None:
+            ref, err = out, 0.0
+        else:
+            err = (out.double() - ref).abs().max().item() / ref.abs().max().item()
+        res[form] = {"ms": ms, "rel_err_vs_fp64": err, "tflops": plan.stats["flops"] / ms / 1e9,
+                     "steps": [(st["log2_m"], st["log2_n"], st["log2_k"]) for st in plan.steps]}
+        del plan
+        torch.cuda.empty_cache()
+    return {"study": "precision", "workload": spec.meta["name"], "entries": 1 << 30, "forms": res}
+
+
+def _random_order(rng, spec, fixed, temperature=2.0):
+    """A randomized greedy contraction order: among pairs of nodes sharing a
+    cut, pick the one whose result has the fewest index bits plus Gumbel noise
+    (node ids grow as in the plan API: the result of step s is node m + s)."""
+    m = len(spec.tensors)
+    cuts = {i: set(t.cut_ids) for i, t in enumerate(spec.tensors)}
+    outs = {i: sum(1 for q in t.outputs if q not in fixed) for i, t in enumerate(spec.tensors)}
+    order, nid = [], m
+    while len(cuts) > 1:
+        best, pick = None, None
+        for a in cuts:
+            for b in cuts:
+                if a < b and cuts[a] & cuts[b]:
+                    bits = 2 * len(cuts[a] ^ cuts[b]) + outs[a] + outs[b]
+                    score = bits + temperature * rng.gumbel()
+                    if best is None or score < best:
+                        best, pick = score, (a, b)
+        a, b = pick
+        order.append((a, b))
+        cuts[nid] = cuts.pop(a) ^ cuts.pop(b)
+        outs[nid] = outs.pop(a) + outs.pop(b)
+        nid += 1
+    return order
+
+
+def costmodel_study(tqc, torch):
+    """Learned cost model A/B on the 12-patch grid network (2^24 free entries):
+    train the MLP on per-step device times of random contraction orders of
+    five other seeds of the same workload family, then plan seed 0 with the
+    float64-roofline model (exact dynamic programming over subsets) and with
+    the MLP ranking 2000 randomized candidates; report both measured times."""
+    from workloads import synthetic
+    rng = np.random.default_rng(7)
+    feats, secs = [], []
+    for seed in range(1, 6):
+        spec = synthetic.grid_patch_network(seed=seed)
+        fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+        net = tqc.Network.from_spec(spec)
+        for _ in range(24):
+            order = _random_order(rng, spec, fixed)
+            plan = tqc.Plan(net, precision="fp32", out_dtype="f64", fixed=fixed, order=order)
+            if plan.stats["workspace_bytes"] > (64 << 30):
+                continue
+            out = plan.output_tensor()
+            plan.execute_profiled(out)
+            _, ph = plan.execute_profiled(out)
+            f = tqc.step_features(plan)
+            for i, row in enumerate(f):
+                feats.append(row)
+                secs.append(max(ph[2 + i], 1e-4) * 1e-3)
+            del plan, out
+    model = tqc.CostModel(seed=11)
+    losses = model.train(np.array(feats), np.array(secs), epochs=80, batch=64, lr=2e-3)
+    spec = synthetic.grid_patch_network(seed=0)
+    fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+    net = tqc.Network.from_spec(spec)
+    res = {}
+    for name, kw in (("roofline_dp", dict(cost="flopbyte")),
+                     ("mlp_2000", dict(cost="mlp", cost_model=model, num_candidates=2000, seed=3))):
+        plan = tqc.Plan(net, precision="fp32", out_dtype="f64", fixed=fixed, **kw)
+        out = plan.output_tensor()
+        res[name] = {"ms": _median_ms(plan, out, 15), "predicted_ms": plan.stats["predicted_seconds"] * 1e3,
+                     "plan_ms": plan.stats["plan_seconds"] * 1e3, "flops": plan.stats["flops"],
+                     "bytes": plan.stats["bytes"]}
+        if name == "roofline_dp":
+            ref = out.clone()
+        else:
+            res[name]["max_abs_diff_vs_dp"] = (out - ref).abs().max().item()
+        del plan
+    return {"study": "costmodel", "workload": spec.meta["name"], "train_rows": len(secs),
+            "train_loss_first_last": [float(losses[0]), float(losses[-1])], "plans": res,
+            "speedup_mlp_over_dp": res["roofline_dp"]["ms"] / res["mlp_2000"]["ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +201,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--study", choices=["precision", "costmodel"], default=None,
+                    help="instead of the benchmark line: the precision study of the 18-cut "
+                         "synthetic network (2^30 slice) or the cost-model A/B on the 12-patch grid")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -110,6 +218,13 @@ def main():
     import torch
     import paper_2502_03445_amd as tqc
     from workloads import qaoa
+
+    if args.study == "precision":
+        print(json.dumps(precision_study(tqc, torch)))
+        return
+    if args.study == "costmodel":
+        print(json.dumps(costmodel_study(tqc, torch)))
+        return
 
     spec = qaoa.qaoa_network()
     net = tqc.Network.from_spec(spec)
