@@ -1157,8 +1157,12 @@ static void costmodel_predict(CostModel *m, const float *feats, int64_t n, doubl
 // Rank candidate orders with the model; returns the best order.
 static std::vector<int> mlp_choose_order(Network *net, Prec prec, tqc_dtype out, const std::vector<int> &sliced,
                                          const std::vector<int> &fixed_q, CostModel *m, int count,
-                                         uint64_t seed, double *best_score, hipStream_t s) {
+                                         uint64_t seed, double *best_score, hipStream_t s,
+                                         const std::vector<int> *roofline_order = nullptr) {
   auto orders = sample_orders(net, prec, out, sliced, fixed_q, std::max(2, count), seed);
+  // the roofline planner's own order competes too: the model only replaces
+  // it where it predicts a faster one
+  if (roofline_order && !roofline_order->empty()) orders.insert(orders.begin(), *roofline_order);
   const uint64_t slices = 1ull << (2 * sliced.size());
   std::vector<float> F;
   std::vector<double> mult;
@@ -1239,10 +1243,15 @@ tqc_status tqc_plan_create(tqc_network_t net, const tqc_plan_options *opt, tqc_p
       o1.cost_kind = TQC_COST_FLOPBYTE;
       std::unique_ptr<Plan> p0(build_plan(reinterpret_cast<Network *>(net), o1));
       double score = 0;
+      std::vector<int> p0_order;
+      for (const Step &st : p0->steps) {
+        p0_order.push_back(st.a);
+        p0_order.push_back(st.b);
+      }
       std::vector<int> order = mlp_choose_order(
           reinterpret_cast<Network *>(net), p0->prec, p0->out_dtype, p0->sliced, p0->fixed_q,
           reinterpret_cast<CostModel *>(opt->cost_model),
-          opt->num_candidates > 0 ? opt->num_candidates : 1000, opt->seed, &score, nullptr);
+          opt->num_candidates > 0 ? opt->num_candidates : 1000, opt->seed, &score, nullptr, &p0_order);
       tqc_plan_options o2 = o1;
       o2.num_order_steps = (int32_t)order.size() / 2;
       o2.order = order.data();
