@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
     const char *Bp[3] = {(const char *)g.b0, (const char *)g.b1, (const char *)g.b2};
     // A row-blocks repeat along a walk (the same tile row for many tiles):
     // when they fit, all k groups of A stay in registers and only B streams
-    constexpr bool HOLD_A = (P != 3) && (NKG * NP * FM * 4 <= 64);
+    constexpr bool HOLD_A = NKG * NP * FM * 4 <= (P == 3 ? 96 : 64);
     constexpr int NA = HOLD_A ? NKG : R;
     Frag fa[NA][NP][FM], fb[R][NP][FN];
     floatx4 acc[FM][FN];
@@ -232,7 +232,118 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
             *(float *)(ct + (trow[i][r] ^ tcol[j])) = acc[i][j][r];
       lds_barrier();
     };
-    if constexpr (HOLD_A) {
+    if constexpr (HOLD_A && P >= 2) {
+      // Half-tile pipeline: unit u = (tile u / 2, column half u % 2).  The
+      // MFMAs of unit u run while the accumulators of unit u - 1 go to the
+      // staged tile, so the staging writes overlap the math; the barrier that
+      // hands a tile to the store waves follows the write of its second half.
+      constexpr int FH = FN / 2;
+      Frag fbh[R][NP][FH];
+      floatx4 ah[2][FM][FH];
+      const uint32_t nunits = 2 * mine;
+      auto bh_off = [&](uint32_t u) {
+        const uint32_t tile = tile_at(u >> 1);
+        return ((uint64_t)(tile & tnmask) * kRT + wn * 64 + (u & 1) * 32 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+      };
+      auto load_bh = [&](uint64_t bo, int kg, int q) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int j = 0; j < FH; ++j)
+            fbh[q][p][j] = *(const Frag *)(Bp[p] + bo + (uint64_t)(j * 16 * KP + kg * KG) * ES);
+      };
+      auto mfma_half = [&](int sa, int kg, int q) {
+        if constexpr (P == 1) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+              for (int j = 0; j < FH; ++j)
+                ah[sa][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[kg][0][i][t], fbh[q][0][j][t], ah[sa][i][j], 0, 0, 0);
+        } else {
+          constexpr int NPR = (P == 3) ? 6 : 3;
+          constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
+          constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
+#pragma unroll
+          for (int pr = 0; pr < NPR; ++pr) {
+            const int x = (P == 3) ? pa3[pr] : pa2[pr];
+            const int y = (P == 3) ? pb3[pr] : pb2[pr];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+              for (int j = 0; j < FH; ++j)
+                ah[sa][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[kg][x][i], fbh[q][y][j], ah[sa][i][j], 0, 0, 0);
+          }
+        }
+      };
+      auto write_half = [&](uint32_t u, int sa) {
+        char *ct = smem + ((u >> 1) & 1) * kCtBytes;
+        const int h = (int)(u & 1);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < FH; ++j)
+              *(float *)(ct + (trow[i][r] ^ tcol[h * FH + j])) = ah[sa][i][j][r];
+      };
+      // compute unit u into ah[u & 1] (prefetching the next unit's B groups);
+      // with PREV, also stage unit u - 1 from ah[(u - 1) & 1]
+      auto unit_step = [&](auto PREV, auto SA, uint32_t u) {
+        constexpr bool WR = decltype(PREV)::value;
+        constexpr int sa = decltype(SA)::value;  // = u & 1, compile-time register set
+        const uint64_t cb = bh_off(u), nb = bh_off(u + 1 < nunits ? u + 1 : u);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FH; ++j) ah[sa][i][j] = floatx4{0, 0, 0, 0};
+#pragma unroll
+        for (int kg = 0; kg < NKG; ++kg) {
+          const int q = kg % R;
+          mfma_half(sa, kg, q);
+          if (kg + R < NKG) load_bh(cb, kg + R, q);
+          else load_bh(nb, kg + R - NKG, q);
+          if constexpr (WR) {
+            if (kg == 0) write_half(u - 1, sa ^ 1);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (WR && sa == 0) lds_barrier();  // unit u - 1 completed tile (u - 1) / 2
+      };
+      using T1h = std::true_type;
+      using F0h = std::false_type;
+      using S0 = std::integral_constant<int, 0>;
+      using S1 = std::integral_constant<int, 1>;
+      {
+        const uint64_t bo = bh_off(0);
+#pragma unroll
+        for (int q = 0; q < R; ++q) load_bh(bo, q, q);
+      }
+      // runs of units in one tile row: A loaded once per run, outside the
+      // inner loop, so the inner loop has no conditional loads
+      uint32_t it = 0;
+      while (it < mine) {
+        const uint32_t tm_run = tile_at(it) >> lgtn;
+        const uint64_t ao = a_off(tile_at(it));
+#pragma unroll
+        for (int q = 0; q < NA; ++q) load_a(ao, q, q);
+        if (it == 0) {
+          unit_step(F0h{}, S0{}, 0);
+          unit_step(T1h{}, S1{}, 1);
+          ++it;
+        }
+        while (it < mine && (tile_at(it) >> lgtn) == tm_run) {
+          unit_step(T1h{}, S0{}, 2 * it);
+          unit_step(T1h{}, S1{}, 2 * it + 1);
+          ++it;
+        }
+      }
+      write_half(nunits - 1, 1);
+      lds_barrier();
+    } else if constexpr (HOLD_A) {
+      // (float32 operands: the MFMA pipe is the bound and the whole-tile
+      // order measured faster than the half-tile pipeline)
       // runs of consecutive tiles in one tile row: A loaded once per run,
       // outside the inner loop, so the inner loop has no conditional loads
       uint32_t it = 0;
