@@ -182,14 +182,13 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
     // tile-local row / column -> swizzled compact (output-ordered) index
     // (the swizzle is XOR-linear and row / column bits are disjoint, so the
     // swizzled index is the XOR of a row part and a column part)
-    uint32_t tcol[FN], trow[FM][4];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) tcol[j] = 4 * ct_swz((uint32_t)deposit_c<7>(wn * 64 + j * 16 + lr, g.rankN, 7));
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        trow[i][r] = 4 * ct_swz((uint32_t)deposit_c<7>(wm * 64 + i * 16 + 4 * lg + r, g.rankM, 7));
+    // Deposits of disjoint bits add up, so the index splits further into a
+    // per-lane part (lane row / column bits) and wave-uniform parts per
+    // (i, r) and j, kept in scalar registers.
+    const uint32_t ctlane = 4 * ct_swz((uint32_t)deposit_c<7>(wm * 64 + 4 * lg, g.rankM, 7)) ^
+                            4 * ct_swz((uint32_t)deposit_c<7>(wn * 64 + lr, g.rankN, 7));
+    auto trow = [&](int i, int r) { return 4 * ct_swz((uint32_t)deposit_c<7>(i * 16 + r, g.rankM, 7)); };
+    auto tcol = [&](int j) { return 4 * ct_swz((uint32_t)deposit_c<7>(j * 16, g.rankN, 7)); };
     {
       const uint64_t bo = b_off(tile_at(0));
 #pragma unroll
@@ -229,28 +228,39 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            *(float *)(ct + (trow[i][r] ^ tcol[j])) = acc[i][j][r];
+            *(float *)(ct + (ctlane ^ trow(i, r) ^ tcol(j))) = acc[i][j][r];
       lds_barrier();
     };
     if constexpr (HOLD_A && P >= 2) {
-      // Half-tile pipeline: unit u = (tile u / 2, column half u % 2).  The
-      // MFMAs of unit u run while the accumulators of unit u - 1 go to the
-      // staged tile, so the staging writes overlap the math; the barrier that
-      // hands a tile to the store waves follows the write of its second half.
-      constexpr int FH = FN / 2;
-      Frag fbh[R][NP][FH];
+      // Column-slice pipeline: unit u = (tile u / NSL, column slice u % NSL).
+      // The MFMAs of unit u run while the accumulators of unit u - 1 go to
+      // the staged tile, so the staging writes overlap the math; the barrier
+      // that hands a tile to the store waves follows the write of its last
+      // slice.  Narrower slices for bf16x6 keep its registers in budget.
+      constexpr int NSL = (P == 3) ? 4 : 2;
+      constexpr int FH = FN / NSL;
+      // B fragment groups in flight: the ring runs across slices and tiles
+      constexpr int RSMAX = 2;
+      constexpr int RS = NSL * NKG < RSMAX ? NSL * NKG : RSMAX;
+      static_assert((NSL * NKG) % RS == 0, "ring aligned with tiles");
+      Frag fbh[RS][NP][FH];
       floatx4 ah[2][FM][FH];
-      const uint32_t nunits = 2 * mine;
+      const uint32_t nunits = NSL * mine;
+      // B address = wave-uniform part (tile column block and slice: scalar
+      // registers) + a 32-bit per-lane part fixed for the whole kernel
+      const uint32_t blane = (uint32_t)(wn * 64 + lr) * (uint32_t)(KP * ES) + 16u * lg;
       auto bh_off = [&](uint32_t u) {
-        const uint32_t tile = tile_at(u >> 1);
-        return ((uint64_t)(tile & tnmask) * kRT + wn * 64 + (u & 1) * 32 + lr) * (uint64_t)(KP * ES) + 16 * lg;
+        const uint32_t tile = tile_at(u / NSL);
+        return ((uint64_t)(tile & tnmask) * kRT + (u % NSL) * (64 / NSL)) * (uint64_t)(KP * ES);
       };
       auto load_bh = [&](uint64_t bo, int kg, int q) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p) {
+          const char *bp = Bp[p] + bo;
 #pragma unroll
           for (int j = 0; j < FH; ++j)
-            fbh[q][p][j] = *(const Frag *)(Bp[p] + bo + (uint64_t)(j * 16 * KP + kg * KG) * ES);
+            fbh[q][p][j] = *(const Frag *)(bp + blane + (uint32_t)((j * 16 * KP + kg * KG) * ES));
+        }
       };
       auto mfma_half = [&](int sa, int kg, int q) {
         if constexpr (P == 1) {
@@ -278,47 +288,54 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
         }
       };
       auto write_half = [&](uint32_t u, int sa) {
-        char *ct = smem + ((u >> 1) & 1) * kCtBytes;
-        const int h = (int)(u & 1);
+        char *ct = smem + ((u / NSL) & 1) * kCtBytes;
+        const int h = (int)(u % NSL);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int j = 0; j < FH; ++j)
-              *(float *)(ct + (trow[i][r] ^ tcol[h * FH + j])) = ah[sa][i][j][r];
+              *(float *)(ct + (ctlane ^ trow(i, r) ^ tcol(h * FH + j))) = ah[sa][i][j][r];
       };
       // compute unit u into ah[u & 1] (prefetching the next unit's B groups);
       // with PREV, also stage unit u - 1 from ah[(u - 1) & 1]
-      auto unit_step = [&](auto PREV, auto SA, uint32_t u) {
+      // unit u is slice SI of its tile; its k groups are ring slots
+      // (SI * NKG + kg) % RS, refilled RS groups ahead
+      auto unit_step = [&](auto PREV, auto SA, auto SI, uint32_t u) {
         constexpr bool WR = decltype(PREV)::value;
         constexpr int sa = decltype(SA)::value;  // = u & 1, compile-time register set
-        const uint64_t cb = bh_off(u), nb = bh_off(u + 1 < nunits ? u + 1 : u);
+        constexpr int si = decltype(SI)::value;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FH; ++j) ah[sa][i][j] = floatx4{0, 0, 0, 0};
 #pragma unroll
         for (int kg = 0; kg < NKG; ++kg) {
-          const int q = kg % R;
+          const int gidx = si * NKG + kg;
+          const int q = gidx % RS;
           mfma_half(sa, kg, q);
-          if (kg + R < NKG) load_bh(cb, kg + R, q);
-          else load_bh(nb, kg + R - NKG, q);
+          {
+            const int G = gidx + RS;
+            const uint32_t ut = u - si + G / NKG;
+            load_bh(bh_off(ut < nunits ? ut : nunits - 1), G % NKG, q);
+          }
           if constexpr (WR) {
             if (kg == 0) write_half(u - 1, sa ^ 1);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (WR && sa == 0) lds_barrier();  // unit u - 1 completed tile (u - 1) / 2
+        if constexpr (WR) {
+          if (u % NSL == 0) lds_barrier();  // unit u - 1 completed tile (u - 1) / NSL
+        }
       };
       using T1h = std::true_type;
       using F0h = std::false_type;
       using S0 = std::integral_constant<int, 0>;
       using S1 = std::integral_constant<int, 1>;
       {
-        const uint64_t bo = bh_off(0);
 #pragma unroll
-        for (int q = 0; q < R; ++q) load_bh(bo, q, q);
+        for (int q = 0; q < RS; ++q) load_bh(bh_off((uint32_t)(q / NKG) < nunits ? q / NKG : nunits - 1), q % NKG, q);
       }
       // runs of units in one tile row: A loaded once per run, outside the
       // inner loop, so the inner loop has no conditional loads
@@ -328,14 +345,25 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
         const uint64_t ao = a_off(tile_at(it));
 #pragma unroll
         for (int q = 0; q < NA; ++q) load_a(ao, q, q);
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        auto tile_units = [&](auto FIRST, uint32_t t) {
+          if constexpr (decltype(FIRST)::value) unit_step(F0h{}, S0{}, I0{}, NSL * t);
+          else unit_step(T1h{}, S0{}, I0{}, NSL * t);
+          unit_step(T1h{}, S1{}, I1{}, NSL * t + 1);
+          if constexpr (NSL == 4) {
+            unit_step(T1h{}, S0{}, I2{}, NSL * t + 2);
+            unit_step(T1h{}, S1{}, I3{}, NSL * t + 3);
+          }
+        };
         if (it == 0) {
-          unit_step(F0h{}, S0{}, 0);
-          unit_step(T1h{}, S1{}, 1);
+          tile_units(T1h{}, 0);
           ++it;
         }
         while (it < mine && (tile_at(it) >> lgtn) == tm_run) {
-          unit_step(T1h{}, S0{}, 2 * it);
-          unit_step(T1h{}, S1{}, 2 * it + 1);
+          tile_units(F0h{}, it);
           ++it;
         }
       }
