@@ -193,6 +193,107 @@ def costmodel_study(tqc, torch):
             "speedup_mlp_over_dp": res["roofline_dp"]["ms"] / res["mlp_2000"]["ms"]}
 
 
+def _batch_job(i):
+    from workloads import batch
+    return batch.job(i)
+
+
+def _pcts(x):
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)),
+            "max": float(np.max(x)), "mean": float(np.mean(x))}
+
+
+def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
+    """Batched execution of uneven reconstructions: num_jobs seeded cut
+    circuits (n uniform in 16..28 qubits, 2..5 subcircuits, 2..10 cuts, line
+    or grid layouts, exact subcircuit tensors) with autotuned tiles, run as one
+    HIP graph over four streams versus the same jobs as sequential plain
+    launches on one stream.  Reports the batch time (median of `reps`), jobs
+    per second, per-job time (end - start) and completion time (end - batch
+    start) percentiles from device timestamps, and that every output equals
+    the job's own plain execution bit for bit."""
+    from workloads import batch
+    t0 = time.perf_counter()
+    specs = [None] * num_jobs
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for k, (i, spec) in enumerate(zip(range(num_jobs), pool.imap(_batch_job, range(num_jobs)))):
+            specs[i] = spec
+            if (k + 1) % 64 == 0:
+                print(f"# generated {k + 1}/{num_jobs} jobs ({time.perf_counter() - t0:.1f} s)",
+                      file=sys.stderr, flush=True)
+    gen_s = time.perf_counter() - t0
+    dist = batch.describe(specs)
+    nets = []
+    for spec in specs:
+        net = tqc.Network.from_spec(spec)
+        net.upload()
+        nets.append(net)
+    meta = [(s.n, len(s.tensors), s.num_cuts) for s in specs]
+    del specs
+    dt = "f64" if form == "fp64" else "f32"
+    # autotune: one plan per distinct set of step shapes; the table then
+    # serves every plan created with tile_policy=1
+    t0 = time.perf_counter()
+    tuned, ntuned = set(), 0
+    for k, net in enumerate(nets):
+        if k % 128 == 0:
+            print(f"# autotune pass at job {k} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+        p = tqc.Plan(net, precision=form, out_dtype=dt)
+        keys = {(st["log2_m"], st["log2_n"], st["log2_k"]) for st in p.steps}
+        if not keys <= tuned:
+            tqc.autotune(p, reps=2)
+            tuned |= keys
+            ntuned += 1
+        del p
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    print(f"# autotuned {ntuned} plans ({len(tuned)} step shapes) in {tune_s:.1f} s", file=sys.stderr,
+          flush=True)
+    plans = [tqc.Plan(net, precision=form, out_dtype=dt, tile_policy=1) for net in nets]
+    outs = [p.output_tensor() for p in plans]
+    runs = {}
+    for name, kw in (("graph_4streams", dict(use_graph=True, streams=4)),
+                     ("sequential_plain", dict(use_graph=False, streams=1))):
+        mj = tqc.Multi(plans, outs=outs, **kw)
+        timed = tqc.Multi(plans, outs=outs, timed=True, **kw)
+        mj.execute()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mj.execute()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        timed.execute()
+        timed.execute()
+        st, en = timed.job_times()
+        batch_ms = float(np.median(ms))
+        runs[name] = {"batch_ms": batch_ms, "batch_ms_all": [round(x, 4) for x in ms],
+                      "jobs_per_s": num_jobs / batch_ms * 1e3,
+                      "per_job_ms": _pcts(en - st), "completion_ms": _pcts(en),
+                      "timed_batch_ms": float(en.max())}
+        print(f"# {name}: {batch_ms:.3f} ms per batch", file=sys.stderr, flush=True)
+        del mj, timed
+    # every output equals the job's own plain execution
+    same = 0
+    for p, o in zip(plans, outs):
+        ref = torch.empty_like(o)
+        p.execute(ref)
+        same += int(torch.equal(ref, o))
+        del ref
+    return {"study": "batch", "workload": f"{num_jobs} seeded cut circuits, n 16..28, 2..5 subcircuits, "
+                                          "2..10 cuts, line/grid, exact tensors",
+            "form": form, "jobs": num_jobs, "distribution": dist, "generation_s": gen_s,
+            "autotune": {"plans_tuned": ntuned, "step_shapes": len(tuned), "seconds": tune_s},
+            "runs": runs,
+            "speedup_graph_over_sequential": runs["sequential_plain"]["batch_ms"] /
+                                             runs["graph_4streams"]["batch_ms"],
+            "outputs_equal_plain_execution": same,
+            "largest_jobs": sorted(meta, reverse=True)[:3]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,9 +302,11 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--study", choices=["precision", "costmodel"], default=None,
+    ap.add_argument("--study", choices=["precision", "costmodel", "batch"], default=None,
                     help="instead of the benchmark line: the precision study of the 18-cut "
-                         "synthetic network (2^30 slice) or the cost-model A/B on the 12-patch grid")
+                         "synthetic network (2^30 slice), the cost-model A/B on the 12-patch grid, "
+                         "or batched execution of 512 uneven reconstructions (--forms picks the form)")
+    ap.add_argument("--jobs", type=int, default=512, help="jobs of the batch study")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -224,6 +327,11 @@ def main():
         return
     if args.study == "costmodel":
         print(json.dumps(costmodel_study(tqc, torch)))
+        return
+    if args.study == "batch":
+        for form in args.forms.split(","):
+            print(json.dumps(batch_study(tqc, torch, form, num_jobs=args.jobs)), flush=True)
+            torch.cuda.empty_cache()
         return
 
     spec = qaoa.qaoa_network()

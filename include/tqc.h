@@ -247,9 +247,43 @@ tqc_status tqc_execute_summary(tqc_plan_t plan, void *out, uint64_t out_bytes, i
                                uint64_t *top_idx, double *top_val, double *total,
                                double *phase_ms, int32_t num_phases, void *stream);
 
+/* --------------------------------------------------------------- multi-job
+ * Many independent reconstructions replayed as one HIP graph (batched
+ * execution for serving; the paper runs one reconstruction at a time).
+ * tqc_multi_create binds num_jobs unsliced plans to their outputs (device
+ * pointers to out_entries values of each plan's out_dtype; out_bytes may be
+ * NULL, else each entry is checked), allocates every workspace, and spreads
+ * the jobs over num_streams streams (0 = 4, at most 16), largest predicted
+ * first, each to the least-loaded stream.  With use_graph = 1 the first
+ * tqc_multi_execute captures every job's launches (transform, packs,
+ * pairwise steps, final step) between a fork from and a join into `stream`
+ * once; each call then replays that graph on `stream`.  With use_graph = 0
+ * the same launches are enqueued directly (num_streams = 1 gives the jobs as
+ * sequential plain launches).  Results equal tqc_execute's bit for bit.  Jobs
+ * must not share a plan; a plan must not be executed elsewhere while the
+ * object runs it.  The object keeps pointers to the plans and outputs:
+ * destroy it before them.  With timed = 1 a one-thread kernel stores the
+ * device clock before and after each job (a few microseconds per job);
+ * tqc_multi_job_times then waits for the last execute and gives each job's
+ * start and end in ms after that execute began (num_jobs doubles in each
+ * array; either may be NULL).  Errors: INVALID_ARG (also job times without
+ * timed, or before any execute), UNSUPPORTED (sliced plan), SHAPE,
+ * OUT_OF_MEMORY, DEVICE (also a failed capture). */
+typedef struct tqc_multi_s *tqc_multi_t;
+tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                            const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams,
+                            int32_t timed, void *stream, tqc_multi_t *out);
+tqc_status tqc_multi_execute(tqc_multi_t multi, void *stream);
+tqc_status tqc_multi_job_times(tqc_multi_t multi, double *start_ms, double *end_ms);
+void tqc_multi_destroy(tqc_multi_t multi);
+
 /* -------------------------------------------------------------------- batch
- * Many independent reconstructions in a few launches, captured once into a
- * HIP graph and replayed: three short launches over all jobs (Pauli
+ * tqc_batch_execute is switched off (returns UNSUPPORTED): GPU runs of the
+ * persistent launch below did not finish, and the cause has not been
+ * identified.  tqc_batch_execute_sequential (plain per-job launches) works;
+ * tqc_multi_* above is the working batched path.
+ * Design of the persistent path: many independent reconstructions in a few
+ * launches, captured once into a HIP graph and replayed: three short launches over all jobs (Pauli
  * transform, operand abs-max, power-of-two exponents), then persistent
  * launches whose workgroups claim pack chunks and GEMM tiles of all jobs
  * from a shared queue.  Default: one persistent launch per depth of the

@@ -115,6 +115,10 @@ def _declare(L):
         "tqc_batch_execute_sequential": [vp, vp, _dp],
         "tqc_batch_job_times": [vp, _dp, _dp, ctypes.POINTER(ctypes.c_uint32)],
         "tqc_batch_info": [vp, ctypes.POINTER(u64), _i32p, _i32p],
+        "tqc_multi_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64), i32, i32,
+                             i32, vp, ctypes.POINTER(vp)],
+        "tqc_multi_execute": [vp, vp],
+        "tqc_multi_job_times": [vp, _dp, _dp],
         "tqc_plan_autotune": [vp, vp, u64, i32, vp],
         "tqc_autotune_save": [ctypes.c_char_p],
         "tqc_autotune_load": [ctypes.c_char_p],
@@ -140,7 +144,7 @@ def _declare(L):
     L.tqc_costmodel_num_params.restype = ctypes.c_int32
     L.tqc_costmodel_num_features.restype = ctypes.c_int32
     for name in ("tqc_network_destroy", "tqc_plan_destroy", "tqc_batch_destroy",
-                 "tqc_costmodel_destroy"):
+                 "tqc_multi_destroy", "tqc_costmodel_destroy"):
         getattr(L, name).argtypes = [vp]
         getattr(L, name).restype = None
     L.tqc_plan_options_default.argtypes = [ctypes.POINTER(PlanOptions)]
@@ -438,6 +442,46 @@ class Batch:
         h = getattr(self, "handle", None)
         if h is not None and _LIB is not None:
             _LIB.tqc_batch_destroy(h)
+            self.handle = None
+
+
+class Multi:
+    """Independent unsliced reconstructions replayed as one HIP graph
+    (``use_graph``) or enqueued as plain launches, spread over ``streams``
+    streams; ``streams=1, use_graph=False`` runs them one after another.
+    Outputs equal each plan's own ``execute`` bit for bit."""
+
+    def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None):
+        L = lib()
+        if outs is None:
+            outs = [p.output_tensor() for p in plans]
+        self.plans = list(plans)
+        self.outs = list(outs)
+        self.timed = bool(timed)
+        n = len(self.plans)
+        ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
+        ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
+        h = ctypes.c_void_p()
+        _check(L.tqc_multi_create(n, ph, oh, ob, int(bool(use_graph)), int(streams), int(self.timed),
+                                  _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check(lib().tqc_multi_execute(self.handle, _stream_ptr(stream)))
+
+    def job_times(self):
+        """(start_ms, end_ms) per job, from the start of the last execute."""
+        n = len(self.plans)
+        a = (ctypes.c_double * n)()
+        b = (ctypes.c_double * n)()
+        _check(lib().tqc_multi_job_times(self.handle, ctypes.cast(a, _dp), ctypes.cast(b, _dp)))
+        return np.array(a[:]), np.array(b[:])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.tqc_multi_destroy(h)
             self.handle = None
 
 

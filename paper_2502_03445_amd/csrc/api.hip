@@ -20,6 +20,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "transform_sched.hpp"
 #include "batch.hpp"
 #include "costmodel.hpp"
 #include "dev_ops.hpp"
@@ -183,7 +184,36 @@ static void check_device(int want) {
 // --------------------------------------------------------------- execute
 static TransformArgs make_transform_args(const TensorIn &t, double *out);
 
+static void *get_scratch(uint64_t bytes, hipStream_t s);
+static std::mutex &scratch_mutex();
+
+// Separable transform of a raw tensor with at least kPassMinCuts cuts: each
+// pass reads the previous layout and writes the next, alternating between
+// two scratch buffers of `scr_bytes` each so that the last pass lands in dst.
+static void transform_passes(const TensorIn &t, double *dst, double *s0, double *s1, uint64_t scr_bytes,
+                             hipStream_t s) {
+  const TransformSchedule sc = transform_schedule(t);
+  const int P = (int)sc.passes.size();
+  if (P > 1 && sc.max_intermediate * 8 > scr_bytes) fail(TQC_ERR_INTERNAL, "transform scratch too small");
+  const double *in = t.dev_raw;
+  for (int i = 0; i < P; ++i) {
+    TransformPassArgs a = sc.passes[i];
+    double *out = i == P - 1 ? dst : ((P - 2 - i) % 2 == 0 ? s0 : s1);
+    a.in = in;
+    a.out = out;
+    HIP_OK(launch_transform_pass(a, s));
+    in = out;
+  }
+}
+
 static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
+  if ((int)t.cuts.size() >= kPassMinCuts) {
+    const uint64_t b = (transform_schedule(t).max_intermediate * 8 + 255) & ~uint64_t(255);
+    std::lock_guard<std::mutex> lk(scratch_mutex());
+    char *sp = (char *)get_scratch(2 * b, s);
+    transform_passes(t, out, (double *)sp, (double *)(sp + b), b, s);
+    return;
+  }
   TransformArgs a = make_transform_args(t, out);
   HIP_OK(launch_transform(a, s));
 }
@@ -291,7 +321,7 @@ static ScaleBuf scale_buffers(Plan *p) {
 static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
   Network &net = *p->net;
   const int m = net.m;
-  HIP_OK(hipMemsetAsync(sb.maxbits, 0, (size_t)m * 8, s));
+  HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
   for (int j = 0; j < m; ++j) {
     const TensorIn &t = net.t[j];
     PackArgs pa = make_pack_args(p, j, nullptr, nullptr, nullptr, 0, 0);
@@ -427,9 +457,16 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
   const int pc = int(p->prec);
   if (tm) tm->begin(0);
   {
+    // tensors with several cuts: separable passes; the rest: the per-entry
+    // kernel, up to four tensors per launch
     std::vector<TransformArgs> ta;
-    for (auto &t : net.t)
-      if (t.basis == TQC_BASIS_RAW) ta.push_back(make_transform_args(t, t.dev_pauli));
+    double *s0 = (double *)((char *)p->ws + p->tscr_offset);
+    double *s1 = (double *)((char *)p->ws + p->tscr_offset + p->tscr_bytes);
+    for (auto &t : net.t) {
+      if (t.basis != TQC_BASIS_RAW) continue;
+      if ((int)t.cuts.size() >= kPassMinCuts) transform_passes(t, t.dev_pauli, s0, s1, p->tscr_bytes, s);
+      else ta.push_back(make_transform_args(t, t.dev_pauli));
+    }
     if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
   }
   if (tm) tm->end();
@@ -990,6 +1027,167 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
 }
 
 
+// ------------------------------------------------------------- multi-job
+// Many independent reconstructions as one HIP graph: every job's plain
+// launches (transform, packs, pairwise steps, final step) are captured once,
+// spread over a few streams (largest predicted jobs first, each to the
+// least-loaded stream), and the graph is replayed per call.  Independent
+// branches let the device run small jobs side by side and the replay costs
+// one launch instead of a few per job.  Every allocation happens at creation,
+// outside the capture.  With `timed`, one-thread kernels store the device
+// clock before and after every job (kernels rather than timing events, so the
+// stamps are ordinary graph nodes).
+struct Multi {
+  std::vector<Plan *> plans;
+  std::vector<void *> outs;
+  std::vector<uint64_t> out_bytes;
+  std::vector<int> stream_of;     // job -> worker stream
+  std::vector<int> order;         // launch order (largest first)
+  int device = -1;
+  bool use_graph = true, timed = false;
+  double tick_ms = 0.0;           // milliseconds per clock tick
+  unsigned long long *stamps = nullptr;  // [0] = launch, [1 + 2j] / [2 + 2j] = job j start / end
+  std::vector<hipStream_t> streams;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipStream_t last_stream = nullptr;
+  bool ran = false;
+  ~Multi() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (stamps) (void)hipFree(stamps);
+  }
+};
+
+static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
+                           int use_graph, int nstreams, int timed, hipStream_t s) {
+  if (njobs < 1 || !plans || !outs) fail(TQC_ERR_INVALID_ARG, "no jobs");
+  if (nstreams < 0 || nstreams > 16) fail(TQC_ERR_INVALID_ARG, "streams %d (0..16)", nstreams);
+  if (nstreams == 0) nstreams = 4;
+  std::unique_ptr<Multi> b(new Multi());
+  b->use_graph = use_graph != 0;
+  b->timed = timed != 0;
+  HIP_OK(hipGetDevice(&b->device));
+  std::vector<double> cost(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    Plan *p = plans[j];
+    if (!p || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
+    if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not batched", j);
+    if (p->net->device >= 0 && p->net->device != b->device)
+      fail(TQC_ERR_DEVICE, "job %d: network lives on device %d, current device is %d", j, p->net->device,
+           b->device);
+    const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
+    if (out_bytes && out_bytes[j] < need) fail(TQC_ERR_SHAPE, "job %d: output too small", j);
+    // every lazy allocation of the execute path, before any capture
+    ensure_workspace(p, s);
+    if (p->net->m >= 2) (void)scale_buffers(p);
+    b->plans.push_back(p);
+    b->outs.push_back(outs[j]);
+    b->out_bytes.push_back(need);
+    cost[j] = p->stats.predicted_seconds;
+  }
+  for (int j = 1; j < njobs; ++j)
+    for (int i = 0; i < j; ++i)
+      if (plans[i] == plans[j]) fail(TQC_ERR_INVALID_ARG, "jobs %d and %d share a plan (and its workspace)", i, j);
+  (void)root_gemm_warm();
+  b->order.resize(njobs);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> load(nstreams, 0.0);
+  b->stream_of.assign(njobs, 0);
+  for (int j : b->order) {
+    const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+    b->stream_of[j] = k;
+    load[k] += cost[j];
+  }
+  if (b->timed) {
+    int khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    if (khz <= 0) fail(TQC_ERR_DEVICE, "device reports no clock rate for timestamps");
+    b->tick_ms = 1.0 / khz;
+    HIP_OK(hipMalloc((void **)&b->stamps, (1 + 2 * (size_t)njobs) * 8));
+    HIP_OK(launch_zero_u64(b->stamps, 1 + 2 * (uint64_t)njobs, s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  b->streams.resize(nstreams);
+  for (auto &st : b->streams) HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  b->join.resize(nstreams);
+  for (auto &e : b->join) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return b.release();
+}
+
+// fork from `origin`, every job on its stream (between its two stamps), join
+static void multi_enqueue(Multi *b, hipStream_t origin) {
+  if (b->timed) HIP_OK(launch_stamp(b->stamps, origin));
+  HIP_OK(hipEventRecord(b->fork, origin));
+  for (auto st : b->streams) HIP_OK(hipStreamWaitEvent(st, b->fork, 0));
+  for (int j : b->order) {
+    hipStream_t st = b->streams[b->stream_of[j]];
+    if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * j, st));
+    execute(b->plans[j], b->outs[j], b->out_bytes[j], st);
+    if (b->timed) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
+  }
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    HIP_OK(hipEventRecord(b->join[k], b->streams[k]));
+    HIP_OK(hipStreamWaitEvent(origin, b->join[k], 0));
+  }
+}
+
+static void multi_execute(Multi *b, hipStream_t s) {
+  check_device(b->device);
+  b->last_stream = s;
+  b->ran = true;
+  if (!b->use_graph) {
+    multi_enqueue(b, s);
+    return;
+  }
+  if (!b->exec) {
+    HIP_OK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    bool ok = true;
+    std::string msg;
+    try {
+      multi_enqueue(b, b->cap);
+    } catch (const Error &e) {
+      ok = false;
+      msg = e.msg;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->cap, &g);
+    if (!ok) {
+      if (g) (void)hipGraphDestroy(g);
+      fail(TQC_ERR_DEVICE, "capture of the jobs failed: %s", msg.c_str());
+    }
+    HIP_OK(ce);
+    b->graph = g;
+    HIP_OK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_OK(hipGraphLaunch(b->exec, s));
+}
+
+// per-job start / end in milliseconds after the launch began (last call)
+static void multi_times(Multi *b, double *start_ms, double *end_ms) {
+  if (!b->timed) fail(TQC_ERR_INVALID_ARG, "the jobs were set up without timestamps");
+  if (!b->ran) fail(TQC_ERR_INVALID_ARG, "the jobs have not run yet");
+  check_device(b->device);
+  HIP_OK(hipStreamSynchronize(b->last_stream));
+  const size_t n = b->plans.size();
+  std::vector<unsigned long long> st(1 + 2 * n);
+  HIP_OK(hipMemcpy(st.data(), b->stamps, st.size() * 8, hipMemcpyDeviceToHost));
+  for (size_t j = 0; j < n; ++j) {
+    if (start_ms) start_ms[j] = double((long long)(st[1 + 2 * j] - st[0])) * b->tick_ms;
+    if (end_ms) end_ms[j] = double((long long)(st[2 + 2 * j] - st[0])) * b->tick_ms;
+  }
+}
+
 // ------------------------------------------------------------- cost model
 struct CostModel {
   int device = -1;
@@ -1424,6 +1622,37 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits, 
 }
 
 struct tqc_batch_s : Batch {};
+struct tqc_multi_s : Multi {};
+
+tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                            const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams, int32_t timed,
+                            void *stream, tqc_multi_t *out) {
+  return guarded([&] {
+    if (!out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    Multi *m = create_multi(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, use_graph,
+                            num_streams, timed, (hipStream_t)stream);
+    *out = reinterpret_cast<tqc_multi_t>(static_cast<tqc_multi_s *>(m));
+  });
+}
+
+tqc_status tqc_multi_execute(tqc_multi_t multi, void *stream) {
+  return guarded([&] {
+    if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
+    multi_execute(static_cast<Multi *>(multi), (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_multi_job_times(tqc_multi_t multi, double *start_ms, double *end_ms) {
+  return guarded([&] {
+    if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
+    multi_times(static_cast<Multi *>(multi), start_ms, end_ms);
+  });
+}
+
+void tqc_multi_destroy(tqc_multi_t multi) {
+  if (multi) delete static_cast<Multi *>(static_cast<tqc_multi_s *>(multi));
+}
 
 tqc_status tqc_batch_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, const tqc_batch_options *opt, void *stream,

@@ -34,6 +34,27 @@ struct TransformArgs {
   uint64_t w[kMaxCutsT];    // mixed-radix weight of the cut's raw row digit
 };
 
+// One pass of the separable Pauli transform: one or two cuts of a tensor
+// change from their measured / prepared variants to Pauli digits, every
+// other index is a free coordinate.  A free coordinate splits, innermost
+// first, into segments of extent seg_ext; each segment's digit moves the
+// source and destination by seg_in / seg_out elements.  For pass cut i the
+// source holds its variants at multiples of row_in[i] (row digit: basis or
+// preparation) and bit_in[i] (the measured bit of an upstream end); the
+// destination holds its Pauli digit at multiples of row_out[i].
+constexpr int kPassSegs = 5;
+struct TransformPassArgs {
+  const double *in;
+  double *out;
+  uint64_t nfree;
+  int nseg;
+  int g;                      // cuts in the pass (1 or 2)
+  int up[2];                  // 1 = upstream end
+  uint64_t seg_ext[kPassSegs], seg_in[kPassSegs], seg_out[kPassSegs];
+  uint64_t row_in[2], bit_in[2], row_out[2];
+  uint64_t out_entries;       // destination size (for host-side checks)
+};
+
 // ---------------------------------------------------------------- pack
 // Gather one leaf operand from its float64 Pauli tensor: slice / fixed-qubit
 // selection via a base offset, arbitrary bit permutation, cast or split.

@@ -40,6 +40,13 @@ __global__ void __launch_bounds__(256) f64_to_f32_kernel(const double *in, float
     out[i] = (float)in[i];
 }
 
+// zero fill (a kernel rather than a memset node, so it can be captured in a
+// graph and replayed)
+__global__ void __launch_bounds__(256) zero_u64_kernel(unsigned long long *buf, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    buf[i] = 0ull;
+}
+
 __global__ void __launch_bounds__(256) scale_f64_kernel(double *buf, uint64_t n, double s) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -91,6 +98,123 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u) {
   return (unsigned)(b > cap ? cap : b);
 }
 
+// Separable transform pass (Sec. II-A maps, one cut at a time).  Downstream
+// end, preparations |0>, |1>, |+>, |i>: I = r0 + r1, X = 2 r+ - r0 - r1,
+// Y = 2 ri - r0 - r1, Z = r0 - r1.  Upstream end, bases Z, X, Y with
+// measured bit b: I = Z0 + Z1, X = X0 - X1, Y = Y0 - Y1, Z = Z0 - Z1.
+__device__ inline void down_map(const double r[4], double p[4]) {
+  const double s01 = r[0] + r[1];
+  p[0] = s01;
+  p[1] = 2.0 * r[2] - s01;
+  p[2] = 2.0 * r[3] - s01;
+  p[3] = r[0] - r[1];
+}
+__device__ inline void up_map(const double v[6], double p[4]) {
+  p[0] = v[0] + v[1];
+  p[1] = v[2] - v[3];
+  p[2] = v[4] - v[5];
+  p[3] = v[0] - v[1];
+}
+
+template <bool UP>
+__device__ inline uint64_t variant_off(const TransformPassArgs &a, int i, int v) {
+  if constexpr (UP) return (uint64_t)(v >> 1) * a.row_in[i] + (uint64_t)(v & 1) * a.bit_in[i];
+  else return (uint64_t)v * a.row_in[i];
+}
+
+template <bool UP>
+__device__ inline void cut_map(const double *v, double *p) {
+  if constexpr (UP) up_map(v, p);
+  else down_map(v, p);
+}
+
+// One thread per free coordinate: loads every variant of the pass cuts,
+// applies the first cut's map then the second's, stores 4 or 16 digits.
+// Consecutive threads take consecutive innermost coordinates, so every
+// load and store instruction of a wave covers consecutive addresses.
+template <int G, bool UA, bool UB>
+__global__ void __launch_bounds__(256) transform_pass_kernel(TransformPassArgs a) {
+  constexpr int NA = UA ? 6 : 4;
+  constexpr int NB = G == 2 ? (UB ? 6 : 4) : 1;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const bool small = a.nfree <= 0xffffffffull;
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.nfree; f += stride) {
+    uint64_t ib = 0, ob = 0;
+    if (small) {
+      uint32_t r = (uint32_t)f;
+      for (int s = 0; s < a.nseg - 1; ++s) {
+        const uint32_t e = (uint32_t)a.seg_ext[s];
+        const uint32_t q = r / e, c = r - q * e;
+        ib += (uint64_t)c * a.seg_in[s];
+        ob += (uint64_t)c * a.seg_out[s];
+        r = q;
+      }
+      ib += (uint64_t)r * a.seg_in[a.nseg - 1];
+      ob += (uint64_t)r * a.seg_out[a.nseg - 1];
+    } else {
+      uint64_t r = f;
+      for (int s = 0; s < a.nseg - 1; ++s) {
+        const uint64_t e = a.seg_ext[s];
+        const uint64_t q = r / e, c = r - q * e;
+        ib += c * a.seg_in[s];
+        ob += c * a.seg_out[s];
+        r = q;
+      }
+      ib += r * a.seg_in[a.nseg - 1];
+      ob += r * a.seg_out[a.nseg - 1];
+    }
+    double v[NA * NB];
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        uint64_t off = ib + variant_off<UA>(a, 0, ia);
+        if constexpr (G == 2) off += variant_off<UB>(a, 1, jb);
+        v[ia * NB + jb] = a.in[off];
+      }
+    double t[4 * NB];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      double col[NA], p[4];
+#pragma unroll
+      for (int ia = 0; ia < NA; ++ia) col[ia] = v[ia * NB + jb];
+      cut_map<UA>(col, p);
+#pragma unroll
+      for (int sa = 0; sa < 4; ++sa) t[sa * NB + jb] = p[sa];
+    }
+    if constexpr (G == 1) {
+#pragma unroll
+      for (int sa = 0; sa < 4; ++sa) a.out[ob + (uint64_t)sa * a.row_out[0]] = t[sa];
+    } else {
+#pragma unroll
+      for (int sa = 0; sa < 4; ++sa) {
+        double p[4];
+        cut_map<UB>(t + sa * NB, p);
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+          a.out[ob + (uint64_t)sa * a.row_out[0] + (uint64_t)sb * a.row_out[1]] = p[sb];
+      }
+    }
+  }
+}
+
+hipError_t launch_transform_pass(const TransformPassArgs &a, hipStream_t s) {
+  if (a.nfree == 0) return hipSuccess;
+  if (a.nseg < 1 || a.nseg > kPassSegs || a.g < 1 || a.g > 2) return hipErrorInvalidValue;
+  const dim3 grid(grid_for(a.nfree)), block(256);
+  if (a.g == 1) {
+    if (a.up[0]) hipLaunchKernelGGL((transform_pass_kernel<1, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((transform_pass_kernel<1, false, false>), grid, block, 0, s, a);
+  } else if (a.up[0]) {
+    if (a.up[1]) hipLaunchKernelGGL((transform_pass_kernel<2, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((transform_pass_kernel<2, true, false>), grid, block, 0, s, a);
+  } else {
+    if (a.up[1]) hipLaunchKernelGGL((transform_pass_kernel<2, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((transform_pass_kernel<2, false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_transform(const TransformArgs &a, hipStream_t s) {
   const uint64_t total = (1ull << (2 * a.c)) << a.o;
   hipLaunchKernelGGL(transform_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
@@ -132,6 +256,22 @@ hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s) {
 hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
                                   double *root_scale, hipStream_t s) {
   hipLaunchKernelGGL(scale_exponents_kernel, dim3(1), dim3(64), 0, s, maxbits, m, K, exps, root_scale);
+  return hipGetLastError();
+}
+
+// one thread stores the device's constant-rate clock (a timestamp that
+// orders work across streams of one device)
+__global__ void stamp_kernel(unsigned long long *dst) {
+  if (threadIdx.x == 0) dst[0] = wall_clock64();
+}
+
+hipError_t launch_stamp(unsigned long long *dst, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(n)), dim3(256), 0, s, buf, n);
   return hipGetLastError();
 }
 

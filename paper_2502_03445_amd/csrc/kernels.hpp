@@ -12,6 +12,10 @@ hipError_t launch_transforms(const TransformArgs *args, int n, hipStream_t s);  
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s);
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s);
+hipError_t launch_stamp(unsigned long long *dst, hipStream_t s);
+hipError_t launch_transform_pass(const TransformPassArgs &a, hipStream_t s);
+int root_gemm_warm();  // caches the device's CU count (call outside graph capture)
 hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s);
 hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
                                   double *root_scale, hipStream_t s);

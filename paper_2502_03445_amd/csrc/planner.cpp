@@ -22,6 +22,7 @@
 #include <random>
 
 #include "internal.hpp"
+#include "transform_sched.hpp"
 
 namespace tqc {
 
@@ -361,6 +362,15 @@ static void assemble(Plan &p) {
   // float64 Pauli tensors of raw inputs (transform output)
   for (int j = 0; j < m; ++j)
     if (net.t[j].basis == TQC_BASIS_RAW) off = align(off + net.t[j].pauli_entries() * 8);
+  // ping-pong buffers of the multi-pass transform (shared by the tensors,
+  // which are transformed one after another)
+  uint64_t inter = 0;
+  for (int j = 0; j < m; ++j)
+    if (net.t[j].basis == TQC_BASIS_RAW && (int)net.t[j].cuts.size() >= kPassMinCuts)
+      inter = std::max(inter, transform_schedule(net.t[j]).max_intermediate);
+  p.tscr_bytes = inter ? align(inter * 8) : 0;
+  p.tscr_offset = off;
+  off += 2 * p.tscr_bytes;
   for (size_t i = 0; i < p.nodes.size(); ++i) {
     Node &nd = p.nodes[i];
     nd.rows = 1ull << (nd.labels.size() - nd.log2k);

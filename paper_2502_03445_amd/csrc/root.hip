@@ -512,6 +512,8 @@ int cu_count() {
 
 }  // namespace
 
+int root_gemm_warm() { return cu_count(); }
+
 bool root_gemm_eligible(int prec, const GemmArgs &g) {
   if (prec < 1 || prec > 3 || g.out_kind != OUT_F32) return false;
   if (g.lm < 7 || g.ln < 7 || g.lm > kMaxBits || g.ln > kMaxBits) return false;

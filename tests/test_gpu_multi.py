@@ -1,0 +1,128 @@
+"""Many independent reconstructions as one HIP graph (GPU).
+
+Each job runs the same launches as its plan's own execute, only on one of a
+few worker streams and, with a graph, replayed from one capture; so every
+output must equal the plan's plain execution bit for bit, and match the
+oracle within the form's tolerance.  Graph replays are checked one by one
+against the eager result, with unrelated device work and host waits between
+them."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2502_03445_amd as tqc
+from oracle.reconstruct import full_distribution
+from workloads import configs, synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def jobs(form):
+    specs = [configs.config1(), configs.ghz(12, 3), configs.aqft(10, 3, 2),
+             configs.random_cut_circuit(9, 3, 4, 3, 4)]
+    for i, (m, K, outs) in enumerate([(2, 3, [7, 8]), (3, 4, [4, 5, 5]), (4, 6, [3, 3, 3, 4]),
+                                      (5, 7, [2, 3, 3, 2, 3]), (1, 0, [9]), (3, 2, [0, 6, 6]),
+                                      (2, 2, [10, 9]), (4, 5, [2, 4, 4, 4]), (2, 4, [8, 9])]):
+        specs.append(synthetic.random_network(m, K, outs, seed=700 + i))
+    nets = [tqc.Network.from_spec(s) for s in specs]
+    dt = "f64" if form == "fp64" else "f32"
+    plans = [tqc.Plan(n, precision=form, out_dtype=dt) for n in nets]
+    return specs, nets, plans
+
+
+def tol(form, ref):
+    if form == "fp64":
+        return 1e-12
+    return (3e-5 if form == "bf16x3" else 1e-6) * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("form,use_graph,streams", [("fp32", True, 4), ("bf16x3", True, 3),
+                                                    ("fp64", True, 4), ("fp32", False, 4),
+                                                    ("bf16x6", False, 1)])
+def test_multi_equals_plain_execution(form, use_graph, streams):
+    specs, nets, plans = jobs(form)
+    plain = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=use_graph, streams=streams)
+    for o in mj.outs:
+        o.fill_(-7.0)
+    mj.execute()
+    torch.cuda.synchronize()
+    for i, (spec, o, ref_gpu) in enumerate(zip(specs, mj.outs, plain)):
+        assert torch.equal(o, ref_gpu), i
+        ref = full_distribution(spec)
+        got = o.double().cpu().numpy()
+        assert np.abs(got - ref).max() <= tol(form, ref), (i, np.abs(got - ref).max())
+
+
+def test_graph_replays_match_eager():
+    specs, nets, plans = jobs("fp32")
+    eager = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=True, streams=4, timed=True)
+    for rep in range(4):
+        for o in mj.outs:
+            o.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        mj.execute()
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        for i, (o, e) in enumerate(zip(mj.outs, eager)):
+            assert torch.equal(o, e), (rep, i)
+        st, en = mj.job_times()
+        assert np.all(st >= 0) and np.all(en >= st), rep
+
+
+def test_sequential_jobs_do_not_overlap():
+    specs, nets, plans = jobs("fp32")
+    mj = tqc.Multi(plans, use_graph=False, streams=1, timed=True)
+    mj.execute()
+    st, en = mj.job_times()
+    order = np.argsort(st, kind="stable")
+    assert np.all(en >= st)
+    # one stream: each job starts after the previous one ended
+    assert np.all(st[order][1:] >= en[order][:-1])
+    # launched largest predicted first
+    pred = np.array([p.stats["predicted_seconds"] for p in plans])
+    assert np.all(np.diff(pred[order]) <= 1e-15)
+
+
+def test_multi_rejects_bad_jobs():
+    specs, nets, plans = jobs("fp32")
+    with pytest.raises(tqc.TqcError):
+        tqc.Multi([plans[0], plans[0]], outs=[plans[0].output_tensor(), plans[0].output_tensor()])
+    small = torch.empty(4, device="cuda")
+    with pytest.raises(tqc.TqcError):
+        tqc.Multi([plans[0]], outs=[small])
+    with pytest.raises(tqc.TqcError):
+        tqc.Multi(plans[:2], streams=17)
+    untimed = tqc.Multi(plans[:2])
+    untimed.execute()
+    with pytest.raises(tqc.TqcError):
+        untimed.job_times()
+    timed = tqc.Multi(plans[:2], timed=True)
+    with pytest.raises(tqc.TqcError):
+        timed.job_times()  # nothing ran yet
+
+
+@pytest.mark.parametrize("form,rtol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 3e-5)])
+def test_generated_batch_jobs_match_oracle(form, rtol):
+    from oracle.reconstruct import entries_variable_elimination
+    from workloads import batch
+    specs = [batch.job(i) for i in (158, 285, 335, 58, 170, 428)]  # 16-17 qubits, 2..10 cuts
+    nets = [tqc.Network.from_spec(s) for s in specs]
+    plans = [tqc.Plan(n, precision=form) for n in nets]
+    plain = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=True, streams=4)
+    mj.execute()
+    mj.execute()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for i, (spec, o, ref_gpu) in enumerate(zip(specs, mj.outs, plain)):
+        assert torch.equal(o, ref_gpu), i
+        got = o.double().cpu().numpy()
+        xs = rng.choice(1 << spec.n, 512, replace=False).astype(np.uint64)
+        xs = np.unique(np.concatenate([xs, np.argsort(got)[-8:].astype(np.uint64)]))
+        ref = entries_variable_elimination(spec, xs)
+        bound = rtol * np.abs(ref).max()
+        assert np.abs(got[xs.astype(np.int64)] - ref).max() <= bound, (i, spec.num_cuts)
+        assert abs(got.sum() - 1.0) <= 1e-4

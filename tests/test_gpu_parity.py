@@ -63,6 +63,22 @@ def test_transform_matches_oracle():
             assert np.abs(got - r).max() <= 1e-14 * max(1.0, np.abs(r).max())
 
 
+def test_transform_many_cuts_matches_oracle():
+    # tensors with 4..8 cuts (up to 4 measured and 4 prepared ends): the
+    # separable multi-pass transform, against the oracle's per-entry sums
+    from workloads import batch
+    for i in (58, 446):
+        spec = batch.job(i)
+        N = tqc.Network.from_spec(spec)
+        ref = network_pauli_tensors(spec)
+        assert max(len(t.cut_ids) for t in spec.tensors) >= 6
+        for j in range(len(spec.tensors)):
+            got = N.pauli_tensor(j).cpu().numpy()
+            r = ref[j][2]
+            assert got.shape == r.shape
+            assert np.abs(got - r).max() <= 1e-14 * max(1.0, np.abs(r).max()), (i, j)
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_config1_against_oracle_and_statevector(form):
     spec = configs.config1()

@@ -201,3 +201,32 @@ def cut_circuit(circ: Circuit, gate_sub, num_subs=None, idle_sub=None):
         infos.append({"width": w, "u": u, "d": len(my_cuts) - u, "outputs": o})
     net = Network(n=n, cuts=cuts, tensors=tensors, meta={"subcircuits": infos})
     return net
+
+
+def cut_shapes(circ: Circuit, gate_sub, num_subs=None, idle_sub=None):
+    """The cut list and per-subcircuit sizes cut_circuit would produce, without
+    simulating anything: (cuts, [{"width", "u", "d", "outputs", "gates"}]).
+    Lets a generator bound simulation cost and tensor sizes up front."""
+    n = circ.n
+    if idle_sub is None:
+        idle_sub = [0] * n
+    if num_subs is None:
+        num_subs = max(list(gate_sub) + list(idle_sub)) + 1
+    segs = _segments(circ, gate_sub, idle_sub)
+    by_q = [[] for _ in range(n)]
+    for si, s in enumerate(segs):
+        by_q[s[0]].append(si)
+    cuts, starts, ends = [], set(), set()
+    for q in range(n):
+        chain = by_q[q]
+        for a, b in zip(chain[:-1], chain[1:]):
+            cuts.append((segs[a][1], segs[b][1]))
+            ends.add(a)
+            starts.add(b)
+    shapes = []
+    for j in range(num_subs):
+        my = [si for si in range(len(segs)) if segs[si][1] == j]
+        u = sum(si in ends for si in my)
+        shapes.append({"width": len(my), "u": u, "d": sum(si in starts for si in my),
+                       "outputs": len(my) - u, "gates": sum(1 for g in gate_sub if g == j)})
+    return cuts, shapes
