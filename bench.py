@@ -144,12 +144,15 @@ def _random_order(rng, spec, fixed, temperature=2.0):
     return order
 
 
-def costmodel_study(tqc, torch):
+def costmodel_study(tqc, torch, candidates=10000):
     """Learned cost model A/B on the 12-patch grid network (2^24 free entries):
     train the MLP on per-step device times of random contraction orders of
     five other seeds of the same workload family, then plan seed 0 with the
     float64-roofline model (exact dynamic programming over subsets) and with
-    the MLP ranking 2000 randomized candidates; report both measured times."""
+    the MLP ranking `candidates` randomized orders (the roofline order among
+    them); report plan time, execute time, their sum, and each plan's error
+    against the float64 form of the full slice (the float64 form is checked
+    against the oracle in the GPU tests)."""
     from workloads import synthetic
     rng = np.random.default_rng(7)
     feats, secs = [], []
@@ -170,27 +173,37 @@ def costmodel_study(tqc, torch):
                 feats.append(row)
                 secs.append(max(ph[2 + i], 1e-4) * 1e-3)
             del plan, out
+        print(f"# cost model: timed orders of seed {seed} ({len(secs)} rows)", file=sys.stderr, flush=True)
     model = tqc.CostModel(seed=11)
     losses = model.train(np.array(feats), np.array(secs), epochs=80, batch=64, lr=2e-3)
     spec = synthetic.grid_patch_network(seed=0)
     fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
     net = tqc.Network.from_spec(spec)
+    ref_plan = tqc.Plan(net, precision="fp64", out_dtype="f64", fixed=fixed)
+    ref = ref_plan.output_tensor()
+    ref_plan.execute(ref)
+    torch.cuda.synchronize()
+    refmax = ref.abs().max().item()
     res = {}
     for name, kw in (("roofline_dp", dict(cost="flopbyte")),
-                     ("mlp_2000", dict(cost="mlp", cost_model=model, num_candidates=2000, seed=3))):
+                     (f"mlp_{candidates}", dict(cost="mlp", cost_model=model, num_candidates=candidates,
+                                                 seed=3))):
+        t0 = time.perf_counter()
         plan = tqc.Plan(net, precision="fp32", out_dtype="f64", fixed=fixed, **kw)
+        plan_ms = (time.perf_counter() - t0) * 1e3
         out = plan.output_tensor()
-        res[name] = {"ms": _median_ms(plan, out, 15), "predicted_ms": plan.stats["predicted_seconds"] * 1e3,
-                     "plan_ms": plan.stats["plan_seconds"] * 1e3, "flops": plan.stats["flops"],
-                     "bytes": plan.stats["bytes"]}
-        if name == "roofline_dp":
-            ref = out.clone()
-        else:
-            res[name]["max_abs_diff_vs_dp"] = (out - ref).abs().max().item()
+        ms = _median_ms(plan, out, 15)
+        res[name] = {"execute_ms": ms, "plan_ms": plan_ms, "end_to_end_ms": plan_ms + ms,
+                     "predicted_ms": plan.stats["predicted_seconds"] * 1e3, "flops": plan.stats["flops"],
+                     "bytes": plan.stats["bytes"],
+                     "rel_err_vs_fp64": (out - ref).abs().max().item() / refmax}
+        print(f"# {name}: plan {plan_ms:.1f} ms, execute {ms:.3f} ms", file=sys.stderr, flush=True)
         del plan
-    return {"study": "costmodel", "workload": spec.meta["name"], "train_rows": len(secs),
-            "train_loss_first_last": [float(losses[0]), float(losses[-1])], "plans": res,
-            "speedup_mlp_over_dp": res["roofline_dp"]["ms"] / res["mlp_2000"]["ms"]}
+    mlp = res[f"mlp_{candidates}"]
+    return {"study": "costmodel", "workload": spec.meta["name"], "candidates": candidates,
+            "train_rows": len(secs), "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+            "plans": res, "execute_speedup_mlp_over_dp": res["roofline_dp"]["execute_ms"] / mlp["execute_ms"],
+            "end_to_end_speedup_mlp_over_dp": res["roofline_dp"]["end_to_end_ms"] / mlp["end_to_end_ms"]}
 
 
 def _batch_job(i):
@@ -252,7 +265,9 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
     plans = [tqc.Plan(net, precision=form, out_dtype=dt, tile_policy=1) for net in nets]
     outs = [p.output_tensor() for p in plans]
     runs = {}
+    probs = float(sum(o.numel() for o in outs))
     for name, kw in (("graph_4streams", dict(use_graph=True, streams=4)),
+                     ("graph_8streams", dict(use_graph=True, streams=8)),
                      ("sequential_plain", dict(use_graph=False, streams=1))):
         mj = tqc.Multi(plans, outs=outs, **kw)
         timed = tqc.Multi(plans, outs=outs, timed=True, **kw)
@@ -271,7 +286,7 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
         st, en = timed.job_times()
         batch_ms = float(np.median(ms))
         runs[name] = {"batch_ms": batch_ms, "batch_ms_all": [round(x, 4) for x in ms],
-                      "jobs_per_s": num_jobs / batch_ms * 1e3,
+                      "jobs_per_s": num_jobs / batch_ms * 1e3, "probs_per_s": probs / batch_ms * 1e3,
                       "per_job_ms": _pcts(en - st), "completion_ms": _pcts(en),
                       "timed_batch_ms": float(en.max())}
         print(f"# {name}: {batch_ms:.3f} ms per batch", file=sys.stderr, flush=True)

@@ -141,3 +141,29 @@ def entries_variable_elimination(net, xs, batch=32, tensors=None, order=None):
             res = res * arr
         out[b0:b0 + B] = res
     return out * (0.5 ** K)
+
+
+def restrict_fixed(net, fixed, tensors=None):
+    """Pauli-basis tensors of ``net`` with the qubits in ``fixed`` (qubit ->
+    bit) held at their values: each tensor keeps the columns that agree with
+    them, and the remaining outputs are renumbered by rank among the free
+    qubits (ascending).  Evaluating Eq. (1) on the result at y gives P(x) for
+    the x that agrees with ``fixed`` and carries y on the free qubits, so
+    global indices wider than 64 bits never have to be formed.  Returns
+    (tensors, number of free qubits)."""
+    tens = tensors if tensors is not None else network_pauli_tensors(net)
+    free = [q for q in range(net.n) if q not in fixed]
+    rank = {q: i for i, q in enumerate(free)}
+    out = []
+    for cut_ids, outs, T in tens:
+        keep = [t for t, q in enumerate(outs) if q not in fixed]
+        base = 0
+        for t, q in enumerate(outs):
+            if q in fixed:
+                base |= int(fixed[q]) << t
+        cols = np.full(1 << len(keep), base, dtype=np.int64)
+        y = np.arange(1 << len(keep), dtype=np.int64)
+        for i, t in enumerate(keep):
+            cols |= ((y >> i) & 1) << t
+        out.append((list(cut_ids), [rank[outs[t]] for t in keep], T[:, cols]))
+    return out, len(free)

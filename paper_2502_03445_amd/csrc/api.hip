@@ -190,20 +190,27 @@ static std::mutex &scratch_mutex();
 // Separable transform of a raw tensor with at least kPassMinCuts cuts: each
 // pass reads the previous layout and writes the next, alternating between
 // two scratch buffers of `scr_bytes` each so that the last pass lands in dst.
-static void transform_passes(const TensorIn &t, double *dst, double *s0, double *s1, uint64_t scr_bytes,
-                             hipStream_t s) {
+// Appends pass i of the tensor to levels[i]; passes of one level (of
+// different tensors) share a launch, and levels run in order.
+static void schedule_passes(const TensorIn &t, double *dst, double *s0, double *s1, uint64_t scr_bytes,
+                            std::vector<std::vector<TransformPassArgs>> &levels) {
   const TransformSchedule sc = transform_schedule(t);
   const int P = (int)sc.passes.size();
   if (P > 1 && sc.max_intermediate * 8 > scr_bytes) fail(TQC_ERR_INTERNAL, "transform scratch too small");
+  if ((int)levels.size() < P) levels.resize(P);
   const double *in = t.dev_raw;
   for (int i = 0; i < P; ++i) {
     TransformPassArgs a = sc.passes[i];
     double *out = i == P - 1 ? dst : ((P - 2 - i) % 2 == 0 ? s0 : s1);
     a.in = in;
     a.out = out;
-    HIP_OK(launch_transform_pass(a, s));
+    levels[i].push_back(a);
     in = out;
   }
+}
+
+static void launch_levels(const std::vector<std::vector<TransformPassArgs>> &levels, hipStream_t s) {
+  for (const auto &lv : levels) HIP_OK(launch_transform_passes(lv.data(), (int)lv.size(), s));
 }
 
 static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
@@ -211,7 +218,9 @@ static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
     const uint64_t b = (transform_schedule(t).max_intermediate * 8 + 255) & ~uint64_t(255);
     std::lock_guard<std::mutex> lk(scratch_mutex());
     char *sp = (char *)get_scratch(2 * b, s);
-    transform_passes(t, out, (double *)sp, (double *)(sp + b), b, s);
+    std::vector<std::vector<TransformPassArgs>> levels;
+    schedule_passes(t, out, (double *)sp, (double *)(sp + b), b, levels);
+    launch_levels(levels, s);
     return;
   }
   TransformArgs a = make_transform_args(t, out);
@@ -322,6 +331,7 @@ static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
   Network &net = *p->net;
   const int m = net.m;
   HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
+  std::vector<AbsMaxArgs> all(m);
   for (int j = 0; j < m; ++j) {
     const TensorIn &t = net.t[j];
     PackArgs pa = make_pack_args(p, j, nullptr, nullptr, nullptr, 0, 0);
@@ -342,8 +352,9 @@ static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
         a.inpos[a.nbits++] = o + 2 * (c - 1 - i);
         a.inpos[a.nbits++] = o + 2 * (c - 1 - i) + 1;
       }
-    HIP_OK(launch_absmax(a, s));
+    all[j] = a;
   }
+  HIP_OK(launch_absmax(all.data(), m, s));
   HIP_OK(launch_scale_exponents(sb.maxbits, m, net.K, sb.exps, sb.root_scale, s));
 }
 
@@ -389,6 +400,10 @@ static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root
   g.ln = st.ln;
   g.lk = st.lk;
   g.kpad = st.kpad_log2;
+  if (p->splitk_bytes) {
+    g.partial = (double *)((char *)p->ws + p->splitk_off);
+    g.partial_bytes = p->splitk_bytes;
+  }
   if (st.lm > kMaxBits || st.ln > kMaxBits) fail(TQC_ERR_UNSUPPORTED, "step too large");
   for (int i = 0; i < st.lm; ++i) g.posM[i] = (uint8_t)st.posM[i];
   for (int i = 0; i < st.ln; ++i) g.posN[i] = (uint8_t)st.posN[i];
@@ -460,13 +475,18 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
     // tensors with several cuts: separable passes; the rest: the per-entry
     // kernel, up to four tensors per launch
     std::vector<TransformArgs> ta;
-    double *s0 = (double *)((char *)p->ws + p->tscr_offset);
-    double *s1 = (double *)((char *)p->ws + p->tscr_offset + p->tscr_bytes);
-    for (auto &t : net.t) {
+    std::vector<std::vector<TransformPassArgs>> levels;
+    for (int j = 0; j < m; ++j) {
+      TensorIn &t = net.t[j];
       if (t.basis != TQC_BASIS_RAW) continue;
-      if ((int)t.cuts.size() >= kPassMinCuts) transform_passes(t, t.dev_pauli, s0, s1, p->tscr_bytes, s);
-      else ta.push_back(make_transform_args(t, t.dev_pauli));
+      if ((int)t.cuts.size() >= kPassMinCuts) {
+        char *b = (char *)p->ws + p->tscr_off[j];
+        schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], levels);
+      } else {
+        ta.push_back(make_transform_args(t, t.dev_pauli));
+      }
     }
+    launch_levels(levels, s);
     if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
   }
   if (tm) tm->end();
@@ -485,13 +505,15 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
   for (uint64_t sl = s0; sl < s1; ++sl) {
     const bool first = (sl == s0);
     if (tm) tm->begin(1);
+    std::vector<PackArgs> packs;
     for (int j = 0; j < m; ++j) {
       Node &nd = p->nodes[j];
       if (!first && !nd.slice_dep) continue;
       char *b = (char *)p->ws + nd.offset;
-      pack_leaf(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
-                nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pc, sl, s, sb.exps + j);
+      packs.push_back(make_pack_args(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
+                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pc, sl, sb.exps + j));
     }
+    if (!packs.empty()) HIP_OK(launch_packs(packs.data(), (int)packs.size(), s));
     if (tm) tm->end();
     for (size_t si = 0; si < p->steps.size(); ++si) {
       const Step &st = p->steps[si];

@@ -288,6 +288,10 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
   const uint64_t KP = 1ull << g.kpad;
   const uint64_t tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  // split-K: the low bits of the workgroup id pick the k range
+  const uint64_t split = g.ksplit ? (bid & ((1ull << g.ksplit) - 1)) : 0;
+  if (g.ksplit) bid >>= g.ksplit;
+  const uint64_t klen = KP >> g.ksplit, kbeg = split * klen, kend = kbeg + klen;
   uint64_t tm, tn;
   tile_of(bid, tilesM, tilesN, g.swz, tm, tn);
   const uint64_t m0 = tm * BM, n0 = tn * BN;
@@ -361,15 +365,15 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   };
 
   // float64 results (A64 with a float64 output) skip the float staging
-  const bool staged = (P != 0) && g.staged &&
+  const bool staged = (P != 0) && g.staged && !g.ksplit &&
                       (!A64 || (g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC));
 
-  load_global(0);
-  for (uint64_t k0 = 0; k0 < KP; k0 += BK) {
+  load_global(kbeg);
+  for (uint64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
     store_lds();
     __syncthreads();
-    if (k0 + BK < KP) load_global(k0 + BK);
+    if (k0 + BK < kend) load_global(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += T::kgroup) {
       if constexpr (P == 0 || P == 1) {
@@ -428,7 +432,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       }
     }
     if constexpr (A64 && P != 0) {
-      if (((k0 + BK) & 255) == 0 || k0 + BK >= KP) {
+      if (((k0 + BK) & 255) == 0 || k0 + BK >= kend) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -566,6 +570,24 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
       }
     }
     if (want_stats) finish_stats();
+    return;
+  }
+  // split-K partial results: unscaled float64, dense [split][m][n]
+  if (g.ksplit) {
+    double *part = g.partial + split * M * N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
+        const uint64_t row = m0 + wm * WM + i * 16 + rr;
+        if (row >= M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const uint64_t col = n0 + wn * WN + j * 16 + lr;
+          if (col < N) part[row * N + col] = result(i, j, r);
+        }
+      }
     return;
   }
   // direct scatter (partial tiles, float64 form): row = m0 | local row, the

@@ -43,6 +43,8 @@ struct TransformArgs {
 // preparation) and bit_in[i] (the measured bit of an upstream end); the
 // destination holds its Pauli digit at multiples of row_out[i].
 constexpr int kPassSegs = 5;
+constexpr int kPassBatch = 8;   // passes per launch
+constexpr int kPackBatch = 8;   // leaves per pack / abs-max launch
 struct TransformPassArgs {
   const double *in;
   double *out;
@@ -110,6 +112,13 @@ struct GemmArgs {
   // largest order-preserving key and float64 sum, at tile tm * tilesN + tn
   unsigned long long *tkey;
   double *tsum;
+  // split-K: with ksplit > 0 each workgroup sums one of 2^ksplit equal k
+  // ranges of one tile and writes float64 partial results to
+  // partial[(split * M + m) * N + n]; a reduction adds the splits in order
+  // and applies the epilogue.  partial_bytes bounds the split count.
+  double *partial;
+  uint64_t partial_bytes;
+  int ksplit;
 };
 
 }  // namespace tqc

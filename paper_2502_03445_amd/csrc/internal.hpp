@@ -94,8 +94,11 @@ struct Plan {
   int device = -1;
   void *ws = nullptr;
   uint64_t ws_bytes = 0;
-  uint64_t tscr_offset = 0;      // two transform scratch buffers in the workspace
-  uint64_t tscr_bytes = 0;       // bytes of each (0 = no multi-pass transform)
+  // per tensor: two transform scratch buffers in the workspace (tensors are
+  // transformed side by side, so each has its own); bytes of each, 0 = none
+  std::vector<uint64_t> tscr_off, tscr_bytes;
+  // split-K partial sums of steps whose tiles cannot fill the device
+  uint64_t splitk_off = 0, splitk_bytes = 0;
   double *acc64 = nullptr;       // float64 accumulator for sliced runs (when out is f32)
   void *scale_buf = nullptr;     // per-leaf |max| bits, exponents, output scale
   void *stats_buf = nullptr;     // per-tile statistics of the root step + top-k scratch

@@ -34,6 +34,18 @@ __global__ void __launch_bounds__(256) pack_kernel(PackArgs a) {
     pack_elem(a, e);
 }
 
+// several leaf operands per launch (blockIdx.y selects the leaf)
+struct PackBatch {
+  PackArgs a[kPackBatch];
+};
+__global__ void __launch_bounds__(256) pack_multi_kernel(PackBatch pb) {
+  const PackArgs &a = pb.a[blockIdx.y];
+  const uint64_t total = 1ull << a.nbits;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    pack_elem(a, e);
+}
+
 __global__ void __launch_bounds__(256) f64_to_f32_kernel(const double *in, float *out, uint64_t n) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -53,7 +65,12 @@ __global__ void __launch_bounds__(256) scale_f64_kernel(double *buf, uint64_t n,
     buf[i] *= s;
 }
 
-__global__ void __launch_bounds__(256) absmax_kernel(AbsMaxArgs a) {
+// several leaves per launch (blockIdx.y selects the leaf)
+struct AbsMaxBatch {
+  AbsMaxArgs a[kPackBatch];
+};
+__global__ void __launch_bounds__(256) absmax_kernel(AbsMaxBatch ab) {
+  const AbsMaxArgs &a = ab.a[blockIdx.y];
   __shared__ double red[256];
   const uint64_t total = 1ull << a.nbits;
   double mx = 0.0;
@@ -83,6 +100,21 @@ __global__ void scale_exponents_kernel(const unsigned long long *maxbits, int m,
     sum += e;
   }
   *root_scale = ldexp(1.0, -K - sum);
+}
+
+// split-K reduction: entry e = m * N + n adds its 2^ksplit partial sums in
+// split order (float64), then stores like the GEMM epilogue
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g) {
+  const uint64_t MN = 1ull << (g.lm + g.ln);
+  const int S = 1 << g.ksplit;
+  const double scale = g.dscale ? *g.dscale : g.scale;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < MN;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int sp = 0; sp < S; ++sp) v += g.partial[sp * MN + e];
+    const uint64_t addr = scatter_bits(e >> g.ln, g.posM, g.lm) + scatter_bits(e & ((1ull << g.ln) - 1), g.posN, g.ln);
+    store_out(g, scale, addr, v);
+  }
 }
 
 template <int P, int BM, int BN, int BK, bool A64>
@@ -133,7 +165,7 @@ __device__ inline void cut_map(const double *v, double *p) {
 // Consecutive threads take consecutive innermost coordinates, so every
 // load and store instruction of a wave covers consecutive addresses.
 template <int G, bool UA, bool UB>
-__global__ void __launch_bounds__(256) transform_pass_kernel(TransformPassArgs a) {
+__device__ inline void pass_body(const TransformPassArgs &a) {
   constexpr int NA = UA ? 6 : 4;
   constexpr int NB = G == 2 ? (UB ? 6 : 4) : 1;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -198,19 +230,38 @@ __global__ void __launch_bounds__(256) transform_pass_kernel(TransformPassArgs a
   }
 }
 
-hipError_t launch_transform_pass(const TransformPassArgs &a, hipStream_t s) {
-  if (a.nfree == 0) return hipSuccess;
-  if (a.nseg < 1 || a.nseg > kPassSegs || a.g < 1 || a.g > 2) return hipErrorInvalidValue;
-  const dim3 grid(grid_for(a.nfree)), block(256);
+// several passes per launch (blockIdx.y selects the pass; one pass of each
+// of several tensors): the variant is uniform over a workgroup
+struct PassBatch {
+  TransformPassArgs a[kPassBatch];
+};
+__global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
+  const TransformPassArgs &a = pb.a[blockIdx.y];
   if (a.g == 1) {
-    if (a.up[0]) hipLaunchKernelGGL((transform_pass_kernel<1, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((transform_pass_kernel<1, false, false>), grid, block, 0, s, a);
+    if (a.up[0]) pass_body<1, true, false>(a);
+    else pass_body<1, false, false>(a);
   } else if (a.up[0]) {
-    if (a.up[1]) hipLaunchKernelGGL((transform_pass_kernel<2, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((transform_pass_kernel<2, true, false>), grid, block, 0, s, a);
+    if (a.up[1]) pass_body<2, true, true>(a);
+    else pass_body<2, true, false>(a);
   } else {
-    if (a.up[1]) hipLaunchKernelGGL((transform_pass_kernel<2, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((transform_pass_kernel<2, false, false>), grid, block, 0, s, a);
+    if (a.up[1]) pass_body<2, false, true>(a);
+    else pass_body<2, false, false>(a);
+  }
+}
+
+hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s) {
+  for (int i = 0; i < n; ++i)
+    if (args[i].nseg < 1 || args[i].nseg > kPassSegs || args[i].g < 1 || args[i].g > 2)
+      return hipErrorInvalidValue;
+  for (int i0 = 0; i0 < n; i0 += kPassBatch) {
+    PassBatch pb{};
+    const int cnt = n - i0 < kPassBatch ? n - i0 : kPassBatch;
+    uint64_t most = 1;
+    for (int i = 0; i < cnt; ++i) {
+      pb.a[i] = args[i0 + i];
+      most = args[i0 + i].nfree > most ? args[i0 + i].nfree : most;
+    }
+    hipLaunchKernelGGL(transform_pass_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, pb);
   }
   return hipGetLastError();
 }
@@ -246,10 +297,33 @@ hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s) {
-  uint64_t total = 1ull << a.nbits;
-  unsigned g = grid_for(total, 1024);
-  hipLaunchKernelGGL(absmax_kernel, dim3(g), dim3(256), 0, s, a);
+hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += kPackBatch) {
+    AbsMaxBatch ab{};
+    const int cnt = n - i0 < kPackBatch ? n - i0 : kPackBatch;
+    uint64_t most = 1;
+    for (int i = 0; i < cnt; ++i) {
+      ab.a[i] = args[i0 + i];
+      const uint64_t total = 1ull << args[i0 + i].nbits;
+      most = total > most ? total : most;
+    }
+    hipLaunchKernelGGL(absmax_kernel, dim3(grid_for(most, 1024), cnt), dim3(256), 0, s, ab);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += kPackBatch) {
+    PackBatch pb{};
+    const int cnt = n - i0 < kPackBatch ? n - i0 : kPackBatch;
+    uint64_t most = 1;
+    for (int i = 0; i < cnt; ++i) {
+      pb.a[i] = args[i0 + i];
+      const uint64_t total = 1ull << args[i0 + i].nbits;
+      most = total > most ? total : most;
+    }
+    hipLaunchKernelGGL(pack_multi_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, pb);
+  }
   return hipGetLastError();
 }
 
@@ -280,6 +354,32 @@ hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s) {
   return hipGetLastError();
 }
 
+static int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// Split count (log2) of a step: only when its tiles cannot fill the device
+// and k is long; every split keeps at least 256 k, the splits of all tiles
+// give about two workgroups per CU, and the partial buffer bounds the count.
+// Steps that write tile statistics are never split.
+static int splitk_log2(const GemmArgs &g, uint64_t tiles, uint64_t mn) {
+  if (!g.partial || g.tkey || g.kpad < 9) return 0;
+  const uint64_t cus = (uint64_t)device_cus();
+  if (cus == 0 || tiles >= cus) return 0;
+  int ks = 0;
+  while ((tiles << ks) < 2 * cus && ks < g.kpad - 8) ++ks;
+  while (ks > 0 && (mn << ks) * 8 > g.partial_bytes) --ks;
+  return ks;
+}
+
 template <int P, int BM, int BN, int BK>
 static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
   using S = GemmShape<P, BM, BN, BK>;
@@ -289,10 +389,14 @@ static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
   prepare_gemm_args(g, P, BM, BN);
   static_assert(S::LDS_BYTES <= 81920, "two workgroups per CU need at most 80 KiB of LDS each");
-  if (P != 0 && g.lk > 8)
-    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+  g.ksplit = splitk_log2(g, tiles, M * N);
+  const uint64_t grid = tiles << g.ksplit;
+  if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+  if (P != 0 && g.kpad - g.ksplit > 8)
+    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, true>), dim3((unsigned)grid), dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, false>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<P, BM, BN, BK, false>), dim3((unsigned)grid), dim3(256), 0, s, g);
+  if (g.ksplit) hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(M * N)), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

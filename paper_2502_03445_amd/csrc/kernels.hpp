@@ -14,9 +14,10 @@ hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *dst, hipStream_t s);
-hipError_t launch_transform_pass(const TransformPassArgs &a, hipStream_t s);
+hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s);  // n passes
+hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s);                    // n leaves
 int root_gemm_warm();  // caches the device's CU count (call outside graph capture)
-hipError_t launch_absmax(const AbsMaxArgs &a, hipStream_t s);
+hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s);                  // n leaves
 hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
                                   double *root_scale, hipStream_t s);
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32

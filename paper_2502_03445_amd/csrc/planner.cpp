@@ -362,15 +362,30 @@ static void assemble(Plan &p) {
   // float64 Pauli tensors of raw inputs (transform output)
   for (int j = 0; j < m; ++j)
     if (net.t[j].basis == TQC_BASIS_RAW) off = align(off + net.t[j].pauli_entries() * 8);
-  // ping-pong buffers of the multi-pass transform (shared by the tensors,
-  // which are transformed one after another)
-  uint64_t inter = 0;
+  // ping-pong buffers of the multi-pass transform, one pair per tensor
+  p.tscr_off.assign(m, 0);
+  p.tscr_bytes.assign(m, 0);
   for (int j = 0; j < m; ++j)
-    if (net.t[j].basis == TQC_BASIS_RAW && (int)net.t[j].cuts.size() >= kPassMinCuts)
-      inter = std::max(inter, transform_schedule(net.t[j]).max_intermediate);
-  p.tscr_bytes = inter ? align(inter * 8) : 0;
-  p.tscr_offset = off;
-  off += 2 * p.tscr_bytes;
+    if (net.t[j].basis == TQC_BASIS_RAW && (int)net.t[j].cuts.size() >= kPassMinCuts) {
+      p.tscr_bytes[j] = align(transform_schedule(net.t[j]).max_intermediate * 8);
+      p.tscr_off[j] = off;
+      off += 2 * p.tscr_bytes[j];
+    }
+  // split-K partial sums: the most any step may use on a 256-CU device with
+  // its largest (128x128) tile, the case with the fewest tiles
+  uint64_t pk = 0;
+  for (const Step &st : p.steps) {
+    if (st.kpad_log2 < 9) continue;
+    const uint64_t M = 1ull << st.lm, N = 1ull << st.ln;
+    const uint64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    if (tiles >= 256) continue;
+    int ks = 0;
+    while ((tiles << ks) < 512 && ks < st.kpad_log2 - 8) ++ks;
+    pk = std::max(pk, (M * N << ks) * 8);
+  }
+  p.splitk_bytes = align(pk);
+  p.splitk_off = off;
+  off += p.splitk_bytes;
   for (size_t i = 0; i < p.nodes.size(); ++i) {
     Node &nd = p.nodes[i];
     nd.rows = 1ull << (nd.labels.size() - nd.log2k);

@@ -67,3 +67,27 @@ def test_mlp_ranked_plan_is_correct(tmp_path):
     assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
     assert plan.stats["predicted_seconds"] > 0
     assert base.stats["num_steps"] == plan.stats["num_steps"]
+
+
+@pytest.mark.parametrize("form,cost", [("fp64", "flopbyte"), ("fp32", "flopbyte"), ("fp32", "random")])
+def test_grid_patch_slice_matches_oracle(form, cost):
+    # the 12-patch grid network (120 qubits, 40 cuts, 96 fixed): 2^24 free
+    # entries against the oracle on sampled and top entries
+    from oracle.reconstruct import entries_variable_elimination, restrict_fixed
+    spec = synthetic.grid_patch_network(seed=0)
+    fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+    net = tqc.Network.from_spec(spec)
+    kw = {} if cost == "flopbyte" else {"cost": "mlp", "cost_model": tqc.CostModel(seed=5),
+                                        "num_candidates": 200, "seed": 9}
+    plan = tqc.Plan(net, precision=form, out_dtype="f64", fixed=fixed, **kw)
+    got = plan.execute().cpu().numpy()
+    tens, nfree = restrict_fixed(spec, fixed)
+    assert got.shape == (1 << nfree,)
+    ys = np.random.default_rng(17).choice(1 << nfree, 192, replace=False)
+    ys = np.unique(np.concatenate([ys, np.argsort(np.abs(got))[-16:]])).astype(np.uint64)
+    ref = entries_variable_elimination(spec, ys, tensors=tens)
+    err = np.abs(got[ys.astype(np.int64)] - ref).max()
+    # float64: 1e-12 absolute is vacuous at these magnitudes (max P ~ 1e-8),
+    # so the relative bound is asserted as well
+    assert err <= 1e-12
+    assert err <= (1e-11 if form == "fp64" else 1e-6) * np.abs(ref).max(), err / np.abs(ref).max()

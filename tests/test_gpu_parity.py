@@ -116,6 +116,56 @@ def test_random_networks(case, form):
     assert ok, (CASES[case], form, e, P.steps)
 
 
+# steps whose tiles cannot fill the device and whose k is long run split
+# over k (float64 partial sums, added in a fixed order)
+SPLITK_CASES = [
+    ((2, 8, [3, 3]), None),        # 8x8 output, K = 65536: 256 splits of one tile
+    ((2, 6, [8, 7]), None),        # 256x128, K = 4096: two 128 tiles, 16 splits
+    ((3, 9, [3, 3, 4]), None),     # a long-k step inside a three-tensor tree
+    ((3, 10, [3, 3, 4]), [0]),     # sliced: a split final step accumulates across slices
+]
+
+
+# Per-entry rounding scale of the sum: A(x) = 2^-K sum_sigma prod_j |T_j|.
+# These synthetic networks cancel heavily (A / max|P| ~ 10^3 for the sliced
+# case), so the reduced forms are held to their arithmetic's bound,
+# |error(x)| <= gamma * A(x): a 256-term float32 chain (gamma = 2^-16) for
+# fp32 / bf16x6 and 2^-16 products for bf16x3 (gamma = 2^-12).  A wrong split
+# (a k range dropped or added twice) errs by the order of P itself.
+# (Checked on the CPU: rounding the exact result to float32 alone reaches
+# err / A = 0.0106 on case 1, all of it in entries below 2^-126.)
+GAMMA = {"fp32": 2.0 ** -16, "bf16x6": 2.0 ** -16, "bf16x3": 2.0 ** -12}
+_SPLITK_REF = {}
+
+
+def _splitk_oracle(case, spec):
+    if case not in _SPLITK_REF:
+        tens = network_pauli_tensors(spec)
+        xs = np.arange(1 << spec.n, dtype=np.uint64)
+        ref = entries_variable_elimination(spec, xs, tensors=tens)
+        A = entries_variable_elimination(spec, xs, tensors=[(c, o, np.abs(t)) for c, o, t in tens])
+        _SPLITK_REF[case] = (ref, A)
+    return _SPLITK_REF[case]
+
+
+@pytest.mark.parametrize("case", range(len(SPLITK_CASES)))
+@pytest.mark.parametrize("form", FORMS)
+def test_split_k_steps(case, form):
+    (m, K, outs), sliced = SPLITK_CASES[case]
+    spec = synthetic.random_network(m, K, outs, seed=1300 + case)
+    got, P = run(spec, precision=form, sliced=sliced)
+    assert any(st["log2_k"] >= 9 for st in P.steps)
+    ref, A = _splitk_oracle(case, spec)
+    if form == "fp64":
+        ok, e = tol_ok(form, got, ref)
+        assert ok, (SPLITK_CASES[case], e, P.steps)
+        return
+    # plus the float32 output's own rounding: entries below 2^-126 (this
+    # Dirichlet(0.1) data has some) are stored at subnormal spacing 2^-149
+    err = np.abs(got - ref)
+    assert np.all(err <= GAMMA[form] * A + 2.0 ** -149), (SPLITK_CASES[case], form, (err / A).max(), P.steps)
+
+
 def test_orders_agree_fp64():
     spec = synthetic.random_network(4, 6, [3, 3, 3, 3], seed=77)
     orders = [[(0, 1), (4, 2), (5, 3)], [(2, 3), (0, 1), (4, 5)], [(3, 1), (4, 0), (5, 2)]]

@@ -254,3 +254,22 @@ def test_mlp_oracle_gradients_match_finite_differences():
     # a planted mistake (ReLU gate dropped in the first layer) is caught
     W1, b1, W2, b2, w3, b3 = mlp.unpack(theta, F, H)
     assert np.any(X @ W1 + b1 < 0)
+
+
+def test_restrict_fixed_equals_entries_of_the_full_distribution():
+    # a fixed-qubit slice read off the full vector, entry by entry
+    from oracle.reconstruct import restrict_fixed
+    spec = synthetic.random_network(4, 6, [3, 4, 2, 3], seed=91)
+    full = full_distribution(spec)
+    fixed = {1: 1, 4: 0, 7: 1, 11: 0}
+    tens, nfree = restrict_fixed(spec, fixed)
+    assert nfree == spec.n - len(fixed)
+    free = [q for q in range(spec.n) if q not in fixed]
+    ys = np.arange(1 << nfree, dtype=np.uint64)
+    got = entries_variable_elimination(spec, ys, tensors=tens)
+    xs = np.zeros(len(ys), dtype=np.int64)
+    for q, v in fixed.items():
+        xs |= v << q
+    for i, q in enumerate(free):
+        xs |= ((ys.astype(np.int64) >> i) & 1) << q
+    assert np.abs(got - full[xs]).max() <= 1e-15 * np.abs(full).max()
