@@ -13,4 +13,5 @@ Modules
   outputs      top-k and marginals of a probability vector (Eq. (10))
   plancost     multiplication count of a contraction sequence (Sec. III-C)
   mlp          float64 MLP forward/backward for the learned cost model
+  hss          heavy state selection (Alg. 1) and its metrics (Eqs. (9)-(13))
 """
