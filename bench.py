@@ -309,6 +309,55 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
             "largest_jobs": sorted(meta, reverse=True)[:3]}
 
 
+def hss_study(tqc, torch, s_max=256):
+    """Heavy state selection (Alg. 1) with s_max = 2^8 retained states over
+    benchmark families of increasing size (GHZ, W, AQFT cut into 4, the
+    QAOA-32 network, generated batch circuits): selection time, reconstruction
+    time of the retained states, and the metrics of Eqs. (9)-(13), P_HSS,
+    r_P = P_HSS / P_HSS^max, r_|HSS| and eta, with P_HSS^max the sum of the
+    |HSS| largest entries of the full distribution (float32 form, device
+    top-k)."""
+    from workloads import batch, configs, qaoa
+    fams = [(f"ghz{n}_4", lambda n=n: configs.ghz(n, 4)) for n in (16, 24, 32)]
+    fams += [(f"w{n}_4", lambda n=n: configs.w_state(n, 4)) for n in (16, 24, 32)]
+    fams += [(f"aqft{n}_4", lambda n=n: configs.aqft(n, 4, 2)) for n in (16, 24, 32)]
+    fams += [("qaoa32_4sub_8cut", qaoa.qaoa_network)]
+    fams += [(f"batch_job{i}", lambda i=i: batch.job(i)) for i in (158, 446, 293, 399)]
+    rows = []
+    for name, make in fams:
+        spec = make()
+        net = tqc.Network.from_spec(spec)
+        net.upload()
+        torch.cuda.synchronize()
+        net.hss_select(s_max)  # first call: kernels and buffers warm
+        t0 = time.perf_counter()
+        subsets, _ = net.hss_select(s_max)
+        t_sel = (time.perf_counter() - t0) * 1e3
+        size = int(np.prod([len(x) for x in subsets]))
+        t0 = time.perf_counter()
+        sub = net.select_states(subsets)
+        t_gather = (time.perf_counter() - t0) * 1e3
+        plan = tqc.Plan(sub, precision="fp64", out_dtype="f64")
+        out = plan.output_tensor()
+        ms = _median_ms(plan, out, 5)
+        p_hss = out.sum().item()
+        full = tqc.Plan(net, precision="fp32")
+        fout = full.output_tensor()
+        full.execute(fout)
+        _, val = tqc.topk(fout, min(size, 4096))
+        p_max = val.sum().item()
+        r_size = size / 2.0 ** spec.n
+        rows.append({"workload": name, "qubits": spec.n, "cuts": spec.num_cuts, "states": size,
+                     "subset_sizes": [len(x) for x in subsets], "select_ms": t_sel, "gather_ms": t_gather,
+                     "reconstruct_ms": ms, "P_HSS": p_hss, "P_HSS_max": p_max,
+                     "r_P": p_hss / p_max if p_max else None, "r_size": r_size, "eta": p_hss / r_size})
+        print(f"# {name}: |HSS| {size}, P_HSS {p_hss:.4f}, r_P {rows[-1]['r_P']:.4f}, select {t_sel:.1f} ms",
+              file=sys.stderr, flush=True)
+        del plan, out, full, fout, sub, net
+        torch.cuda.empty_cache()
+    return {"study": "hss", "s_max": s_max, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,10 +366,11 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--study", choices=["precision", "costmodel", "batch"], default=None,
+    ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss"], default=None,
                     help="instead of the benchmark line: the precision study of the 18-cut "
                          "synthetic network (2^30 slice), the cost-model A/B on the 12-patch grid, "
-                         "or batched execution of 512 uneven reconstructions (--forms picks the form)")
+                         "batched execution of 512 uneven reconstructions (--forms picks the form), "
+                         "or heavy state selection with 2^8 states over benchmark families")
     ap.add_argument("--jobs", type=int, default=512, help="jobs of the batch study")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
@@ -342,6 +392,9 @@ def main():
         return
     if args.study == "costmodel":
         print(json.dumps(costmodel_study(tqc, torch)))
+        return
+    if args.study == "hss":
+        print(json.dumps(hss_study(tqc, torch)))
         return
     if args.study == "batch":
         for form in args.forms.split(","):

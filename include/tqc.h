@@ -247,6 +247,36 @@ tqc_status tqc_execute_summary(tqc_plan_t plan, void *out, uint64_t out_bytes, i
                                uint64_t *top_idx, double *top_val, double *total,
                                double *phase_ms, int32_t num_phases, void *stream);
 
+/* ------------------------------------------------- heavy state selection
+ * Sec. V, Alg. 1.  tqc_hss_select computes, for every tensor j and every
+ * state i of its output qubits, the L2 norm of column i of its Pauli-basis
+ * tensor over all rows (edge permutations), in float64 on the device
+ * (deterministic order).  Every tensor starts with its heaviest state (ties:
+ * smaller i); the other (j, i) join in descending norm order (ties: smaller
+ * j, then smaller i) while the product of the subset sizes is below s_max, so
+ * the product can exceed s_max by the last state added (at most twofold).
+ * Output (host memory): counts[j] = subset size (num_tensors entries);
+ * states = the subsets, tensor by tensor, ascending, at most states_cap
+ * entries (sum_j 2^o_j always suffices); norms (optional, NULL to skip) =
+ * every column norm, tensor by tensor, at most norms_cap entries.  Waits for
+ * `stream`.  Errors: INVALID_ARG, SHAPE (a capacity too small), DEVICE.
+ *
+ * tqc_network_select_states makes a new network (device-resident, Pauli
+ * basis) whose tensor j keeps columns states_j (counts[j] ascending states
+ * of its output qubits, concatenated as tqc_hss_select gives them) padded
+ * with zero columns to 2^b_j, b_j = ceil(log2 counts[j]); its b_j output
+ * qubits come after those of tensors 0..j-1.  Contracting it (any plan,
+ * form or slicing) gives P at the retained product states: entry
+ * sum_j y_j 2^(b_0 + .. + b_{j-1}) is P of the state whose tensor-j output
+ * bits are states_j[y_j]; entries with some y_j >= counts[j] are exactly
+ * zero.  The source network is only read; destroy the new one with
+ * tqc_network_destroy.  Errors: INVALID_ARG (counts out of range, states
+ * not ascending or out of range), OUT_OF_MEMORY, DEVICE. */
+tqc_status tqc_hss_select(tqc_network_t net, uint64_t s_max, int32_t *counts, int32_t *states,
+                          uint64_t states_cap, double *norms, uint64_t norms_cap, void *stream);
+tqc_status tqc_network_select_states(tqc_network_t net, const int32_t *counts, const int32_t *states,
+                                     void *stream, tqc_network_t *out);
+
 /* --------------------------------------------------------------- multi-job
  * Many independent reconstructions replayed as one HIP graph (batched
  * execution for serving; the paper runs one reconstruction at a time).

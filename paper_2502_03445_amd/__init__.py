@@ -118,6 +118,8 @@ def _declare(L):
         "tqc_multi_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64), i32, i32,
                              i32, vp, ctypes.POINTER(vp)],
         "tqc_multi_execute": [vp, vp],
+        "tqc_hss_select": [vp, u64, _i32p, _i32p, u64, _dp, u64, vp],
+        "tqc_network_select_states": [vp, _i32p, _i32p, vp, ctypes.POINTER(vp)],
         "tqc_multi_job_times": [vp, _dp, _dp],
         "tqc_plan_autotune": [vp, vp, u64, i32, vp],
         "tqc_autotune_save": [ctypes.c_char_p],
@@ -233,6 +235,44 @@ class Network:
         _check(lib().tqc_network_pauli_tensor(self.handle, int(j), ctypes.c_void_p(out.data_ptr()),
                                               out.numel() * 8, _stream_ptr(stream)))
         return out
+
+    def hss_select(self, s_max, stream=None):
+        """Heavy state selection (Alg. 1): (subsets, norms), one int32 array of
+        ascending output states and one float64 array of column norms per
+        tensor."""
+        widths = [1 << o for _, o in self.shapes]
+        counts = (ctypes.c_int32 * self.m)()
+        states = (ctypes.c_int32 * sum(widths))()
+        norms = (ctypes.c_double * sum(widths))()
+        _check(lib().tqc_hss_select(self.handle, int(s_max), ctypes.cast(counts, _i32p),
+                                    ctypes.cast(states, _i32p), sum(widths), ctypes.cast(norms, _dp),
+                                    sum(widths), _stream_ptr(stream)))
+        st, nv = np.array(states[:]), np.array(norms[:])
+        subsets, out_norms, a, b = [], [], 0, 0
+        for j in range(self.m):
+            subsets.append(st[a:a + counts[j]].astype(np.int32))
+            out_norms.append(nv[b:b + widths[j]])
+            a += counts[j]
+            b += widths[j]
+        return subsets, out_norms
+
+    def select_states(self, subsets, stream=None):
+        """The network restricted to the given output states of each tensor
+        (zero-padded to powers of two); see tqc_network_select_states."""
+        counts = _i32arr([len(x) for x in subsets])
+        flat = _i32arr([int(v) for x in subsets for v in x])
+        h = ctypes.c_void_p()
+        _check(lib().tqc_network_select_states(self.handle, ctypes.cast(counts, _i32p), ctypes.cast(flat, _i32p),
+                                               _stream_ptr(stream), ctypes.byref(h)))
+        sub = Network.__new__(Network)
+        sub._keep = None
+        sub.handle = h
+        sub.bits = [max(0, int(len(x) - 1).bit_length()) for x in subsets]
+        sub.n = int(sum(sub.bits))
+        sub.m = self.m
+        sub.num_cuts = self.num_cuts
+        sub.shapes = [(c, b) for (c, _), b in zip(self.shapes, sub.bits)]
+        return sub
 
     def __del__(self):
         h = getattr(self, "handle", None)

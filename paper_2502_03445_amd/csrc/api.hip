@@ -1049,6 +1049,142 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
 }
 
 
+// ------------------------------------------------- heavy state selection
+// Sec. V, Alg. 1: per tensor, the L2 norm of every output state over all
+// edge permutations (rows of the Pauli-basis tensor), computed on the device
+// in float64; then on the host every tensor starts with its heaviest state
+// and the other states join in descending norm order (ties: smaller tensor,
+// then smaller state) while the product of the subset sizes is below s_max.
+struct DevMem {
+  void *p = nullptr;
+  explicit DevMem(size_t bytes) { HIP_OK(hipMalloc(&p, bytes ? bytes : 8)); }
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+};
+
+// device Pauli tensor of tensor j: the resident one, or transformed into `tmp`
+static const double *pauli_on_device(const TensorIn &t, std::unique_ptr<DevMem> &tmp, hipStream_t s) {
+  if (t.basis == TQC_BASIS_PAULI) return t.dev_raw;
+  tmp.reset(new DevMem(t.pauli_entries() * 8));
+  transform_tensor(t, (double *)tmp->p, s);
+  return (const double *)tmp->p;
+}
+
+static void hss_norms(Network *net, std::vector<std::vector<double>> &norms, hipStream_t s) {
+  upload(net);
+  check_device(net->device);
+  norms.assign(net->m, {});
+  for (int j = 0; j < net->m; ++j) {
+    const TensorIn &t = net->t[j];
+    const uint64_t rows = 1ull << (2 * t.cuts.size()), cols = 1ull << t.outputs.size();
+    std::unique_ptr<DevMem> tmp;
+    const double *src = pauli_on_device(t, tmp, s);
+    DevMem partial(colnorm_scratch_entries(rows, cols) * 8), dn(cols * 8);
+    HIP_OK(launch_column_norms(src, rows, cols, (double *)partial.p, (double *)dn.p, s));
+    norms[j].resize(cols);
+    HIP_OK(hipMemcpyAsync(norms[j].data(), dn.p, cols * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+}
+
+static std::vector<std::vector<int32_t>> hss_choose(const std::vector<std::vector<double>> &norms,
+                                                    uint64_t s_max) {
+  struct Cand {
+    double v;
+    int j;
+    int32_t i;
+  };
+  const int m = (int)norms.size();
+  std::vector<std::vector<int32_t>> sel(m);
+  std::vector<Cand> rest;
+  for (int j = 0; j < m; ++j) {
+    int32_t first = 0;
+    for (int32_t i = 1; i < (int32_t)norms[j].size(); ++i)
+      if (norms[j][i] > norms[j][first]) first = i;
+    sel[j].push_back(first);
+    for (int32_t i = 0; i < (int32_t)norms[j].size(); ++i)
+      if (i != first) rest.push_back({norms[j][i], j, i});
+  }
+  std::sort(rest.begin(), rest.end(), [](const Cand &a, const Cand &b) {
+    if (a.v != b.v) return a.v > b.v;
+    if (a.j != b.j) return a.j < b.j;
+    return a.i < b.i;
+  });
+  unsigned __int128 size = 1;  // stays below 2 * s_max <= 2^65
+  for (size_t pos = 0; size < s_max && pos < rest.size(); ++pos) {
+    const Cand &c = rest[pos];
+    const uint64_t k = sel[c.j].size();
+    size = size / k * (k + 1);
+    sel[c.j].push_back(c.i);
+  }
+  for (auto &v : sel) std::sort(v.begin(), v.end());
+  return sel;
+}
+
+static int ceil_log2(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+// The network restricted to chosen output states: tensor j keeps the
+// columns states_j (ascending), padded with zero columns to 2^b_j, b_j =
+// ceil(log2 |states_j|); its b_j output qubits are numbered after those of
+// tensors 0..j-1.  Contracting it gives P at every retained product state
+// (entry sum_j y_j 2^off_j holds the state whose tensor-j bits are
+// states_j[y_j]); entries with a padding index are exactly zero.
+static Network *select_states_network(Network *src, const int32_t *counts, const int32_t *states, hipStream_t s) {
+  upload(src);
+  check_device(src->device);
+  const int m = src->m;
+  std::unique_ptr<Network> net(new Network());
+  net->m = m;
+  net->K = src->K;
+  net->cuts = src->cuts;
+  net->t.resize(m);
+  int nq = 0;
+  uint64_t at = 0;
+  for (int j = 0; j < m; ++j) {
+    const TensorIn &t = src->t[j];
+    const uint64_t cols = 1ull << t.outputs.size();
+    const int32_t cnt = counts[j];
+    if (cnt < 1 || (uint64_t)cnt > cols) fail(TQC_ERR_INVALID_ARG, "tensor %d: %d states of %llu", j, cnt,
+                                              (unsigned long long)cols);
+    for (int32_t y = 0; y < cnt; ++y) {
+      const int32_t v = states[at + y];
+      if (v < 0 || (uint64_t)v >= cols || (y > 0 && v <= states[at + y - 1]))
+        fail(TQC_ERR_INVALID_ARG, "tensor %d: states must be ascending and below %llu", j, (unsigned long long)cols);
+    }
+    TensorIn &d = net->t[j];
+    d.cuts = t.cuts;
+    d.up = t.up;
+    d.u = t.u;
+    d.d = t.d;
+    d.basis = TQC_BASIS_PAULI;
+    const int b = ceil_log2((uint64_t)cnt);
+    for (int i = 0; i < b; ++i) d.outputs.push_back(nq + i);
+    nq += b;
+    d.rows = 1ull << (2 * t.cuts.size());
+    d.cols = 1ull << b;
+    HIP_OK(hipMalloc((void **)&d.dev_raw, d.rows * d.cols * 8));
+    d.dev_pauli = d.dev_raw;
+    std::unique_ptr<DevMem> tmp;
+    const double *pt = pauli_on_device(t, tmp, s);
+    DevMem dstates((size_t)cnt * 4);
+    HIP_OK(hipMemcpyAsync(dstates.p, states + at, (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(launch_gather_columns(pt, d.rows, cols, (const int32_t *)dstates.p, (uint64_t)cnt, d.cols, d.dev_raw, s));
+    HIP_OK(hipStreamSynchronize(s));
+    at += cnt;
+  }
+  net->n = nq;
+  net->device = src->device;
+  net->uploaded = true;
+  return net.release();
+}
+
 // ------------------------------------------------------------- multi-job
 // Many independent reconstructions as one HIP graph: every job's plain
 // launches (transform, packs, pairwise steps, final step) are captured once,
@@ -1645,6 +1781,44 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits, 
 
 struct tqc_batch_s : Batch {};
 struct tqc_multi_s : Multi {};
+
+tqc_status tqc_hss_select(tqc_network_t netp, uint64_t s_max, int32_t *counts, int32_t *states,
+                          uint64_t states_cap, double *norms, uint64_t norms_cap, void *stream) {
+  return guarded([&] {
+    Network *net = reinterpret_cast<Network *>(netp);
+    if (!net || !counts || !states) fail(TQC_ERR_INVALID_ARG, "null argument");
+    if (s_max < 1) fail(TQC_ERR_INVALID_ARG, "s_max must be at least 1");
+    std::vector<std::vector<double>> nv;
+    hss_norms(net, nv, (hipStream_t)stream);
+    const auto sel = hss_choose(nv, s_max);
+    uint64_t total = 0, ncols = 0;
+    for (int j = 0; j < net->m; ++j) {
+      total += sel[j].size();
+      ncols += nv[j].size();
+    }
+    if (total > states_cap) fail(TQC_ERR_SHAPE, "states holds %llu entries, needs %llu",
+                                 (unsigned long long)states_cap, (unsigned long long)total);
+    if (norms && norms_cap < ncols) fail(TQC_ERR_SHAPE, "norms holds %llu entries, needs %llu",
+                                         (unsigned long long)norms_cap, (unsigned long long)ncols);
+    uint64_t at = 0, an = 0;
+    for (int j = 0; j < net->m; ++j) {
+      counts[j] = (int32_t)sel[j].size();
+      for (int32_t v : sel[j]) states[at++] = v;
+      if (norms)
+        for (double v : nv[j]) norms[an++] = v;
+    }
+  });
+}
+
+tqc_status tqc_network_select_states(tqc_network_t netp, const int32_t *counts, const int32_t *states, void *stream,
+                                     tqc_network_t *out) {
+  return guarded([&] {
+    Network *net = reinterpret_cast<Network *>(netp);
+    if (!net || !counts || !states || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    *out = reinterpret_cast<tqc_network_t>(select_states_network(net, counts, states, (hipStream_t)stream));
+  });
+}
 
 tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams, int32_t timed,

@@ -333,6 +333,77 @@ hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int 
   return hipGetLastError();
 }
 
+// ===================================================== heavy state selection
+// Column L2 norms of a Pauli tensor [rows][cols] (Alg. 1: per output state,
+// the norm over every edge permutation).  Pass 1: workgroup (x, y) sums the
+// squares of 64 columns over row chunk y (4 row lanes, fixed-order lane
+// sum); pass 2 adds the chunks in order and takes the square root.  The
+// result is deterministic.
+constexpr int kNormRows = 1024;  // rows per chunk
+__global__ void __launch_bounds__(256) colnorm_partial_kernel(const double *T, uint64_t rows, uint64_t cols,
+                                                              double *partial) {
+  __shared__ double red[4][64];
+  const uint64_t col = (uint64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane4 = threadIdx.x >> 6;
+  const uint64_t r0 = (uint64_t)blockIdx.y * kNormRows;
+  const uint64_t r1 = r0 + kNormRows < rows ? r0 + kNormRows : rows;
+  double acc = 0.0;
+  if (col < cols)
+    for (uint64_t r = r0 + lane4; r < r1; r += 4) {
+      const double v = T[r * cols + col];
+      acc += v * v;
+    }
+  red[lane4][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (lane4 == 0 && col < cols)
+    partial[(uint64_t)blockIdx.y * cols + col] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                                 red[3][threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) colnorm_final_kernel(const double *partial, uint64_t chunks, uint64_t cols,
+                                                            double *norms) {
+  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < cols; c += (uint64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (uint64_t k = 0; k < chunks; ++k) s += partial[k * cols + c];
+    norms[c] = sqrt(s);
+  }
+}
+
+uint64_t colnorm_scratch_entries(uint64_t rows, uint64_t cols) {
+  return ((rows + kNormRows - 1) / kNormRows) * cols;
+}
+
+hipError_t launch_column_norms(const double *T, uint64_t rows, uint64_t cols, double *partial, double *norms,
+                               hipStream_t s) {
+  const uint64_t chunks = (rows + kNormRows - 1) / kNormRows;
+  if (chunks > 65535 || cols == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(colnorm_partial_kernel, dim3((unsigned)((cols + 63) / 64), (unsigned)chunks), dim3(256), 0, s,
+                     T, rows, cols, partial);
+  hipLaunchKernelGGL(colnorm_final_kernel, dim3(grid_for(cols)), dim3(256), 0, s, partial, chunks, cols, norms);
+  return hipGetLastError();
+}
+
+// dst[r][y] = src[r][states[y]] for y < count, 0 for the padding columns
+// y in [count, dst_cols)
+__global__ void __launch_bounds__(256) gather_columns_kernel(const double *src, uint64_t rows, uint64_t src_cols,
+                                                             const int32_t *states, uint64_t count,
+                                                             uint64_t dst_cols, double *dst) {
+  const uint64_t total = rows * dst_cols;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = e / dst_cols, y = e - r * dst_cols;
+    dst[e] = y < count ? src[r * src_cols + (uint64_t)states[y]] : 0.0;
+  }
+}
+
+hipError_t launch_gather_columns(const double *src, uint64_t rows, uint64_t src_cols, const int32_t *states,
+                                 uint64_t count, uint64_t dst_cols, double *dst, hipStream_t s) {
+  if (count > dst_cols) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_columns_kernel, dim3(grid_for(rows * dst_cols)), dim3(256), 0, s, src, rows, src_cols,
+                     states, count, dst_cols, dst);
+  return hipGetLastError();
+}
+
 // one thread stores the device's constant-rate clock (a timestamp that
 // orders work across streams of one device)
 __global__ void stamp_kernel(unsigned long long *dst) {

@@ -14,6 +14,11 @@ hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *dst, hipStream_t s);
+uint64_t colnorm_scratch_entries(uint64_t rows, uint64_t cols);
+hipError_t launch_column_norms(const double *T, uint64_t rows, uint64_t cols, double *partial, double *norms,
+                               hipStream_t s);
+hipError_t launch_gather_columns(const double *src, uint64_t rows, uint64_t src_cols, const int32_t *states,
+                                 uint64_t count, uint64_t dst_cols, double *dst, hipStream_t s);
 hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s);  // n passes
 hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s);                    // n leaves
 int root_gemm_warm();  // caches the device's CU count (call outside graph capture)
