@@ -358,6 +358,38 @@ def hss_study(tqc, torch, s_max=256):
     return {"study": "hss", "s_max": s_max, "rows": rows}
 
 
+def ratio_study(tqc):
+    """Prior-method over tensor-network multiplication counts per output
+    state (Sec. III-C): 4^K (m - 1) for the brute-force sum of Eq. (5)
+    against the plan's own pairwise count, log10, over the workload families
+    (host only: the planner, no device work)."""
+    from workloads import batch, configs, qaoa, synthetic
+    fams = [(f"ghz{n}_4", lambda n=n: configs.ghz(n, 4)) for n in (16, 32)]
+    fams += [(f"w{n}_4", lambda n=n: configs.w_state(n, 4)) for n in (16, 32)]
+    fams += [(f"aqft{n}_4", lambda n=n: configs.aqft(n, 4, 2)) for n in (16, 32)]
+    fams += [("qaoa32_4sub_8cut", qaoa.qaoa_network), ("synthetic6_18cut", synthetic.precision_network),
+             ("grid10x12_12patch_40cut", lambda: synthetic.grid_patch_network(seed=0))]
+    rows = []
+    for name, make in fams:
+        spec = make()
+        fq = spec.meta.get("fixed_qubits")
+        fixed = dict(zip(fq, spec.meta["fixed_values"])) if fq else None
+        plan = tqc.Plan(tqc.Network.from_spec(spec), precision="fp64", out_dtype="f64", fixed=fixed)
+        prior = 4.0 ** spec.num_cuts * (len(spec.tensors) - 1)
+        tn = plan.stats["mults_per_state"]
+        rows.append({"workload": name, "tensors": len(spec.tensors), "cuts": spec.num_cuts,
+                     "k_max": plan.stats["k_max_cuts"], "log10_prior": float(np.log10(prior)),
+                     "log10_tensor_network": float(np.log10(tn)), "log10_ratio": float(np.log10(prior / tn))})
+    jobs = []
+    for i in range(64):
+        spec = batch.job(i)
+        plan = tqc.Plan(tqc.Network.from_spec(spec), precision="fp32")
+        jobs.append(np.log10(4.0 ** spec.num_cuts * (len(spec.tensors) - 1) / plan.stats["mults_per_state"]))
+    return {"study": "ratio", "rows": rows,
+            "batch_jobs_0_63_log10_ratio": {"min": float(np.min(jobs)), "median": float(np.median(jobs)),
+                                            "max": float(np.max(jobs))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,11 +398,12 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss"], default=None,
+    ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss", "ratio"], default=None,
                     help="instead of the benchmark line: the precision study of the 18-cut "
                          "synthetic network (2^30 slice), the cost-model A/B on the 12-patch grid, "
                          "batched execution of 512 uneven reconstructions (--forms picks the form), "
-                         "or heavy state selection with 2^8 states over benchmark families")
+                         "heavy state selection with 2^8 states over benchmark families, or the "
+                         "prior-method / tensor-network multiplication ratio (host only)")
     ap.add_argument("--jobs", type=int, default=512, help="jobs of the batch study")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
@@ -392,6 +425,9 @@ def main():
         return
     if args.study == "costmodel":
         print(json.dumps(costmodel_study(tqc, torch)))
+        return
+    if args.study == "ratio":
+        print(json.dumps(ratio_study(tqc)))
         return
     if args.study == "hss":
         print(json.dumps(hss_study(tqc, torch)))
