@@ -14,4 +14,5 @@ Modules
   plancost     multiplication count of a contraction sequence (Sec. III-C)
   mlp          float64 MLP forward/backward for the learned cost model
   hss          heavy state selection (Alg. 1) and its metrics (Eqs. (9)-(13))
+  cutfind      greedy graph growing cut search (Alg. 2-3, Table I), Eq. (6)
 """

@@ -230,3 +230,29 @@ def cut_shapes(circ: Circuit, gate_sub, num_subs=None, idle_sub=None):
         shapes.append({"width": len(my), "u": u, "d": sum(si in starts for si in my),
                        "outputs": len(my) - u, "gates": sum(1 for g in gate_sub if g == j)})
     return cuts, shapes
+
+
+def assign_from_partition(circ: Circuit, labels):
+    """Subcircuit of every gate from a partition of the two-qubit gates
+    (labels: gate index -> partition): a single-qubit gate joins the next
+    two-qubit gate on its wire, else the previous one; a wire without
+    two-qubit gates belongs to partition 0.  Returns (gate_sub, idle_sub,
+    number of partitions) for cut_circuit."""
+    n = circ.n
+    two = [[] for _ in range(n)]
+    for g, gate in enumerate(circ.gates):
+        if len(gate.qubits) == 2:
+            for q in gate.qubits:
+                two[q].append(g)
+    gate_sub = []
+    for g, gate in enumerate(circ.gates):
+        if len(gate.qubits) == 2:
+            gate_sub.append(int(labels[g]))
+            continue
+        q = gate.qubits[0]
+        nxt = [h for h in two[q] if h > g]
+        prv = [h for h in two[q] if h < g]
+        gate_sub.append(int(labels[nxt[0]]) if nxt else (int(labels[prv[-1]]) if prv else 0))
+    idle = [int(labels[two[q][0]]) if two[q] else 0 for q in range(n)]
+    parts = max(list(labels.values()) + [0]) + 1
+    return gate_sub, idle, parts
