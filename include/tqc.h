@@ -247,6 +247,26 @@ tqc_status tqc_execute_summary(tqc_plan_t plan, void *out, uint64_t out_bytes, i
                                uint64_t *top_idx, double *top_val, double *total,
                                double *phase_ms, int32_t num_phases, void *stream);
 
+/* ---------------------------------------------------------------- cut search
+ * Sec. VI, Alg. 2-3, Table I (host only; the step before tqc_network_create).
+ * gate_qubits holds two entries per gate in circuit order: the qubits of a
+ * two-qubit gate, or (q, -1) for a single-qubit gate.  The circuit DAG keeps
+ * one vertex per two-qubit gate and one edge per wire segment between
+ * consecutive two-qubit gates of a qubit.  Partitions grow from single gates
+ * by merging the adjacent pair with the smallest Table I cost (ties: smaller
+ * first gates) while that cost is at most q_max: for the trial union,
+ * w/w_max + s/s_max + k/k_t, where w = qubits (one per maximal run of a
+ * wire's two-qubit gates inside it), s = two-qubit gates, k = the largest
+ * number of contraction edges (cut edges of the union or of a neighbour)
+ * between the union and one of its neighbours; w > w_max or s > s_max is not
+ * allowed, k > k_t costs 4^(k - k_t) + 1 instead of k/k_t.  After a merge only
+ * the pairs touching the merged partition are costed again (Alg. 2).
+ * Output: labels[g] = partition of two-qubit gate g (0.. in order of each
+ * partition's first gate), -1 for single-qubit gates; num_parts.  The paper
+ * uses k_t = 10, q_max = 1e4.  Errors: INVALID_ARG. */
+tqc_status tqc_find_cuts(int32_t num_qubits, int32_t num_gates, const int32_t *gate_qubits, int32_t w_max,
+                         int32_t s_max, int32_t k_t, double q_max, int32_t *labels, int32_t *num_parts);
+
 /* ------------------------------------------------- heavy state selection
  * Sec. V, Alg. 1.  tqc_hss_select computes, for every tensor j and every
  * state i of its output qubits, the L2 norm of column i of its Pauli-basis

@@ -119,6 +119,7 @@ def _declare(L):
                              i32, vp, ctypes.POINTER(vp)],
         "tqc_multi_execute": [vp, vp],
         "tqc_hss_select": [vp, u64, _i32p, _i32p, u64, _dp, u64, vp],
+        "tqc_find_cuts": [i32, i32, _i32p, i32, i32, i32, ctypes.c_double, _i32p, _i32p],
         "tqc_network_select_states": [vp, _i32p, _i32p, vp, ctypes.POINTER(vp)],
         "tqc_multi_job_times": [vp, _dp, _dp],
         "tqc_plan_autotune": [vp, vp, u64, i32, vp],
@@ -523,6 +524,22 @@ class Multi:
         if h is not None and _LIB is not None:
             _LIB.tqc_multi_destroy(h)
             self.handle = None
+
+
+def find_cuts(num_qubits, gates, w_max, s_max, k_t=10, q_max=1e4):
+    """Greedy graph growing cut search (Alg. 2-3): gates is a sequence of
+    qubit tuples in circuit order; returns (labels, num_parts) with labels[g]
+    the partition of two-qubit gate g and -1 for single-qubit gates."""
+    flat = []
+    for qs in gates:
+        flat += [int(qs[0]), int(qs[1]) if len(qs) == 2 else -1]
+    g = _i32arr(flat if flat else [0])
+    n = len(gates)
+    labels = (ctypes.c_int32 * max(1, n))()
+    parts = ctypes.c_int32()
+    _check(lib().tqc_find_cuts(int(num_qubits), n, ctypes.cast(g, _i32p), int(w_max), int(s_max), int(k_t),
+                               float(q_max), ctypes.cast(labels, _i32p), ctypes.byref(parts)))
+    return np.array(labels[:n], dtype=np.int32), parts.value
 
 
 def autotune(plan, out=None, reps=3, stream=None):

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libtqc.so")
 ARCH = os.environ.get("TQC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "kernels.hip", "root.hip", "outputs.hip", "batch.hip", "costmodel.hip",
-           "planner.cpp"]
+           "planner.cpp", "cutfind.cpp"]
 
 
 def hipcc():

@@ -1782,6 +1782,16 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits, 
 struct tqc_batch_s : Batch {};
 struct tqc_multi_s : Multi {};
 
+tqc_status tqc_find_cuts(int32_t num_qubits, int32_t num_gates, const int32_t *gate_qubits, int32_t w_max,
+                         int32_t s_max, int32_t k_t, double q_max, int32_t *labels, int32_t *num_parts) {
+  return guarded([&] {
+    if (num_qubits < 1 || num_gates < 0 || (num_gates && (!gate_qubits || !labels)) || !num_parts)
+      fail(TQC_ERR_INVALID_ARG, "bad circuit arguments");
+    if (w_max < 1 || s_max < 1 || k_t < 1 || !(q_max >= 0)) fail(TQC_ERR_INVALID_ARG, "thresholds must be positive");
+    *num_parts = find_cuts(num_qubits, num_gates, gate_qubits, w_max, s_max, k_t, q_max, labels);
+  });
+}
+
 tqc_status tqc_hss_select(tqc_network_t netp, uint64_t s_max, int32_t *counts, int32_t *states,
                           uint64_t states_cap, double *norms, uint64_t norms_cap, void *stream) {
   return guarded([&] {

@@ -109,6 +109,10 @@ struct Plan {
 // planner entry
 Plan *build_plan(Network *net, const tqc_plan_options &opt);
 
+// greedy graph growing cut search; returns the number of partitions
+int find_cuts(int num_qubits, int num_gates, const int32_t *gate_qubits, int w_max, int s_max, int k_t,
+              double q_max, int32_t *labels);
+
 // shapes of the steps a contraction order produces (no layouts)
 struct StepShape {
   int lm, ln, lk, kpad, root, slice_dep, tile;
