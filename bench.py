@@ -390,6 +390,86 @@ def ratio_study(tqc):
                                             "max": float(np.max(jobs))}}
 
 
+def _cut_case(args):
+    """host worker: cut search result -> exact subcircuit tensors (or None
+    when they are too costly to simulate)"""
+    name, n, gates_kind, seed, w_max = args
+    import math as _m
+    from workloads import batch
+    from workloads.circuit import Circuit
+    from workloads.cutting import assign_from_partition, cut_circuit, cut_shapes
+    from workloads.qaoa import random_regular_graph
+    import paper_2502_03445_amd as _tqc
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    if gates_kind == "qaoa":
+        for q in range(n):
+            c.add("h", q)
+        for a, b in random_regular_graph(n, 3, rng):
+            c.add("rzz", int(a), int(b), params=(float(rng.uniform(0, _m.pi)),))
+        for q in range(n):
+            c.add("rx", q, params=(float(rng.uniform(0, _m.pi)),))
+    else:
+        for layer in range(8):
+            for q in range(n):
+                c.add(("rx", "ry", "rz")[int(rng.integers(3))], q, params=(float(rng.uniform(0, 2 * _m.pi)),))
+            for q in range(layer % 2, n - 1, 2):
+                c.add("cz", q, q + 1)
+    gates = [g.qubits for g in c.gates]
+    t0 = time.perf_counter()
+    labels, parts = _tqc.find_cuts(n, gates, w_max, 10 ** 6, 10, 1e4)
+    search_ms = (time.perf_counter() - t0) * 1e3
+    lab = {g: int(l) for g, l in enumerate(labels) if l >= 0}
+    gs, idle, m = assign_from_partition(c, lab)
+    cuts, shapes = cut_shapes(c, gs, num_subs=m, idle_sub=idle)
+    depth = []
+    for j in range(m):
+        lay = [0] * n
+        for g, gate in zip(gs, c.gates):
+            if g == j:
+                t = 1 + max(lay[q] for q in gate.qubits)
+                for q in gate.qubits:
+                    lay[q] = t
+        depth.append(max(lay))
+    info = {"workload": name, "qubits": n, "w_max": w_max, "subcircuits": m, "cuts": len(cuts),
+            "widths": [s["width"] for s in shapes], "search_ms": search_ms,
+            "qpu_inputs": [(s["u"], s["d"], s["width"], d) for s, d in zip(shapes, depth)]}
+    if n <= 32 and batch._accept(cuts, shapes):
+        return info, cut_circuit(c, gs, num_subs=m, idle_sub=idle)
+    return info, None
+
+
+def cutfind_study(tqc, torch, workers=16):
+    """Cut search (Alg. 2-3, K_t = 10, Q_max = 1e4) on QAOA (3-regular
+    graphs, p = 1) and brickwork circuits for QPUs of w_max qubits, with the
+    runtime model of Eqs. (6)-(8): T_QPU over 10 QPUs in parallel (t_g = 1e-7
+    s, t_m = 1e-6 s), T_classical = plan flops / FP32 MFMA peak, and, where the
+    subcircuit tensors are small enough to simulate exactly, the measured
+    reconstruction time of the full distribution (fp32 form)."""
+    cases = [(f"qaoa{n}_w{w}", n, "qaoa", 100 + n, w) for n in (16, 24, 32, 48, 64) for w in (10, 14)]
+    cases += [(f"brick{n}_w{w}", n, "brick", 200 + n, w) for n in (16, 24, 32) for w in (10, 14)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_cut_case, cases, chunksize=1)
+    rows = []
+    for info, spec in res:
+        t_qpu = sum(3 ** u * 4 ** d * 2 ** w * (t * 1e-7 + 1e-6) for u, d, w, t in info.pop("qpu_inputs")) / 10
+        info["T_qpu_s"] = t_qpu
+        if spec is not None:
+            net = tqc.Network.from_spec(spec)
+            plan = tqc.Plan(net, precision="fp32")
+            out = plan.output_tensor()
+            ms = _median_ms(plan, out, 5)
+            info.update({"flops": plan.stats["flops"], "T_classical_model_s": plan.stats["flops"] / MFMA_PEAK["fp32"],
+                         "reconstruct_ms": ms, "k_max": plan.stats["k_max_cuts"],
+                         "T_total_s": t_qpu + ms * 1e-3})
+            del plan, out, net
+            torch.cuda.empty_cache()
+        rows.append(info)
+        print(f"# {info['workload']}: {info['subcircuits']} subcircuits, {info['cuts']} cuts, "
+              f"search {info['search_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return {"study": "cutfind", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,12 +478,14 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss", "ratio"], default=None,
+    ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss", "ratio", "cutfind"],
+                    default=None,
                     help="instead of the benchmark line: the precision study of the 18-cut "
                          "synthetic network (2^30 slice), the cost-model A/B on the 12-patch grid, "
                          "batched execution of 512 uneven reconstructions (--forms picks the form), "
                          "heavy state selection with 2^8 states over benchmark families, or the "
-                         "prior-method / tensor-network multiplication ratio (host only)")
+                         "prior-method / tensor-network multiplication ratio (host only), or the "
+                         "cut search with the runtime model of Eqs. (6)-(8)")
     ap.add_argument("--jobs", type=int, default=512, help="jobs of the batch study")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
@@ -425,6 +507,9 @@ def main():
         return
     if args.study == "costmodel":
         print(json.dumps(costmodel_study(tqc, torch)))
+        return
+    if args.study == "cutfind":
+        print(json.dumps(cutfind_study(tqc, torch)))
         return
     if args.study == "ratio":
         print(json.dumps(ratio_study(tqc)))
