@@ -26,8 +26,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "bf16x6": 2.5e15}
-PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
+MFMA_PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "bf16x6": 2.5e15, "fp16x3": 2.5e15}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 HBM_PEAK = 8.0e12
 TOL = 1e-6
 TOPK = 1000
@@ -104,7 +104,7 @@ def precision_study(tqc, torch):
     fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
     net = tqc.Network.from_spec(spec)
     res, ref = {}, None
-    for form in ("fp64", "fp32", "bf16x6", "bf16x3"):
+    for form in ("fp64", "fp32", "bf16x6", "bf16x3", "fp16x3"):
         plan = tqc.Plan(net, precision=form, out_dtype="f64" if form == "fp64" else "f32", fixed=fixed)
         out = plan.output_tensor()
         ms = _median_ms(plan, out)
@@ -475,7 +475,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,bf16x3,bf16x6")
+    ap.add_argument("--forms", default="fp32,bf16x3,bf16x6,fp16x3")
     ap.add_argument("--sample", type=int, default=0, help="oracle entries (0 = calibrate to about 10-20 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--study", choices=["precision", "costmodel", "batch", "hss", "ratio", "cutfind"],
@@ -648,7 +648,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "bf16x6": "bf16x6 (f32 acc)",
-                  "fp64": "f64"}[chosen],
+                  "fp16x3": "fp16x3 final step, f32 pairwise steps (f32 acc)", "fp64": "f64"}[chosen],
         "data": "synthetic (seeded QAOA circuit, exact subcircuit simulation)",
         "config": {"workload": "qaoa32_regular3_p1_4sub_8cut_full_2^32",
                    "qubits": n, "subcircuits": len(spec.tensors), "cuts": spec.num_cuts,

@@ -72,8 +72,14 @@ typedef enum {
  *          RNE(a), lo = RNE(a - hi)); products hi*hi + hi*lo + lo*hi on
  *          bfloat16 MFMA with float32 accumulation.
  *   BF16X6 three-way split a = hi + mid + lo; the six products whose
- *          combined weight is above 2^-24 (hh, hm, mh, hl, mm, lh). */
-typedef enum { TQC_FP64 = 0, TQC_FP32 = 1, TQC_BF16X3 = 2, TQC_BF16X6 = 3 } tqc_precision;
+ *          combined weight is above 2^-24 (hh, hm, mh, hl, mm, lh).
+ *   FP16X3 pairwise steps as FP32; the final step's two operands are each
+ *          scaled by a power of two that puts their largest |value| in
+ *          [2^14, 2^15) and split into two float16 values (hi = RNE(a),
+ *          lo = RNE(a - hi), 22 significant bits), products hi*hi + hi*lo +
+ *          lo*hi on float16 MFMA with float32 accumulation; the scale is
+ *          undone exactly in the output epilogue. */
+typedef enum { TQC_FP64 = 0, TQC_FP32 = 1, TQC_BF16X3 = 2, TQC_BF16X6 = 3, TQC_FP16X3 = 4 } tqc_precision;
 
 /* Element type of a device probability vector. */
 typedef enum { TQC_F64 = 0, TQC_F32 = 1 } tqc_dtype;

@@ -26,7 +26,7 @@ __all__ = ["lib", "Network", "Plan", "Batch", "CostModel", "step_features", "top
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtqc.so")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
 DTYPES = {"f64": 0, "f32": 1}
 BASES = {"raw": 0, "pauli": 1}
 COST = {"flopbyte": 0, "mlp": 1}

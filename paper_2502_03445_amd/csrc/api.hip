@@ -252,10 +252,19 @@ static int out_kind_for(Prec p) {
   switch (p) {
     case Prec::F64: return OUT_F64;
     case Prec::F32: return OUT_F32;
+    case Prec::F16X3: return OUT_F32;  // pairwise steps in float32
     case Prec::BF16X3: return OUT_SPLIT2;
     default: return OUT_SPLIT3;
   }
 }
+
+// GEMM form of a step and pack form of the leaves: a float16-split plan runs
+// its pairwise steps in float32 and only its final step on float16 planes
+static int step_prec(const Plan *p, const Step &st) {
+  if (p->prec != Prec::F16X3) return int(p->prec);
+  return st.root ? 4 : 1;
+}
+static int pack_prec(const Plan *p) { return p->prec == Prec::F16X3 ? 1 : int(p->prec); }
 
 static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
                                uint64_t slice, const int *dexp = nullptr) {
@@ -318,13 +327,16 @@ struct ScaleBuf {
   unsigned long long *maxbits;
   int *exps;
   double *root_scale;
+  double *root_scale2;               // float16-split plans: root scale of the final step
+  unsigned long long *maxbits16;     // ... and the abs-max of its two operands
 };
 
 static ScaleBuf scale_buffers(Plan *p) {
   const int m = p->net->m;
   if (!p->scale_buf) HIP_OK(hipMalloc(&p->scale_buf, 256 + (size_t)m * 16));
   char *b = (char *)p->scale_buf;
-  return ScaleBuf{(unsigned long long *)(b + 256), (int *)(b + 256 + (size_t)m * 8), (double *)b};
+  return ScaleBuf{(unsigned long long *)(b + 256), (int *)(b + 256 + (size_t)m * 8), (double *)b, (double *)(b + 8),
+                  (unsigned long long *)(b + 16)};
 }
 
 static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
@@ -407,6 +419,16 @@ static GemmArgs make_gemm_args(Plan *p, const Step &st, void *root_out, int root
   if (st.lm > kMaxBits || st.ln > kMaxBits) fail(TQC_ERR_UNSUPPORTED, "step too large");
   for (int i = 0; i < st.lm; ++i) g.posM[i] = (uint8_t)st.posM[i];
   for (int i = 0; i < st.ln; ++i) g.posN[i] = (uint8_t)st.posN[i];
+  if (st.root && p->prec == Prec::F16X3) {
+    char *ha = (char *)p->ws + p->h16_off[0], *hb = (char *)p->ws + p->h16_off[1];
+    g.a0 = ha;
+    g.a1 = ha + p->h16_plane[0];
+    g.a2 = nullptr;
+    g.b0 = hb;
+    g.b1 = hb + p->h16_plane[1];
+    g.b2 = nullptr;
+    if (dscale) dscale = scale_buffers(p).root_scale2;
+  }
   if (st.root) {
     g.c0 = root_out;
     g.scale = std::ldexp(1.0, -p->net->K);
@@ -469,7 +491,6 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
                        unsigned long long *tkey = nullptr, double *tsum = nullptr) {
   Network &net = *p->net;
   const int m = net.m;
-  const int pc = int(p->prec);
   if (tm) tm->begin(0);
   {
     // tensors with several cuts: separable passes; the rest: the per-entry
@@ -511,7 +532,8 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
       if (!first && !nd.slice_dep) continue;
       char *b = (char *)p->ws + nd.offset;
       packs.push_back(make_pack_args(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
-                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pc, sl, sb.exps + j));
+                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pack_prec(p), sl,
+                                     sb.exps + j));
     }
     if (!packs.empty()) HIP_OK(launch_packs(packs.data(), (int)packs.size(), s));
     if (tm) tm->end();
@@ -526,9 +548,19 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
         g.tsum = tsum;
       }
       if (tm) tm->begin(2 + (int)si);
-      if (st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(pc, g))
-        HIP_OK(launch_root_gemm(pc, g, s));
-      else HIP_OK(launch_gemm(pc, g, st.tile, s));
+      const int sp = step_prec(p, st);
+      if (st.root && p->prec == Prec::F16X3) {
+        // float32 operands of the final step -> two float16 planes each
+        const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
+        char *ha = (char *)p->ws + p->h16_off[0], *hb = (char *)p->ws + p->h16_off[1];
+        HIP_OK(launch_f16_split((const float *)((char *)p->ws + na.offset), na.elems(), (uint16_t *)ha,
+                                (uint16_t *)(ha + p->h16_plane[0]), (const float *)((char *)p->ws + nb.offset),
+                                nb.elems(), (uint16_t *)hb, (uint16_t *)(hb + p->h16_plane[1]), sb.maxbits16,
+                                sb.root_scale, sb.root_scale2, s));
+      }
+      if (st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(sp, g))
+        HIP_OK(launch_root_gemm(sp, g, s));
+      else HIP_OK(launch_gemm(sp, g, st.tile, s));
       if (tm) tm->end();
     }
     first_done = true;
@@ -707,6 +739,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
     Plan *p = plans[j];
     if (!p || !outs || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
     if (int(p->prec) != b->prec) fail(TQC_ERR_INVALID_ARG, "job %d: all jobs need one precision", j);
+    if (p->prec == Prec::F16X3) fail(TQC_ERR_UNSUPPORTED, "job %d: float16-split plans are not batched", j);
     if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not batched", j);
     const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
     if (out_bytes && out_bytes[j] < need) fail(TQC_ERR_SHAPE, "job %d: output too small", j);
@@ -1027,9 +1060,9 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
     for (int tile = 0; tile < 3; ++tile) {
       const int bm = tile_bm(tile);
       if (tile != 2 && (st.lm < 5 || st.ln < 5) && bm > 32) continue;
-      HIP_OK(launch_gemm(int(p->prec), g, tile, s));  // warm
+      HIP_OK(launch_gemm(step_prec(p, st), g, tile, s));  // warm
       HIP_OK(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) HIP_OK(launch_gemm(int(p->prec), g, tile, s));
+      for (int r = 0; r < reps; ++r) HIP_OK(launch_gemm(step_prec(p, st), g, tile, s));
       HIP_OK(hipEventRecord(e1, s));
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0;
@@ -1378,7 +1411,7 @@ static void shape_features(const StepShape &sh, Prec prec, tqc_dtype out_dtype, 
   f[6] = (float)std::log2(bytes);
   f[7] = (float)sh.root;
   f[8] = (float)std::log2(outb);
-  f[9 + int(prec)] = 1.f;
+  f[9 + (prec == Prec::F16X3 ? int(Prec::BF16X3) : int(prec))] = 1.f;  // same MFMA cost class
   f[13 + std::min(2, std::max(0, sh.tile))] = 1.f;
 }
 

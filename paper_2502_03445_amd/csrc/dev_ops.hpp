@@ -15,6 +15,18 @@ namespace tqc {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+// One 16x16x32 MFMA of a split form on eight 16-bit values per lane:
+// bfloat16 for the bf16 forms (P = 2, 3), float16 for P = 4.
+template <int P>
+__device__ inline floatx4 mfma_split(const bf16x8 &a, const bf16x8 &b, const floatx4 &c) {
+  if constexpr (P == 4)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0,
+                                                  0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 typedef double double2v __attribute__((ext_vector_type(2)));
 
 // ======================================================= Pauli transform
@@ -149,6 +161,12 @@ struct PrecTraits<1> {  // float32
 };
 template <>
 struct PrecTraits<2> {  // bf16x3
+  using E = uint16_t;
+  static constexpr int planes = 2, kgroup = 32;
+  using Acc = floatx4;
+};
+template <>
+struct PrecTraits<4> {  // fp16x3 (final step of a float16-split plan)
   using E = uint16_t;
   static constexpr int planes = 2, kgroup = 32;
   using Acc = floatx4;
@@ -421,13 +439,13 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
           for (int j = 0; j < FN; ++j) {
             // small terms first, then the leading product
             if constexpr (P == 3) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = mfma_split<P>(af[2][i], bfr[0][j], acc[i][j]);
+              acc[i][j] = mfma_split<P>(af[1][i], bfr[1][j], acc[i][j]);
+              acc[i][j] = mfma_split<P>(af[0][i], bfr[2][j], acc[i][j]);
             }
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = mfma_split<P>(af[1][i], bfr[0][j], acc[i][j]);
+            acc[i][j] = mfma_split<P>(af[0][i], bfr[1][j], acc[i][j]);
+            acc[i][j] = mfma_split<P>(af[0][i], bfr[0][j], acc[i][j]);
           }
       }
     }

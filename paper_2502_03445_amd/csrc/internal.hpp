@@ -48,7 +48,7 @@ struct Network {
 };
 
 // --------------------------------------------------------------------- plan
-enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3, F16X3 = 4 };
 
 struct Node {
   std::vector<int> labels;   // storage layout of the operand form, LSB first
@@ -99,6 +99,9 @@ struct Plan {
   std::vector<uint64_t> tscr_off, tscr_bytes;
   // split-K partial sums of steps whose tiles cannot fill the device
   uint64_t splitk_off = 0, splitk_bytes = 0;
+  // float16-split plans: the final step's two operands as float16 planes
+  // (hi at h16_off[i], lo one plane later), i = 0 for its A side, 1 for B
+  uint64_t h16_off[2] = {0, 0}, h16_plane[2] = {0, 0};
   double *acc64 = nullptr;       // float64 accumulator for sliced runs (when out is f32)
   void *scale_buf = nullptr;     // per-leaf |max| bits, exponents, output scale
   void *stats_buf = nullptr;     // per-tile statistics of the root step + top-k scratch

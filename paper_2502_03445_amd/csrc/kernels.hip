@@ -333,6 +333,79 @@ hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int 
   return hipGetLastError();
 }
 
+// ============================================= float16 split of final operands
+// The final step of a float16-split plan reads each operand as two float16
+// planes: with e the power of two that puts the operand's largest |value| in
+// [2^14, 2^15) (float16 reaches 65504), hi = RNE16(v 2^e) and lo =
+// RNE16(v 2^e - hi) (v 2^e - hi is exact in float32).  The output scale
+// 2^-(ea + eb) times the plan's root scale is written for the epilogue.
+// blockIdx.y selects the operand.
+struct F16Split {
+  const float *src[2];
+  uint64_t n[2];
+  uint16_t *hi[2], *lo[2];
+  unsigned long long *maxbits;  // two entries, zero before the abs-max pass
+  const double *root_scale;
+  double *root_scale2;
+};
+
+__global__ void __launch_bounds__(256) f16_absmax_kernel(F16Split a) {
+  __shared__ float red[256];
+  const int y = blockIdx.y;
+  float mx = 0.f;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += (uint64_t)gridDim.x * blockDim.x)
+    mx = fmaxf(mx, fabsf(a.src[y][i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  // non-negative doubles order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(a.maxbits + y, (unsigned long long)__double_as_longlong((double)red[0]));
+}
+
+__device__ inline int f16_exponent(unsigned long long bits) {
+  const double mx = __longlong_as_double((long long)bits);
+  return mx > 0.0 ? 14 - ilogb(mx) : 0;
+}
+
+__global__ void __launch_bounds__(256) f16_split_kernel(F16Split a) {
+  const int y = blockIdx.y;
+  const int e = f16_exponent(a.maxbits[y]);
+  if (blockIdx.x == 0 && y == 0 && threadIdx.x == 0)
+    *a.root_scale2 = ldexp(*a.root_scale, -f16_exponent(a.maxbits[0]) - f16_exponent(a.maxbits[1]));
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += (uint64_t)gridDim.x * blockDim.x) {
+    const float v = ldexpf(a.src[y][i], e);
+    const _Float16 h = (_Float16)v;
+    const _Float16 l = (_Float16)(v - (float)h);
+    a.hi[y][i] = __builtin_bit_cast(uint16_t, h);
+    a.lo[y][i] = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+hipError_t launch_f16_split(const float *src0, uint64_t n0, uint16_t *hi0, uint16_t *lo0, const float *src1,
+                            uint64_t n1, uint16_t *hi1, uint16_t *lo1, unsigned long long *maxbits,
+                            const double *root_scale, double *root_scale2, hipStream_t s) {
+  F16Split a{};
+  a.src[0] = src0;
+  a.src[1] = src1;
+  a.n[0] = n0;
+  a.n[1] = n1;
+  a.hi[0] = hi0;
+  a.hi[1] = hi1;
+  a.lo[0] = lo0;
+  a.lo[1] = lo1;
+  a.maxbits = maxbits;
+  a.root_scale = root_scale;
+  a.root_scale2 = root_scale2;
+  const uint64_t most = n0 > n1 ? n0 : n1;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, s, maxbits, (uint64_t)2);
+  hipLaunchKernelGGL(f16_absmax_kernel, dim3(grid_for(most, 1024), 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(f16_split_kernel, dim3(grid_for(most), 2), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // ===================================================== heavy state selection
 // Column L2 norms of a Pauli tensor [rows][cols] (Alg. 1: per output state,
 // the norm over every edge permutation).  Pass 1: workgroup (x, y) sums the
@@ -487,7 +560,8 @@ hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s) {
     case 0: return launch_gemm_bk<0, 16>(g, tile, s);
     case 1: return kp >= 5 ? launch_gemm_bk<1, 32>(g, tile, s) : launch_gemm_bk<1, 16>(g, tile, s);
     case 2: return launch_gemm_bk<2, 32>(g, tile, s);
-    default: return launch_gemm_bk<3, 32>(g, tile, s);
+    case 3: return launch_gemm_bk<3, 32>(g, tile, s);
+    default: return launch_gemm_bk<4, 32>(g, tile, s);
   }
 }
 

@@ -14,6 +14,9 @@ hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *dst, hipStream_t s);
+hipError_t launch_f16_split(const float *src0, uint64_t n0, uint16_t *hi0, uint16_t *lo0, const float *src1,
+                            uint64_t n1, uint16_t *hi1, uint16_t *lo1, unsigned long long *maxbits,
+                            const double *root_scale, double *root_scale2, hipStream_t s);
 uint64_t colnorm_scratch_entries(uint64_t rows, uint64_t cols);
 hipError_t launch_column_norms(const double *T, uint64_t rows, uint64_t cols, double *partial, double *norms,
                                hipStream_t s);

@@ -32,6 +32,7 @@ double prec_peak_flops(Prec p) {
     case Prec::F32: return 157.3e12;
     case Prec::BF16X3: return 2.5e15 / 3.0;
     case Prec::BF16X6: return 2.5e15 / 6.0;
+    case Prec::F16X3: return 2.5e15 / 3.0;
   }
   return 157.3e12;
 }
@@ -41,18 +42,20 @@ int prec_bytes(Prec p) {
     case Prec::F32: return 4;
     case Prec::BF16X3: return 4;
     case Prec::BF16X6: return 6;
+    case Prec::F16X3: return 4;
   }
   return 4;
 }
 static int prec_kmin_log2(Prec p) {
   // smallest operand row stride: one MFMA k-group per lane group
-  return (p == Prec::BF16X3 || p == Prec::BF16X6) ? 5 : 4;
+  return (p == Prec::BF16X3 || p == Prec::BF16X6 || p == Prec::F16X3) ? 5 : 4;
 }
 static int prec_planes(Prec p) {
   return p == Prec::BF16X3 ? 2 : (p == Prec::BF16X6 ? 3 : 1);
 }
 static int plane_elem_bytes(Prec p) {
-  return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
+  // float16-split plans keep their operands and intermediates in float32
+  return p == Prec::F64 ? 8 : ((p == Prec::F32 || p == Prec::F16X3) ? 4 : 2);
 }
 
 static constexpr double kHbmBw = 8.0e12;
@@ -399,6 +402,18 @@ static void assemble(Plan &p) {
     nd.offset = off;
     off += nd.plane_bytes * nd.planes;
   }
+  // float16-split plans: the pairwise steps run in float32 (planes as
+  // above); the final step's operands are split again into two float16
+  // planes each
+  if (p.prec == Prec::F16X3)
+    for (const Step &st : p.steps)
+      if (st.root)
+        for (int i = 0; i < 2; ++i) {
+          const Node &nd = p.nodes[i == 0 ? st.a : st.b];
+          p.h16_plane[i] = align(nd.elems() * 2);
+          p.h16_off[i] = off;
+          off += 2 * p.h16_plane[i];
+        }
   p.ws_bytes = off;
 }
 
@@ -538,7 +553,7 @@ Plan *build_plan(Network *net, const tqc_plan_options &opt) {
   std::unique_ptr<Plan> p(new Plan());
   p->net = net;
   p->prec = Prec(int(opt.precision));
-  if (int(opt.precision) < 0 || int(opt.precision) > 3) fail(TQC_ERR_INVALID_ARG, "precision");
+  if (int(opt.precision) < 0 || int(opt.precision) > 4) fail(TQC_ERR_INVALID_ARG, "precision");
   if (opt.out_dtype != TQC_F32 && opt.out_dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "out_dtype");
   p->out_dtype = opt.out_dtype;
   if (opt.tile_policy < 0 || opt.tile_policy > 2) fail(TQC_ERR_INVALID_ARG, "tile_policy %d", opt.tile_policy);

@@ -66,6 +66,13 @@ struct RootTraits<3> {
   static constexpr int ES = 2;
   using Frag = bf16x8;
 };
+template <>
+struct RootTraits<4> {  // two float16 planes: the bf16x3 schedule on float16 MFMA
+  static constexpr int KG = 32;
+  static constexpr int NP = 2;
+  static constexpr int ES = 2;
+  using Frag = bf16x8;  // 16-bit lanes; mfma_split<4> reads them as float16
+};
 
 // Workgroup barrier ordering LDS only.  __syncthreads() also waits for every
 // outstanding global store of the wave, which would drain the output store
@@ -90,7 +97,7 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
   using Frag = typename RT::Frag;
   constexpr int KG = RT::KG, NP = RT::NP, ES = RT::ES;
   constexpr int NKG = KP / KG;
-  constexpr int RMAX = (P == 3) ? 1 : 2;      // fragment groups in flight (256 VGPRs per lane)
+  constexpr int RMAX = (NP == 3) ? 1 : 2;     // fragment groups in flight (256 VGPRs per lane)
   constexpr int R = NKG < RMAX ? NKG : RMAX;
   static_assert(NKG >= 1 && NKG % R == 0, "k groups");
   constexpr int FM = 4, FN = 4;  // 16 x 16 blocks per MFMA wave (64 x 64 sub-tile)
@@ -128,7 +135,7 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
     const char *Bp[3] = {(const char *)g.b0, (const char *)g.b1, (const char *)g.b2};
     // A row-blocks repeat along a walk (the same tile row for many tiles):
     // when they fit, all k groups of A stay in registers and only B streams
-    constexpr bool HOLD_A = NKG * NP * FM * 4 <= (P == 3 ? 96 : 64);
+    constexpr bool HOLD_A = NKG * NP * FM * 4 <= (NP == 3 ? 96 : 64);
     constexpr int NA = HOLD_A ? NKG : R;
     Frag fa[NA][NP][FM], fb[R][NP][FN];
     floatx4 acc[FM][FN];
@@ -164,18 +171,18 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
       } else {
         // products smallest first, the same order per accumulator as the
         // general kernel; all 16 accumulators between dependent MFMAs
-        constexpr int NPR = (P == 3) ? 6 : 3;
+        constexpr int NPR = (NP == 3) ? 6 : 3;
         constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
         constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
 #pragma unroll
         for (int pr = 0; pr < NPR; ++pr) {
-          const int x = (P == 3) ? pa3[pr] : pa2[pr];
-          const int y = (P == 3) ? pb3[pr] : pb2[pr];
+          const int x = (NP == 3) ? pa3[pr] : pa2[pr];
+          const int y = (NP == 3) ? pb3[pr] : pb2[pr];
 #pragma unroll
           for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[qa][x][i], fb[q][y][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = mfma_split<P>(fa[qa][x][i], fb[q][y][j], acc[i][j]);
         }
       }
     };
@@ -231,13 +238,13 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
             *(float *)(ct + (ctlane ^ trow(i, r) ^ tcol(j))) = acc[i][j][r];
       lds_barrier();
     };
-    if constexpr (HOLD_A && P >= 2) {
+    if constexpr (HOLD_A && P != 1) {
       // Column-slice pipeline: unit u = (tile u / NSL, column slice u % NSL).
       // The MFMAs of unit u run while the accumulators of unit u - 1 go to
       // the staged tile, so the staging writes overlap the math; the barrier
       // that hands a tile to the store waves follows the write of its last
       // slice.  Narrower slices for bf16x6 keep its registers in budget.
-      constexpr int NSL = (P == 3) ? 4 : 2;
+      constexpr int NSL = (NP == 3) ? 4 : 2;
       constexpr int FH = FN / NSL;
       // B fragment groups in flight: the ring runs across slices and tiles
       constexpr int RSMAX = 2;
@@ -272,18 +279,18 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
               for (int j = 0; j < FH; ++j)
                 ah[sa][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[kg][0][i][t], fbh[q][0][j][t], ah[sa][i][j], 0, 0, 0);
         } else {
-          constexpr int NPR = (P == 3) ? 6 : 3;
+          constexpr int NPR = (NP == 3) ? 6 : 3;
           constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
           constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
 #pragma unroll
           for (int pr = 0; pr < NPR; ++pr) {
-            const int x = (P == 3) ? pa3[pr] : pa2[pr];
-            const int y = (P == 3) ? pb3[pr] : pb2[pr];
+            const int x = (NP == 3) ? pa3[pr] : pa2[pr];
+            const int y = (NP == 3) ? pb3[pr] : pb2[pr];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
               for (int j = 0; j < FH; ++j)
-                ah[sa][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[kg][x][i], fbh[q][y][j], ah[sa][i][j], 0, 0, 0);
+                ah[sa][i][j] = mfma_split<P>(fa[kg][x][i], fbh[q][y][j], ah[sa][i][j]);
           }
         }
       };
@@ -515,7 +522,7 @@ int cu_count() {
 int root_gemm_warm() { return cu_count(); }
 
 bool root_gemm_eligible(int prec, const GemmArgs &g) {
-  if (prec < 1 || prec > 3 || g.out_kind != OUT_F32) return false;
+  if (prec < 1 || prec > 4 || g.out_kind != OUT_F32) return false;
   if (g.lm < 7 || g.ln < 7 || g.lm > kMaxBits || g.ln > kMaxBits) return false;
   if (g.lm + g.ln - 14 > 30) return false;  // tile ids in 31 bits; 32 tile bits per side at most
   if (g.kpad < (prec == 1 ? 4 : 5) || g.kpad > 8 || g.lk > g.kpad) return false;
@@ -537,7 +544,8 @@ hipError_t launch_root_gemm(int prec, const GemmArgs &g_in, hipStream_t s) {
   switch (prec) {
     case 1: return launch_root_p<1>(g, ntiles, lgtn, grid, s);
     case 2: return launch_root_p<2>(g, ntiles, lgtn, grid, s);
-    default: return launch_root_p<3>(g, ntiles, lgtn, grid, s);
+    case 3: return launch_root_p<3>(g, ntiles, lgtn, grid, s);
+    default: return launch_root_p<4>(g, ntiles, lgtn, grid, s);
   }
 }
 

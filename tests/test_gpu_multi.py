@@ -38,7 +38,7 @@ def tol(form, ref):
 
 @pytest.mark.parametrize("form,use_graph,streams", [("fp32", True, 4), ("bf16x3", True, 3),
                                                     ("fp64", True, 4), ("fp32", False, 4),
-                                                    ("bf16x6", False, 1)])
+                                                    ("bf16x6", False, 1), ("fp16x3", True, 4)])
 def test_multi_equals_plain_execution(form, use_graph, streams):
     specs, nets, plans = jobs(form)
     plain = [p.execute().clone() for p in plans]
@@ -104,7 +104,7 @@ def test_multi_rejects_bad_jobs():
         timed.job_times()  # nothing ran yet
 
 
-@pytest.mark.parametrize("form,rtol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 3e-5)])
+@pytest.mark.parametrize("form,rtol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 3e-5), ("fp16x3", 1e-6)])
 def test_generated_batch_jobs_match_oracle(form, rtol):
     from oracle.reconstruct import entries_variable_elimination
     from workloads import batch

@@ -21,7 +21,7 @@ from workloads import configs, probabilities, qaoa, synthetic
 
 pytestmark = pytest.mark.gpu
 
-FORMS = ["fp64", "fp32", "bf16x3", "bf16x6"]
+FORMS = ["fp64", "fp32", "bf16x3", "bf16x6", "fp16x3"]
 
 
 def tol_ok(form, got, ref):
@@ -148,8 +148,12 @@ def _splitk_oracle(case, spec):
     return _SPLITK_REF[case]
 
 
+# fp16x3 runs its split final steps through the same k-split code; its
+# per-entry error has an absolute part (float16 range) that gamma * A(x) does
+# not model, so it is checked on the random-network cases (K = 1024, 4096)
+# against the normwise bound instead
 @pytest.mark.parametrize("case", range(len(SPLITK_CASES)))
-@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_split_k_steps(case, form):
     (m, K, outs), sliced = SPLITK_CASES[case]
     spec = synthetic.random_network(m, K, outs, seed=1300 + case)
@@ -324,6 +328,7 @@ SUMMARY_CASES = [
     ("fp64", dict(), (1, 0, [9])),                          # one tensor: standalone scans
     ("fp32", dict(), (2, 3, [9, 9])),                       # persistent final-step kernel
     ("bf16x6", dict(), (3, 5, [8, 3, 8])),                  # persistent final-step kernel
+    ("fp16x3", dict(), (3, 5, [8, 3, 8])),                  # float16 split of the final operands
 ]
 
 
@@ -354,7 +359,7 @@ def test_summary_qaoa32_full_size():
     """The benchmark's step at its full size: 2^32 float32 entries, top-1000."""
     spec = qaoa.qaoa_network()
     N = tqc.Network.from_spec(spec)
-    for form in ("fp32", "bf16x6"):
+    for form in ("fp32", "bf16x6", "fp16x3"):
         P = tqc.Plan(N, precision=form)
         out, idx, val, tot, _ = P.execute_summary(k=1000)
         ri, rv = tqc.topk(out, 1000)
@@ -381,7 +386,7 @@ ROOT_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(ROOT_CASES)))
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 def test_final_step_kernel(case, form):
     m, K, outs = ROOT_CASES[case]
     spec = synthetic.random_network(m, K, outs, seed=900 + case)
@@ -422,7 +427,9 @@ def test_precision_network_slice_full_size():
     got = ref[torch.from_numpy(local.astype(np.int64)).cuda()].cpu().numpy()
     assert np.abs(got - want).max() <= 1e-12, np.abs(got - want).max()
     scale = ref.abs().max().item()
-    bounds = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5}
+    # fp16x3: float32 pairwise steps, then 22-bit final operands (two bits
+    # fewer than float32): up to 4x the float32 error of this network
+    bounds = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5, "fp16x3": 4e-6}
     for form, bound in bounds.items():
         P = tqc.Plan(N, precision=form, out_dtype="f32", fixed=fixed)
         out = P.execute()
