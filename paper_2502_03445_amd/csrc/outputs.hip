@@ -21,6 +21,7 @@ namespace tqc {
 constexpr int kDigitBits = 11;
 constexpr int kBins = 1 << kDigitBits;
 constexpr uint64_t kChunk = 1ull << 16;  // elements per block in ordered passes
+constexpr uint64_t kChunkGrid = 2048;     // largest grid of the exact passes (grid-strided)
 constexpr int kMaxK = 4096;
 
 struct TopkState {
@@ -61,6 +62,28 @@ __device__ inline double key_value(uint64_t key, int dtype) {
 }
 
 __device__ inline bool gated_off(const unsigned int *gate) { return gate && *gate == 0; }
+
+// Appends the flagged entries of a wave to the candidate list with one
+// atomic per wave (slot order inside a wave by lane); every lane of the wave
+// must call it.  The count keeps growing past kMaxK so that an overflow is
+// seen by the sort, which then raises the fallback flag.
+__device__ inline void append_candidate(bool hit, uint64_t key, uint64_t idx, TopkState *fast, uint64_t *cand_key,
+                                        uint64_t *cand_idx) {
+  const unsigned long long bal = __ballot(hit);
+  if (!bal) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)bal) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(&fast->ncand, (unsigned long long)__popcll(bal));
+  base = __shfl(base, leader, 64);
+  if (hit) {
+    const unsigned long long slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+    if (slot < (unsigned long long)kMaxK) {
+      cand_key[slot] = key;
+      cand_idx[slot] = idx;
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) topk_init(TopkState *st, unsigned long long *hist,
                                                  int keybits, int k, const unsigned int *gate) {
@@ -164,25 +187,29 @@ __global__ void __launch_bounds__(256) topk_collect_gt(const void *p, int dtype,
                                                        const unsigned int *gate) {
   if (gated_off(gate)) return;
   __shared__ unsigned int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
   const uint64_t tau = st->prefix;
-  const uint64_t lo = blockIdx.x * kChunk;
-  const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
-  unsigned int mine = 0;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const uint64_t key = sort_key(p, dtype, i);
-    if (key > tau) {
-      const unsigned long long s = atomicAdd(&st->n_gt, 1ull);
-      cand_key[s] = key;
-      cand_idx[s] = i;
-    } else if (key == tau) {
-      ++mine;
+  const uint64_t nchunks = (len + kChunk - 1) / kChunk;
+  // chunks grid-strided (a small grid costs little when the gate is off)
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const uint64_t lo = c * kChunk;
+    const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
+    unsigned int mine = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const uint64_t key = sort_key(p, dtype, i);
+      if (key > tau) {
+        const unsigned long long s = atomicAdd(&st->n_gt, 1ull);
+        cand_key[s] = key;
+        cand_idx[s] = i;
+      } else if (key == tau) {
+        ++mine;
+      }
     }
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) blockcnt[c] = cnt;
   }
-  if (mine) atomicAdd(&cnt, mine);
-  __syncthreads();
-  if (threadIdx.x == 0) blockcnt[blockIdx.x] = cnt;
 }
 
 // exclusive scan of the per-block equal counts (one block, fixed order)
@@ -221,35 +248,40 @@ __global__ void __launch_bounds__(256) topk_collect_eq(const void *p, int dtype,
                                                        const unsigned int *gate) {
   if (gated_off(gate)) return;
   const unsigned long long need = st->kr;
-  const unsigned long long base = blockpre[blockIdx.x];
-  if (base >= need) return;
   const uint64_t tau = st->prefix;
-  const uint64_t lo = blockIdx.x * kChunk;
-  const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
+  const uint64_t nchunks = (len + kChunk - 1) / kChunk;
   const unsigned long long slot0 = (unsigned long long)k - need;
   __shared__ unsigned int wcount[4];
   __shared__ unsigned long long run;
-  if (threadIdx.x == 0) run = base;
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (uint64_t c = lo; c < hi; c += blockDim.x) {
-    const uint64_t i = c + threadIdx.x;
-    const bool eq = (i < hi) && (sort_key(p, dtype, i) == tau);
-    const unsigned long long bal = __ballot(eq);
-    const unsigned int below = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[wave] = __popcll(bal);
+  // chunks grid-strided (a small grid costs little when the gate is off)
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const unsigned long long base = blockpre[ch];
+    if (base >= need) continue;  // uniform over the block
+    const uint64_t lo = ch * kChunk;
+    const uint64_t hi = lo + kChunk < len ? lo + kChunk : len;
+    if (threadIdx.x == 0) run = base;
     __syncthreads();
-    unsigned long long r = run;
-    for (int w = 0; w < wave; ++w) r += wcount[w];
-    r += below;
-    if (eq && r < need) {
-      cand_key[slot0 + r] = tau;
-      cand_idx[slot0 + r] = i;
+    for (uint64_t c = lo; c < hi; c += blockDim.x) {
+      const uint64_t i = c + threadIdx.x;
+      const bool eq = (i < hi) && (sort_key(p, dtype, i) == tau);
+      const unsigned long long bal = __ballot(eq);
+      const unsigned int below = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[wave] = __popcll(bal);
+      __syncthreads();
+      unsigned long long r = run;
+      for (int w = 0; w < wave; ++w) r += wcount[w];
+      r += below;
+      if (eq && r < need) {
+        cand_key[slot0 + r] = tau;
+        cand_idx[slot0 + r] = i;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) run += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      __syncthreads();
+      if (run >= need) break;
     }
     __syncthreads();
-    if (threadIdx.x == 0) run += wcount[0] + wcount[1] + wcount[2] + wcount[3];
-    __syncthreads();
-    if (run >= need) break;
   }
 }
 
@@ -358,13 +390,7 @@ __global__ void __launch_bounds__(256) topk_collect_fast(const void *p, int dtyp
   const uint64_t hi = lo + kMaxChunk < len ? lo + kMaxChunk : len;
   for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) {
     const uint64_t key = sort_key(p, dtype, i);
-    if (key >= tau0) {
-      const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
-      if (slot < (unsigned long long)kMaxK) {
-        cand_key[slot] = key;
-        cand_idx[slot] = i;
-      }
-    }
+    append_candidate(key >= tau0, key, i, fast, cand_key, cand_idx);
   }
 }
 
@@ -393,7 +419,7 @@ static void exact_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   const int keybits = dtype == 1 ? 32 : 64;
   hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, st, hist, keybits, k, gate);
   uint64_t hb = (len + 255) / 256;
-  if (hb > 8192) hb = 8192;
+  if (hb > kChunkGrid) hb = kChunkGrid;
   for (int resolved = 0; resolved < keybits;) {
     const int bits = (keybits - resolved) < kDigitBits ? (keybits - resolved) : kDigitBits;
     hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb), dim3(256), 0, s, probs, dtype, len, st, hist, bits,
@@ -401,11 +427,12 @@ static void exact_topk(const void *probs, int dtype, uint64_t len, int k, uint64
     hipLaunchKernelGGL(topk_select, dim3(1), dim3(256), 0, s, st, hist, bits, gate);
     resolved += bits;
   }
-  hipLaunchKernelGGL(topk_collect_gt, dim3((unsigned)nblocks), dim3(256), 0, s, probs, dtype, len, st,
-                     cand_key, cand_idx, blockcnt, gate);
+  const unsigned cg = (unsigned)(nblocks < kChunkGrid ? nblocks : kChunkGrid);
+  hipLaunchKernelGGL(topk_collect_gt, dim3(cg), dim3(256), 0, s, probs, dtype, len, st, cand_key, cand_idx,
+                     blockcnt, gate);
   hipLaunchKernelGGL(topk_scan, dim3(1), dim3(1024), 0, s, blockcnt, nblocks, gate);
-  hipLaunchKernelGGL(topk_collect_eq, dim3((unsigned)nblocks), dim3(256), 0, s, probs, dtype, len, st,
-                     k, cand_key, cand_idx, blockcnt, gate);
+  hipLaunchKernelGGL(topk_collect_eq, dim3(cg), dim3(256), 0, s, probs, dtype, len, st, k, cand_key, cand_idx,
+                     blockcnt, gate);
   hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, cand_key, cand_idx, k, dtype, idx_out,
                      val_out, (TopkState *)nullptr, gate);
 }
@@ -506,13 +533,7 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
       for (int q = 0; q < 4; ++q) {
         const uint32_t u = __float_as_uint(e[q]);
         const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
-        if (key >= tau0) {
-          const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
-          if (slot < (unsigned long long)kMaxK) {
-            cand_key[slot] = key;
-            cand_idx[slot] = i0 + q;
-          }
-        }
+        append_candidate(key >= tau0, key, i0 + q, fast, cand_key, cand_idx);
       }
     }
     return;
@@ -524,16 +545,10 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
     const uint64_t tm = t / tilesN, tn = t % tilesN;
     const uint64_t m0 = tm << lbm, n0 = tn << lbn;
     const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
-    if (m0 + rl >= M || n0 + cl >= N) continue;
-    const uint64_t i = scatter_bits(m0 | rl, g.posM, g.lm) + scatter_bits(n0 | cl, g.posN, g.ln);
-    const uint64_t key = sort_key(p, dtype, i);
-    if (key >= tau0) {
-      const unsigned long long slot = atomicAdd(&fast->ncand, 1ull);
-      if (slot < (unsigned long long)kMaxK) {
-        cand_key[slot] = key;
-        cand_idx[slot] = i;
-      }
-    }
+    const bool inside = m0 + rl < M && n0 + cl < N;
+    const uint64_t i = inside ? scatter_bits(m0 | rl, g.posM, g.lm) + scatter_bits(n0 | cl, g.posN, g.ln) : 0;
+    const uint64_t key = inside ? sort_key(p, dtype, i) : 0;
+    append_candidate(inside && key >= tau0, key, i, fast, cand_key, cand_idx);
   }
 }
 
