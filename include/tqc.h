@@ -200,8 +200,10 @@ tqc_status tqc_execute(tqc_plan_t plan, void *out, uint64_t out_bytes, void *str
 
 /* tqc_execute, then wait for the stream and report device time per phase,
  * measured with HIP events on that stream: phase_ms[0] Pauli-basis
- * transform, [1] operand packing, [2 + i] pairwise step i (summed over
- * slices), [2 + num_steps] float64-to-float32 conversion (0 if none).
+ * transform, [1] operand scaling and packing, [2 + i] pairwise step i
+ * (summed over slices; for FP16X3 the final step's phase includes the
+ * float16 split of its two operands), [2 + num_steps] float64-to-float32
+ * conversion (0 if none).
  * num_phases >= 3 + num_steps.  Synchronous.  Used for the benchmark's
  * per-kernel roofline and as training data of the learned cost model. */
 tqc_status tqc_execute_profiled(tqc_plan_t plan, void *out, uint64_t out_bytes, void *stream,
