@@ -565,7 +565,9 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         ph = np.mean(np.array(phases), axis=0)
+        per_step = np.array(phases).sum(axis=1)  # device time of each timed step
         res[form] = {"ms": ms, "phases": ph.tolist(), "plan": plan.stats, "steps": plan.steps,
+                     "step_ms_median": float(np.median(per_step)), "step_ms_std": float(np.std(per_step)),
                      "total": tot.item(), "top_idx": idx.cpu().numpy(), "top_val": val.cpu().numpy()}
         print(f"# {form}: {ms:.3f} ms/step, phases {np.round(ph, 3).tolist()}, sum {tot.item():.9f}",
               file=sys.stderr, flush=True)
@@ -644,6 +646,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": R["ms"],
+        "ms_per_step_median": R["step_ms_median"],
+        "ms_per_step_std": R["step_ms_std"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -660,7 +664,8 @@ def main():
                        "mfma_frac": (res["fp32"]["plan"]["flops"] / (res["fp32"]["ms"] * 1e-3) /
                                      MFMA_PEAK["fp32"]) if "fp32" in res else None},
         "chosen_mfma_frac": PRODUCTS[chosen] * R["plan"]["flops"] / (R["ms"] * 1e-3) / MFMA_PEAK[chosen],
-        "forms": {f: {"ms_per_step": res[f]["ms"], "rel_err": res[f]["rel_err"],
+        "forms": {f: {"ms_per_step": res[f]["ms"], "step_ms_median": res[f]["step_ms_median"],
+                      "step_ms_std": res[f]["step_ms_std"], "rel_err": res[f]["rel_err"],
                       "max_abs_err": res[f]["max_abs_err"], "sum": res[f]["total"],
                       "phase_ms": [round(x, 4) for x in res[f]["phases"]]} for f in forms},
         "roofline": roof,

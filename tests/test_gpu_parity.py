@@ -180,7 +180,8 @@ def test_orders_agree_fp64():
         assert np.abs(o - outs[0]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("form,out_dtype", [("fp64", "f64"), ("fp32", "f32"), ("fp32", "f64")])
+@pytest.mark.parametrize("form,out_dtype", [("fp64", "f64"), ("fp32", "f32"), ("fp32", "f64"), ("fp16x3", "f32"),
+                                            ("fp16x3", "f64")])
 def test_slicing_is_exact(form, out_dtype):
     spec = synthetic.random_network(4, 6, [3, 3, 2, 3], seed=31)
     ref = full_distribution(spec)
@@ -213,7 +214,7 @@ def test_budget_slicing_and_resume():
     assert np.abs(a - b).max() <= 1e-15 * max(1.0, np.abs(a).max()) * 16
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "fp16x3"])
 def test_fixed_qubit_slice(form):
     spec = synthetic.random_network(4, 5, [3, 4, 3, 3], seed=55)
     fixed = {1: 1, 4: 0, 9: 1}
