@@ -16,7 +16,10 @@ namespace tqc {
 // order-preserving integer key (11-bit digits, most significant first), then
 // collection of every entry above that value plus the lowest-index entries
 // equal to it, then a bitonic sort of the k winners by (value desc, index
-// asc).
+// asc).  The fast forms gather a candidate superset (up to kMaxK entries)
+// and place the first k by rank instead: each candidate's position in the
+// order (value desc, index asc) is the number of candidates that sort before
+// it, counted in parallel over 256 x 256 blocks of candidate pairs.
 
 constexpr int kDigitBits = 11;
 constexpr int kBins = 1 << kDigitBits;
@@ -285,26 +288,15 @@ __global__ void __launch_bounds__(256) topk_collect_eq(const void *p, int dtype,
   }
 }
 
-// bitonic sort of k (padded to a power of two) by (key desc, index asc)
-// Sorts `count` candidates (count from *ncand when given) by (key desc,
-// index asc) and writes the first k.  With a candidate counter: if it holds
-// more than kMaxK (or fewer than k) entries, raise the fallback flag instead.
+// bitonic sort of the k selected entries (padded to a power of two) by
+// (key desc, index asc)
 __global__ void __launch_bounds__(1024) topk_sort(const uint64_t *cand_key, const uint64_t *cand_idx,
                                                   int k, int dtype, uint64_t *idx_out,
-                                                  double *val_out, TopkState *fast,
-                                                  const unsigned int *gate) {
+                                                  double *val_out, const unsigned int *gate) {
   if (gated_off(gate)) return;
   __shared__ uint64_t sk[kMaxK];
   __shared__ uint64_t si[kMaxK];
-  int cnt = k;
-  if (fast) {
-    const unsigned long long c = fast->ncand;
-    if (c > (unsigned long long)kMaxK || c < (unsigned long long)k) {
-      if (threadIdx.x == 0) fast->fallback = 1;
-      return;
-    }
-    cnt = (int)c;
-  }
+  const int cnt = k;
   int n = 1;
   while (n < cnt) n <<= 1;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -341,6 +333,67 @@ __global__ void __launch_bounds__(1024) topk_sort(const uint64_t *cand_key, cons
     idx_out[i] = si[i];
     val_out[i] = key_value(sk[i], dtype);
   }
+}
+
+// Candidate ranks.  The count of candidates is fast->ncand; outside
+// [k, kMaxK] the fast form cannot decide and the placement raises the
+// fallback flag.  Keys and indices are distinct pairs (every output index is
+// a candidate at most once), so the ranks are a permutation of [0, count).
+// partial[bj * kMaxK + i] = how many of candidates [256 bj, 256 bj + 256)
+// sort before candidate i.
+constexpr int kRankBlocks = kMaxK / 256;
+
+__global__ void __launch_bounds__(256) topk_rank_count(const uint64_t *cand_key, const uint64_t *cand_idx,
+                                                       int k, const TopkState *fast, unsigned int *partial) {
+  const unsigned long long c = fast->ncand;
+  if (c > (unsigned long long)kMaxK || c < (unsigned long long)k) return;
+  const int n = (int)c;
+  const int i0 = blockIdx.x * 256, j0 = blockIdx.y * 256;
+  if (i0 >= n || j0 >= n) return;  // uniform over the block
+  __shared__ uint64_t sk[256];
+  __shared__ uint64_t si[256];
+  const int t = threadIdx.x;
+  const int jn = n - j0 < 256 ? n - j0 : 256;
+  if (t < jn) {
+    sk[t] = cand_key[j0 + t];
+    si[t] = cand_idx[j0 + t];
+  }
+  __syncthreads();
+  const int i = i0 + t;
+  if (i >= n) return;
+  const uint64_t ki = cand_key[i], ii = cand_idx[i];
+  unsigned int cnt = 0;
+  for (int j = 0; j < jn; ++j) cnt += (sk[j] > ki || (sk[j] == ki && si[j] < ii)) ? 1u : 0u;
+  partial[blockIdx.y * kMaxK + i] = cnt;
+}
+
+__global__ void __launch_bounds__(256) topk_rank_place(const uint64_t *cand_key, const uint64_t *cand_idx,
+                                                       int k, int dtype, uint64_t *idx_out, double *val_out,
+                                                       TopkState *fast, const unsigned int *partial) {
+  const unsigned long long c = fast->ncand;
+  if (c > (unsigned long long)kMaxK || c < (unsigned long long)k) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) fast->fallback = 1;
+    return;
+  }
+  const int n = (int)c;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int nb = (n + 255) / 256;
+  unsigned int r = 0;
+  for (int b = 0; b < nb; ++b) r += partial[b * kMaxK + i];
+  if (r < (unsigned int)k) {
+    idx_out[r] = cand_idx[i];
+    val_out[r] = key_value(cand_key[i], dtype);
+  }
+}
+
+static void launch_rank_place(const uint64_t *cand_key, const uint64_t *cand_idx, int k, int dtype,
+                              uint64_t *idx_out, double *val_out, TopkState *fast, unsigned int *partial,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(topk_rank_count, dim3(kRankBlocks, kRankBlocks), dim3(256), 0, s, cand_key, cand_idx, k,
+                     (const TopkState *)fast, partial);
+  hipLaunchKernelGGL(topk_rank_place, dim3(kRankBlocks), dim3(256), 0, s, cand_key, cand_idx, k, dtype, idx_out,
+                     val_out, fast, (const unsigned int *)partial);
 }
 
 // ---- fast path: per-chunk maxima bound the threshold from below
@@ -406,7 +459,7 @@ uint64_t topk_scratch_bytes(uint64_t len, int k) {
   const uint64_t nblocks = (len + kChunk - 1) / kChunk;
   const uint64_t nchunks = (len + kMaxChunk - 1) / kMaxChunk;
   return 3 * 256 + kBins * 8 + nblocks * 8 + nchunks * 8 + 2 * (uint64_t)kMaxK * 8 +
-         2 * (uint64_t)k * 8 + 1024;
+         2 * (uint64_t)k * 8 + (uint64_t)kRankBlocks * kMaxK * 4 + 1024;
 }
 
 // Exact passes over the whole vector: radix select of the k-th largest key,
@@ -434,7 +487,7 @@ static void exact_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   hipLaunchKernelGGL(topk_collect_eq, dim3(cg), dim3(256), 0, s, probs, dtype, len, st, k, cand_key, cand_idx,
                      blockcnt, gate);
   hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, cand_key, cand_idx, k, dtype, idx_out,
-                     val_out, (TopkState *)nullptr, gate);
+                     val_out, gate);
 }
 
 hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
@@ -454,6 +507,7 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   uint64_t *fidx = fkey + kMaxK;
   uint64_t *cand_key = fidx + kMaxK;
   uint64_t *cand_idx = cand_key + k;
+  unsigned int *partial = (unsigned int *)(cand_idx + k);
   const int keybits = dtype == 1 ? 32 : 64;
   if (nchunks < (uint64_t)k) {
     exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx,
@@ -477,8 +531,7 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   }
   hipLaunchKernelGGL(topk_collect_fast, dim3((unsigned)nchunks), dim3(256), 0, s, probs, dtype, len,
                      cmax, sel, fast, fkey, fidx);
-  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, fkey, fidx, k, dtype, idx_out, val_out, fast,
-                     (const unsigned int *)nullptr);
+  launch_rank_place(fkey, fidx, k, dtype, idx_out, val_out, fast, partial, s);
   // exact passes, skipped on the device unless the fast path gave up
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx,
              &fast->fallback, s);
@@ -506,56 +559,122 @@ __global__ void __launch_bounds__(256) topk_list_tiles(const unsigned long long 
   }
 }
 
-// 2) every entry >= tau0 of the listed tiles; work items are (tile, run of
-//    256 entries), spread over the whole grid
+// 2) every entry >= tau0 of the listed tiles.  A block walks its share of
+//    the list (grid-strided) with kCollectDepth loads in flight per thread,
+//    stages its hits in LDS (one LDS atomic per wave and group of hits) and
+//    reserves its slots in the global list with one atomic at the end; hits
+//    past the kStage LDS slots go to the global list directly.  The stage is
+//    small so that the kernel fits beside a running final-step kernel of
+//    another stream (which leaves about 29 KB of a CU's LDS free).
+constexpr int kCollectGrid = 256;
+constexpr int kCollectDepth = 8;
+constexpr unsigned int kStage = 1024;
+
+// every lane of the wave calls it
+__device__ inline void stage_hit(bool hit, uint64_t key, uint64_t idx, unsigned int *bcount, uint64_t *bk,
+                                 uint64_t *bi, TopkState *fast, uint64_t *cand_key, uint64_t *cand_idx) {
+  const unsigned long long bal = __ballot(hit);
+  if (!bal) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)bal) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(bcount, (unsigned int)__popcll(bal));
+  base = __shfl(base, leader, 64);
+  const unsigned int r = base + (unsigned int)__popcll(bal & ((1ull << lane) - 1ull));
+  if (hit && r < kStage) {
+    bk[r] = key;
+    bi[r] = idx;
+  }
+  append_candidate(hit && r >= kStage, key, idx, fast, cand_key, cand_idx);
+}
+
 __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dtype, GemmArgs g, int lbm,
                                                           int lbn, uint64_t tilesN,
                                                           const uint64_t *qlist, const TopkState *sel,
                                                           TopkState *fast, uint64_t *cand_key,
                                                           uint64_t *cand_idx) {
+  __shared__ uint64_t bk[kStage];
+  __shared__ uint64_t bi[kStage];
+  __shared__ unsigned int bcount;
+  __shared__ unsigned long long bbase;
   const uint64_t tau0 = sel->prefix;
   const uint64_t nq = fast->nq < (unsigned long long)kMaxK ? fast->nq : (unsigned long long)kMaxK;
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  if (threadIdx.x == 0) bcount = 0;
+  __syncthreads();
   if (g.vec4 && g.ncompact == lbm + lbn && dtype == 1) {
     // full tile whose two lowest output bits are tile bits: compact index x
     // (tile entries in output order) lands at base + deposit(x, lpos), and
     // x, x+1, x+2, x+3 are adjacent in the output
     const uint32_t runs4 = (1u << (lbm + lbn)) / 1024u;
-    for (uint64_t w = blockIdx.x; w < nq * runs4; w += gridDim.x) {
-      const uint64_t t = qlist[w / runs4];
-      const uint32_t x = (uint32_t)(w % runs4) * 1024u + threadIdx.x * 4u;
+    for (uint64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+      const uint64_t t = qlist[q];
       const uint64_t tm = t / tilesN, tn = t % tilesN;
       const uint64_t base = scatter_bits(tm << lbm, g.posM, g.lm) + scatter_bits(tn << lbn, g.posN, g.ln);
-      const uint64_t i0 = base + deposit_c<16>((uint64_t)x, g.lpos, lbm + lbn);
-      const float4 v = *(const float4 *)((const float *)p + i0);
-      const float e[4] = {v.x, v.y, v.z, v.w};
+      for (uint32_t r0 = 0; r0 < runs4; r0 += kCollectDepth) {
+        float4 v[kCollectDepth];
+        uint64_t at[kCollectDepth];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t u = __float_as_uint(e[q]);
-        const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
-        append_candidate(key >= tau0, key, i0 + q, fast, cand_key, cand_idx);
+        for (int d = 0; d < kCollectDepth; ++d) {
+          const uint32_t x = (r0 + d) * 1024u + threadIdx.x * 4u;
+          at[d] = base + deposit_c<16>((uint64_t)x, g.lpos, lbm + lbn);
+          if (r0 + d < runs4) v[d] = *(const float4 *)((const float *)p + at[d]);
+        }
+#pragma unroll
+        for (int d = 0; d < kCollectDepth; ++d) {
+          if (r0 + d >= runs4) break;  // uniform over the block
+          const float e[4] = {v[d].x, v[d].y, v[d].z, v[d].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t u = __float_as_uint(e[c]);
+            const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+            stage_hit(key >= tau0, key, at[d] + c, &bcount, bk, bi, fast, cand_key, cand_idx);
+          }
+        }
       }
     }
-    return;
+  } else {
+    const uint32_t runs = (1u << (lbm + lbn)) / 256u;  // tiles hold >= 1024 entries
+    for (uint64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+      const uint64_t t = qlist[q];
+      const uint64_t m0 = (t / tilesN) << lbm, n0 = (t % tilesN) << lbn;
+      for (uint32_t r0 = 0; r0 < runs; r0 += kCollectDepth) {
+        uint64_t key[kCollectDepth], at[kCollectDepth];
+        bool ok[kCollectDepth];
+#pragma unroll
+        for (int d = 0; d < kCollectDepth; ++d) {
+          const uint32_t e = (r0 + d) * 256u + threadIdx.x;
+          const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
+          ok[d] = r0 + d < runs && m0 + rl < M && n0 + cl < N;
+          at[d] = ok[d] ? scatter_bits(m0 | rl, g.posM, g.lm) + scatter_bits(n0 | cl, g.posN, g.ln) : 0;
+          key[d] = ok[d] ? sort_key(p, dtype, at[d]) : 0;
+        }
+#pragma unroll
+        for (int d = 0; d < kCollectDepth; ++d)
+          stage_hit(ok[d] && key[d] >= tau0, key[d], at[d], &bcount, bk, bi, fast, cand_key, cand_idx);
+      }
+    }
   }
-  const uint32_t runs = (1u << (lbm + lbn)) / 256u;  // tiles hold >= 1024 entries
-  for (uint64_t w = blockIdx.x; w < nq * runs; w += gridDim.x) {
-    const uint64_t t = qlist[w / runs];
-    const uint32_t e = (uint32_t)(w % runs) * 256u + threadIdx.x;
-    const uint64_t tm = t / tilesN, tn = t % tilesN;
-    const uint64_t m0 = tm << lbm, n0 = tn << lbn;
-    const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
-    const bool inside = m0 + rl < M && n0 + cl < N;
-    const uint64_t i = inside ? scatter_bits(m0 | rl, g.posM, g.lm) + scatter_bits(n0 | cl, g.posN, g.ln) : 0;
-    const uint64_t key = inside ? sort_key(p, dtype, i) : 0;
-    append_candidate(inside && key >= tau0, key, i, fast, cand_key, cand_idx);
+  __syncthreads();
+  const unsigned int kept = bcount < kStage ? bcount : kStage;
+  if (kept == 0) return;  // uniform over the block
+  if (threadIdx.x == 0) bbase = atomicAdd(&fast->ncand, (unsigned long long)kept);
+  __syncthreads();
+  const unsigned long long b0 = bbase;
+  for (unsigned int i = threadIdx.x; i < kept; i += blockDim.x) {
+    const unsigned long long slot = b0 + i;
+    if (slot < (unsigned long long)kMaxK) {
+      cand_key[slot] = bk[i];
+      cand_idx[slot] = bi[i];
+    }
   }
 }
 
 uint64_t topk_tiles_scratch_bytes(uint64_t len, uint64_t ntiles, int k) {
   const uint64_t nblocks = (len + kChunk - 1) / kChunk;
   (void)ntiles;
-  return 3 * 256 + kBins * 8 + nblocks * 8 + 3 * (uint64_t)kMaxK * 8 + 2 * (uint64_t)k * 8 + 1024;
+  return 3 * 256 + kBins * 8 + nblocks * 8 + 3 * (uint64_t)kMaxK * 8 + 2 * (uint64_t)k * 8 +
+         (uint64_t)kRankBlocks * kMaxK * 4 + 1024;
 }
 
 hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const GemmArgs &g, int lbm,
@@ -578,6 +697,7 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
   uint64_t *qlist = fidx + kMaxK;
   uint64_t *cand_key = qlist + kMaxK;
   uint64_t *cand_idx = cand_key + k;
+  unsigned int *partial = (unsigned int *)(cand_idx + k);
   if (ntiles < (uint64_t)k) {
     exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, nullptr, s);
     return hipGetLastError();
@@ -598,10 +718,9 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
   uint64_t lg = (ntiles + 255) / 256;
   if (lg > 1024) lg = 1024;
   hipLaunchKernelGGL(topk_list_tiles, dim3((unsigned)lg), dim3(256), 0, s, tkey, ntiles, sel, fast, qlist);
-  hipLaunchKernelGGL(topk_collect_tiles, dim3(4096), dim3(256), 0, s, probs, dtype, g, lbm, lbn, tilesN,
-                     (const uint64_t *)qlist, sel, fast, fkey, fidx);
-  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, fkey, fidx, k, dtype, idx_out, val_out, fast,
-                     (const unsigned int *)nullptr);
+  hipLaunchKernelGGL(topk_collect_tiles, dim3(kCollectGrid), dim3(256), 0, s, probs, dtype, g, lbm, lbn,
+                     tilesN, (const uint64_t *)qlist, sel, fast, fkey, fidx);
+  launch_rank_place(fkey, fidx, k, dtype, idx_out, val_out, fast, partial, s);
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, &fast->fallback,
              s);
   return hipGetLastError();

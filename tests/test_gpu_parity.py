@@ -356,6 +356,47 @@ def test_summary_equals_standalone_scans(case):
     assert tot0.item() == tot.item()
 
 
+def _tied_tile_network(ties_per_side, seed):
+    """Two tensors of 10 output qubits joined by one cut, with only the
+    identity row nonzero: P(x, y) = f(x) g(y) / 2.  f and g equal 1/32 on
+    `ties_per_side` arguments below 128 (one 128 x 128 tile of the final
+    step), so ties_per_side^2 entries tie exactly at the maximum 2^-11 inside
+    one tile; elsewhere they are below 1/64."""
+    from workloads.cutting import Network, TensorSpec
+    rng = np.random.default_rng(seed)
+    tensors = []
+    for j in range(2):
+        T = np.zeros((4, 1 << 10))
+        T[0] = rng.uniform(0.0, 1.0 / 64, size=1 << 10)
+        T[0, rng.choice(128, size=ties_per_side, replace=False)] = 1.0 / 32
+        tensors.append(TensorSpec(cut_ids=[0], outputs=list(range(10 * j, 10 * j + 10)), basis="pauli", data=T))
+    return Network(n=20, cuts=[(0, 1)], tensors=tensors)
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16x3"])
+@pytest.mark.parametrize("ties", [40, 80])
+def test_summary_many_ties_in_one_tile(form, ties):
+    """40^2 = 1600 tied candidates in one tile exceed a block's LDS stage
+    (the rest go to the candidate list directly); 80^2 = 6400 exceed the
+    candidate list, so the exact passes decide."""
+    spec = _tied_tile_network(ties, seed=ties)
+    N = tqc.Network.from_spec(spec)
+    P = tqc.Plan(N, precision=form)
+    plain = P.execute().clone()
+    ref = full_distribution(spec)
+    assert np.abs(plain.double().cpu().numpy() - ref).max() <= 1e-6 * ref.max()
+    assert (plain == 2.0 ** -11).sum().item() == ties * ties
+    for k in (1, 5, 37):
+        out, idx, val, tot, _ = P.execute_summary(k=k)
+        torch.cuda.synchronize()
+        assert torch.equal(out, plain)
+        ri, rv = oout.topk(out.cpu().numpy(), k)
+        assert np.array_equal(idx.cpu().numpy(), ri), (k, ties)
+        assert np.array_equal(val.cpu().numpy(), rv), (k, ties)
+        si, sv = tqc.topk(out, k)
+        assert torch.equal(idx, si) and torch.equal(val, sv)
+
+
 def test_summary_qaoa32_full_size():
     """The benchmark's step at its full size: 2^32 float32 entries, top-1000."""
     spec = qaoa.qaoa_network()
