@@ -353,17 +353,21 @@ __global__ void __launch_bounds__(256) topk_rank_count(const uint64_t *cand_key,
   __shared__ uint64_t sk[256];
   __shared__ uint64_t si[256];
   const int t = threadIdx.x;
-  const int jn = n - j0 < 256 ? n - j0 : 256;
-  if (t < jn) {
-    sk[t] = cand_key[j0 + t];
-    si[t] = cand_idx[j0 + t];
-  }
+  // past the end: (key 0, index ~0), which never sorts before a candidate
+  const bool live = j0 + t < n;
+  sk[t] = live ? cand_key[j0 + t] : 0ull;
+  si[t] = live ? cand_idx[j0 + t] : ~0ull;
   __syncthreads();
   const int i = i0 + t;
   if (i >= n) return;
   const uint64_t ki = cand_key[i], ii = cand_idx[i];
   unsigned int cnt = 0;
-  for (int j = 0; j < jn; ++j) cnt += (sk[j] > ki || (sk[j] == ki && si[j] < ii)) ? 1u : 0u;
+  // branch-free comparisons, several LDS reads in flight
+#pragma unroll 16
+  for (int j = 0; j < 256; ++j) {
+    const uint64_t a = sk[j], b = si[j];
+    cnt += (unsigned int)((a > ki) | ((a == ki) & (b < ii)));
+  }
   partial[blockIdx.y * kMaxK + i] = cnt;
 }
 
@@ -560,14 +564,15 @@ __global__ void __launch_bounds__(256) topk_list_tiles(const unsigned long long 
 }
 
 // 2) every entry >= tau0 of the listed tiles.  A block walks its share of
-//    the list (grid-strided) with kCollectDepth loads in flight per thread,
+//    the list (grid-strided) with several loads in flight per thread,
 //    stages its hits in LDS (one LDS atomic per wave and group of hits) and
 //    reserves its slots in the global list with one atomic at the end; hits
 //    past the kStage LDS slots go to the global list directly.  The stage is
 //    small so that the kernel fits beside a running final-step kernel of
 //    another stream (which leaves about 29 KB of a CU's LDS free).
-constexpr int kCollectGrid = 256;
-constexpr int kCollectDepth = 8;
+constexpr int kCollectGrid = 1024;
+constexpr int kCollectDepth = 16;  // float4 loads in flight per thread (vector form)
+constexpr int kGenericDepth = 8;   // scalar loads in flight per thread (general form)
 constexpr unsigned int kStage = 1024;
 
 // every lane of the wave calls it
@@ -606,29 +611,33 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
     // full tile whose two lowest output bits are tile bits: compact index x
     // (tile entries in output order) lands at base + deposit(x, lpos), and
     // x, x+1, x+2, x+3 are adjacent in the output
+    // x = r * 1024 + 4 * thread: the low 10 compact bits are fixed per
+    // thread, the run r sets the rest (uniform over the block)
     const uint32_t runs4 = (1u << (lbm + lbn)) / 1024u;
+    const int hb = lbm + lbn - 10;
+    const uint64_t lo = deposit_c<10>((uint64_t)threadIdx.x * 4, g.lpos, 10);
     for (uint64_t q = blockIdx.x; q < nq; q += gridDim.x) {
       const uint64_t t = qlist[q];
       const uint64_t tm = t / tilesN, tn = t % tilesN;
-      const uint64_t base = scatter_bits(tm << lbm, g.posM, g.lm) + scatter_bits(tn << lbn, g.posN, g.ln);
+      const uint64_t base =
+          scatter_bits(tm << lbm, g.posM, g.lm) + scatter_bits(tn << lbn, g.posN, g.ln) + lo;
       for (uint32_t r0 = 0; r0 < runs4; r0 += kCollectDepth) {
         float4 v[kCollectDepth];
-        uint64_t at[kCollectDepth];
+#pragma unroll
+        for (int d = 0; d < kCollectDepth; ++d)
+          if (r0 + d < runs4)
+            v[d] = *(const float4 *)((const float *)p + base + deposit_c<6, 10>((uint64_t)(r0 + d), g.lpos, hb));
 #pragma unroll
         for (int d = 0; d < kCollectDepth; ++d) {
-          const uint32_t x = (r0 + d) * 1024u + threadIdx.x * 4u;
-          at[d] = base + deposit_c<16>((uint64_t)x, g.lpos, lbm + lbn);
-          if (r0 + d < runs4) v[d] = *(const float4 *)((const float *)p + at[d]);
-        }
+          if (r0 + d < runs4) {  // uniform over the block
+            const uint64_t at = base + deposit_c<6, 10>((uint64_t)(r0 + d), g.lpos, hb);
+            const float e[4] = {v[d].x, v[d].y, v[d].z, v[d].w};
 #pragma unroll
-        for (int d = 0; d < kCollectDepth; ++d) {
-          if (r0 + d >= runs4) break;  // uniform over the block
-          const float e[4] = {v[d].x, v[d].y, v[d].z, v[d].w};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const uint32_t u = __float_as_uint(e[c]);
-            const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
-            stage_hit(key >= tau0, key, at[d] + c, &bcount, bk, bi, fast, cand_key, cand_idx);
+            for (int c = 0; c < 4; ++c) {
+              const uint32_t u = __float_as_uint(e[c]);
+              const uint64_t key = (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+              stage_hit(key >= tau0, key, at + c, &bcount, bk, bi, fast, cand_key, cand_idx);
+            }
           }
         }
       }
@@ -638,11 +647,11 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
     for (uint64_t q = blockIdx.x; q < nq; q += gridDim.x) {
       const uint64_t t = qlist[q];
       const uint64_t m0 = (t / tilesN) << lbm, n0 = (t % tilesN) << lbn;
-      for (uint32_t r0 = 0; r0 < runs; r0 += kCollectDepth) {
-        uint64_t key[kCollectDepth], at[kCollectDepth];
-        bool ok[kCollectDepth];
+      for (uint32_t r0 = 0; r0 < runs; r0 += kGenericDepth) {
+        uint64_t key[kGenericDepth], at[kGenericDepth];
+        bool ok[kGenericDepth];
 #pragma unroll
-        for (int d = 0; d < kCollectDepth; ++d) {
+        for (int d = 0; d < kGenericDepth; ++d) {
           const uint32_t e = (r0 + d) * 256u + threadIdx.x;
           const uint64_t rl = e >> lbn, cl = e & ((1u << lbn) - 1);
           ok[d] = r0 + d < runs && m0 + rl < M && n0 + cl < N;
@@ -650,7 +659,7 @@ __global__ void __launch_bounds__(256) topk_collect_tiles(const void *p, int dty
           key[d] = ok[d] ? sort_key(p, dtype, at[d]) : 0;
         }
 #pragma unroll
-        for (int d = 0; d < kCollectDepth; ++d)
+        for (int d = 0; d < kGenericDepth; ++d)
           stage_hit(ok[d] && key[d] >= tau0, key[d], at[d], &bcount, bk, bi, fast, cand_key, cand_idx);
       }
     }
