@@ -473,8 +473,8 @@ def cutfind_study(tqc, torch, workers=16):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--inflight", type=int, default=2,
                     help="independent reconstructions in flight (one plan, output and stream each)")
     ap.add_argument("--forms", default="fp32,bf16x3,bf16x6,fp16x3")
