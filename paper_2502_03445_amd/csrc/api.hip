@@ -364,6 +364,10 @@ static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
         a.inpos[a.nbits++] = o + 2 * (c - 1 - i);
         a.inpos[a.nbits++] = o + 2 * (c - 1 - i) + 1;
       }
+    // the maximum is the same in any visiting order: ascending source bit
+    // positions make consecutive threads read consecutive addresses (the
+    // packing order puts the cut digits, the slowest source bits, first)
+    std::sort(a.inpos, a.inpos + a.nbits);
     all[j] = a;
   }
   HIP_OK(launch_absmax(all.data(), m, s));
