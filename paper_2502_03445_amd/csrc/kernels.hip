@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(256) absmax_kernel(AbsMaxBatch ab) {
   __shared__ double red[256];
   const uint64_t total = 1ull << a.nbits;
   double mx = 0.0;
+#pragma unroll 4
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
        e += (uint64_t)gridDim.x * blockDim.x)
     mx = fmax(mx, gathered_abs(a, e));
@@ -124,6 +125,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 }
 
 // ============================================================ launchers
+// Reductions that end in one atomic per workgroup on a single address keep
+// their grids at one workgroup per CU: those atomics serialize (about 26 ns
+// each measured here), so 1024 workgroups spend ~27 us on them alone.
+constexpr unsigned kMaxGrid = 256;
+
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u) {
   uint64_t b = (n + 255) / 256;
   if (b < 1) b = 1;
@@ -307,7 +313,8 @@ hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s) {
       const uint64_t total = 1ull << args[i0 + i].nbits;
       most = total > most ? total : most;
     }
-    hipLaunchKernelGGL(absmax_kernel, dim3(grid_for(most, 1024), cnt), dim3(256), 0, s, ab);
+    // about 8 entries per thread: fewer workgroups, fewer serialized atomics
+    hipLaunchKernelGGL(absmax_kernel, dim3(grid_for(most / 8 + 1, kMaxGrid), cnt), dim3(256), 0, s, ab);
   }
   return hipGetLastError();
 }
@@ -349,12 +356,30 @@ struct F16Split {
   double *root_scale2;
 };
 
+// Operands whose length is a multiple of 4 and whose base is 16-byte aligned
+// (the planner's layouts always are) are read and written four entries at a
+// time; the scalar loop is the general case.
+__device__ inline bool f16_vec_ok(const F16Split &a, int y) {
+  return (a.n[y] & 3) == 0 && ((uintptr_t)a.src[y] & 15) == 0 && ((uintptr_t)a.hi[y] & 7) == 0 &&
+         ((uintptr_t)a.lo[y] & 7) == 0;
+}
+
 __global__ void __launch_bounds__(256) f16_absmax_kernel(F16Split a) {
   __shared__ float red[256];
   const int y = blockIdx.y;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   float mx = 0.f;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += (uint64_t)gridDim.x * blockDim.x)
-    mx = fmaxf(mx, fabsf(a.src[y][i]));
+  if (f16_vec_ok(a, y)) {
+    const float4 *v = (const float4 *)a.src[y];
+#pragma unroll 4
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y] / 4; i += stride) {
+      const float4 q = v[i];
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+    }
+  } else {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += stride)
+      mx = fmaxf(mx, fabsf(a.src[y][i]));
+  }
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
@@ -375,7 +400,28 @@ __global__ void __launch_bounds__(256) f16_split_kernel(F16Split a) {
   const int e = f16_exponent(a.maxbits[y]);
   if (blockIdx.x == 0 && y == 0 && threadIdx.x == 0)
     *a.root_scale2 = ldexp(*a.root_scale, -f16_exponent(a.maxbits[0]) - f16_exponent(a.maxbits[1]));
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += (uint64_t)gridDim.x * blockDim.x) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (f16_vec_ok(a, y)) {
+    const float4 *src = (const float4 *)a.src[y];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y] / 4; i += stride) {
+      const float4 q = src[i];
+      const float v[4] = {ldexpf(q.x, e), ldexpf(q.y, e), ldexpf(q.z, e), ldexpf(q.w, e)};
+      uint16_t hs[4], ls[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const _Float16 h = (_Float16)v[c];
+        const _Float16 l = (_Float16)(v[c] - (float)h);
+        hs[c] = __builtin_bit_cast(uint16_t, h);
+        ls[c] = __builtin_bit_cast(uint16_t, l);
+      }
+      const uint2 hw = {(uint32_t)hs[0] | ((uint32_t)hs[1] << 16), (uint32_t)hs[2] | ((uint32_t)hs[3] << 16)};
+      const uint2 lw = {(uint32_t)ls[0] | ((uint32_t)ls[1] << 16), (uint32_t)ls[2] | ((uint32_t)ls[3] << 16)};
+      ((uint2 *)a.hi[y])[i] = hw;
+      ((uint2 *)a.lo[y])[i] = lw;
+    }
+    return;
+  }
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n[y]; i += stride) {
     const float v = ldexpf(a.src[y][i], e);
     const _Float16 h = (_Float16)v;
     const _Float16 l = (_Float16)(v - (float)h);
@@ -401,8 +447,8 @@ hipError_t launch_f16_split(const float *src0, uint64_t n0, uint16_t *hi0, uint1
   a.root_scale2 = root_scale2;
   const uint64_t most = n0 > n1 ? n0 : n1;
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, s, maxbits, (uint64_t)2);
-  hipLaunchKernelGGL(f16_absmax_kernel, dim3(grid_for(most, 1024), 2), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(f16_split_kernel, dim3(grid_for(most), 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(f16_absmax_kernel, dim3(grid_for(most / 4 + 1, kMaxGrid), 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(f16_split_kernel, dim3(grid_for(most / 4 + 1), 2), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
