@@ -305,6 +305,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
             "runs": runs,
             "speedup_graph_over_sequential": runs["sequential_plain"]["batch_ms"] /
                                              runs["graph_4streams"]["batch_ms"],
+            "speedup_graph8_over_sequential": runs["sequential_plain"]["batch_ms"] /
+                                              runs["graph_8streams"]["batch_ms"],
             "outputs_equal_plain_execution": same,
             "largest_jobs": sorted(meta, reverse=True)[:3]}
 
