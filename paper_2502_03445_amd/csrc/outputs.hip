@@ -451,12 +451,25 @@ __global__ void __launch_bounds__(256) topk_collect_fast(const void *p, int dtyp
   }
 }
 
-__global__ void topk_fast_init(TopkState *fast) {
+// One launch sets up a fast form: its counters, the selection state over the
+// chunk or tile maxima, the exact passes' state (used only if they run; the
+// last selection pass leaves the histogram cleared for them) and the
+// histogram.
+__global__ void __launch_bounds__(256) topk_init_fast(TopkState *sel, TopkState *st, TopkState *fast,
+                                                      unsigned long long *hist, int keybits, int k) {
   if (threadIdx.x == 0) {
+    TopkState *both[2] = {sel, st};
+    for (int i = 0; i < 2; ++i) {
+      both[i]->prefix = 0;
+      both[i]->hi_shift = keybits;
+      both[i]->kr = (unsigned long long)k;
+      both[i]->n_gt = 0;
+    }
     fast->ncand = 0;
     fast->fallback = 0;
     fast->nq = 0;
   }
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
 }
 
 uint64_t topk_scratch_bytes(uint64_t len, int k) {
@@ -471,10 +484,10 @@ uint64_t topk_scratch_bytes(uint64_t len, int k) {
 static void exact_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
                        double *val_out, TopkState *st, unsigned long long *hist,
                        unsigned long long *blockcnt, uint64_t *cand_key, uint64_t *cand_idx,
-                       const unsigned int *gate, hipStream_t s) {
+                       const unsigned int *gate, hipStream_t s, bool initialized = false) {
   const uint64_t nblocks = (len + kChunk - 1) / kChunk;
   const int keybits = dtype == 1 ? 32 : 64;
-  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, st, hist, keybits, k, gate);
+  if (!initialized) hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, st, hist, keybits, k, gate);
   uint64_t hb = (len + 255) / 256;
   if (hb > kChunkGrid) hb = kChunkGrid;
   for (int resolved = 0; resolved < keybits;) {
@@ -519,10 +532,8 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
     return hipGetLastError();
   }
   // fast path: tau0 = k-th largest chunk maximum <= the k-th largest entry
-  hipLaunchKernelGGL(topk_fast_init, dim3(1), dim3(64), 0, s, fast);
+  hipLaunchKernelGGL(topk_init_fast, dim3(1), dim3(256), 0, s, sel, st, fast, hist, keybits, k);
   hipLaunchKernelGGL(topk_chunk_max, dim3((unsigned)nchunks), dim3(256), 0, s, probs, dtype, len, cmax);
-  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, sel, hist, keybits, k,
-                     (const unsigned int *)nullptr);
   uint64_t hb = (nchunks + 255) / 256;
   if (hb > 8192) hb = 8192;
   for (int resolved = 0; resolved < keybits;) {
@@ -538,7 +549,7 @@ hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   launch_rank_place(fkey, fidx, k, dtype, idx_out, val_out, fast, partial, s);
   // exact passes, skipped on the device unless the fast path gave up
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx,
-             &fast->fallback, s);
+             &fast->fallback, s, true);
   return hipGetLastError();
 }
 
@@ -713,8 +724,7 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
   }
   // float32 keys occupy the low 32 bits
   const int tbits = dtype == 1 ? 32 : 64;
-  hipLaunchKernelGGL(topk_fast_init, dim3(1), dim3(64), 0, s, fast);
-  hipLaunchKernelGGL(topk_init, dim3(1), dim3(256), 0, s, sel, hist, tbits, k, (const unsigned int *)nullptr);
+  hipLaunchKernelGGL(topk_init_fast, dim3(1), dim3(256), 0, s, sel, st, fast, hist, tbits, k);
   uint64_t hb = (ntiles + 255) / 256;
   if (hb > 8192) hb = 8192;
   for (int resolved = 0; resolved < tbits;) {
@@ -731,7 +741,7 @@ hipError_t launch_topk_tiles(const void *probs, int dtype, uint64_t len, const G
                      tilesN, (const uint64_t *)qlist, sel, fast, fkey, fidx);
   launch_rank_place(fkey, fidx, k, dtype, idx_out, val_out, fast, partial, s);
   exact_topk(probs, dtype, len, k, idx_out, val_out, st, hist, blockcnt, cand_key, cand_idx, &fast->fallback,
-             s);
+             s, true);
   return hipGetLastError();
 }
 
