@@ -688,7 +688,8 @@ def main():
         "config": {"workload": "qaoa32_regular3_p1_4sub_8cut_full_2^32",
                    "qubits": n, "subcircuits": len(spec.tensors), "cuts": spec.num_cuts,
                    "output_entries": entries, "chosen_form": chosen,
-                   "steps_per_pass": "transform+pack+contractions+top1000+sum"},
+                   "steps_per_pass": "transform+pack+contractions+top1000+sum",
+                   "reconstructions_in_flight": inflight},
         "chosen": chosen,
         "plain_fp32": {"value": entries / (plain["ms"] * 1e-3), "ms_per_step": plain["ms"],
                        "rel_err": plain["rel_err"],
