@@ -133,12 +133,12 @@ __global__ void __launch_bounds__(256) topk_hist(const void *p, int dtype, uint6
 }
 
 // Walks the bins from the top: thread t owns the t-th group of `per`
-// consecutive bins (from the largest down); group totals are scanned in LDS
+// consecutive bins (from the largest down); group totals are prefix-summed
 // and the one thread whose group holds the kr-th entry resolves the digit.
 __global__ void __launch_bounds__(256) topk_select(TopkState *st, unsigned long long *hist, int bits,
                                                    const unsigned int *gate) {
   if (gated_off(gate)) return;
-  __shared__ unsigned long long grp[256];
+  __shared__ unsigned long long grp[4];  // per-wave totals
   const int nb = 1 << bits;
   const int per = (nb + 255) / 256;
   const int t = threadIdx.x;
@@ -149,18 +149,18 @@ __global__ void __launch_bounds__(256) topk_select(TopkState *st, unsigned long 
     const int r = t * per + j;  // rank from the top
     if (r < nb) mine += hist[nb - 1 - r];
   }
-  grp[t] = mine;
-  __syncthreads();
-  if (t == 0) {  // exclusive scan of 256 group totals
-    unsigned long long run = 0;
-    for (int i = 0; i < 256; ++i) {
-      const unsigned long long v = grp[i];
-      grp[i] = run;
-      run += v;
-    }
+  // exclusive prefix of the 256 group totals: within each wave by shuffles,
+  // then the totals of the waves below
+  const int lane = t & 63, wave = t >> 6;
+  unsigned long long incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(incl, (unsigned int)o, 64);
+    if (lane >= o) incl += y;
   }
+  if (lane == 63) grp[wave] = incl;
   __syncthreads();
-  const unsigned long long before = grp[t];
+  unsigned long long before = incl - mine;
+  for (int w = 0; w < wave; ++w) before += grp[w];
   if (before < kr && before + mine >= kr) {
     unsigned long long cum = before;
     for (int j = 0; j < per; ++j) {
