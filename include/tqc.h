@@ -276,7 +276,7 @@ tqc_status tqc_find_cuts(int32_t num_qubits, int32_t num_gates, const int32_t *g
                          int32_t s_max, int32_t k_t, double q_max, int32_t *labels, int32_t *num_parts);
 
 /* ------------------------------------------------- heavy state selection
- * Sec. V, Alg. 1.  tqc_hss_select computes, for every tensor j and every
+ * Sec. IV, Alg. 1.  tqc_hss_select computes, for every tensor j and every
  * state i of its output qubits, the L2 norm of column i of its Pauli-basis
  * tensor over all rows (edge permutations), in float64 on the device
  * (deterministic order).  Every tensor starts with its heaviest state (ties:

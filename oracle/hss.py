@@ -1,4 +1,4 @@
-"""Heavy State Selection (Sec. V, Alg. 1) and its metrics (Eqs. (9)-(13)).
+"""Heavy State Selection (Sec. IV, Alg. 1) and its metrics (Eqs. (9)-(13)).
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 

@@ -1087,7 +1087,7 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
 
 
 // ------------------------------------------------- heavy state selection
-// Sec. V, Alg. 1: per tensor, the L2 norm of every output state over all
+// Sec. IV, Alg. 1: per tensor, the L2 norm of every output state over all
 // edge permutations (rows of the Pauli-basis tensor), computed on the device
 // in float64; then on the host every tensor starts with its heaviest state
 // and the other states join in descending norm order (ties: smaller tensor,

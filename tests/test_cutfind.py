@@ -61,6 +61,15 @@ def test_library_partition_equals_oracle(w_max, s_max, k_t, q_max):
         assert all(labels[g] == -1 for g, qs in enumerate(gates) if len(qs) == 1)
 
 
+@pytest.mark.parametrize("w_max,s_max,k_t,q_max,want", [(4, 100, 1, 6.0, [0, 0, 0, 1]), (4, 100, 1, 5.5, [0, 1, 2, 3]),
+                                                        (4, 100, 2, 1e4, [0, 0, 0, 1]), (10, 2, 2, 1e4, [0, 0, 1, 1])])
+def test_library_on_hand_worked_chain(w_max, s_max, k_t, q_max, want):
+    # the chain CZ(0,1), CZ(1,2), CZ(2,3), CZ(3,4) worked by hand from
+    # Table I (tests/test_oracle_cutfind.py explains each partition)
+    labels, parts = tqc.find_cuts(5, [(0, 1), (1, 2), (2, 3), (3, 4)], w_max, s_max, k_t, q_max)
+    assert list(labels) == want and parts == len(set(want))
+
+
 def test_find_cuts_rejects_bad_input():
     with pytest.raises(tqc.TqcError):
         tqc.find_cuts(4, [(0, 5)], 4, 10)

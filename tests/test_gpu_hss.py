@@ -1,4 +1,4 @@
-"""Heavy state selection (Sec. V, Alg. 1) on the GPU against the oracle.
+"""Heavy state selection (Sec. IV, Alg. 1) on the GPU against the oracle.
 
 Column norms are float64 sums in a different order on each side, so the
 selected subsets are compared exactly where the norms are apart and checked

@@ -251,9 +251,29 @@ def test_mlp_oracle_gradients_match_finite_differences():
         tm[i] -= eps
         num[i] = (mlp.loss(tp, X, t, F, H) - mlp.loss(tm, X, t, F, H)) / (2 * eps)
     assert np.abs(g - num).max() <= 1e-6 * max(1.0, np.abs(num).max())
-    # a planted mistake (ReLU gate dropped in the first layer) is caught
-    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta, F, H)
-    assert np.any(X @ W1 + b1 < 0)
+
+
+def test_mlp_oracle_one_unit_network_by_hand():
+    # F = H = 1, theta = (W1, b1, W2, b2, w3, b3) = (0.5, 0.25, -2, 3, 4, -1),
+    # worked by hand.  x = 2: z1 = 1.25, z2 = 0.5, y = 4 * 0.5 - 1 = 1; with
+    # t = 0.25, L = 0.75^2 and dL/dy = 1.5, so dw3 = 0.5 * 1.5, db3 = 1.5,
+    # dz2 = 1.5 * 4 = 6, dW2 = 1.25 * 6, db2 = 6, dz1 = 6 * -2 = -12,
+    # dW1 = 2 * -12, db1 = -12.
+    from oracle import mlp
+    theta = np.array([0.5, 0.25, -2.0, 3.0, 4.0, -1.0])
+    y, _ = mlp.forward(theta, [[2.0]], 1, 1)
+    assert y.tolist() == [1.0]
+    assert mlp.loss(theta, [[2.0]], [0.25], 1, 1) == 0.5625
+    assert mlp.gradients(theta, [[2.0]], [0.25], 1, 1).tolist() == [-24.0, -12.0, 7.5, 6.0, 0.75, 1.5]
+    # x = -2: z1 = -0.75 is cut by the first ReLU, z2 = 3, y = 11 (without
+    # that ReLU: 17); with t = 0, dL/dy = 22: dw3 = 66, db3 = 22, db2 = 88,
+    # and nothing flows into the first layer or W2 (h1 = 0)
+    y, _ = mlp.forward(theta, [[-2.0]], 1, 1)
+    assert y.tolist() == [11.0]
+    assert mlp.gradients(theta, [[-2.0]], [0.0], 1, 1).tolist() == [0.0, 0.0, 0.0, 88.0, 66.0, 22.0]
+    # the batch mean: both samples together halve and add the two gradients
+    g2 = mlp.gradients(theta, [[2.0], [-2.0]], [0.25, 0.0], 1, 1)
+    assert g2.tolist() == [-12.0, -6.0, 3.75, 47.0, 33.375, 11.75]
 
 
 def test_restrict_fixed_equals_entries_of_the_full_distribution():

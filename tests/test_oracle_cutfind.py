@@ -1,8 +1,11 @@
 """Pins of the cut-search oracle (Alg. 2-3, Table I, Eq. (6)): closed-form
-partitions of disconnected and unconstrained circuits, the hard constraints
-and termination on random circuits, agreement of its width count with the
-wire cutter's subcircuits, and exactness of the found cuts (reconstruction
-equals the uncut statevector)."""
+partitions of disconnected and unconstrained circuits, hand-worked merges
+where Table I's contraction-edge penalty (4^(x - K_t) + 1 above K_t, x / K_t
+below) and the largest contraction-edge count K_trial between the trial and a
+neighbour decide the partition, the hard constraints and termination on
+random circuits, agreement of its width count with the wire cutter's
+subcircuits, exactness of the found cuts (reconstruction equals the uncut
+statevector), and Eq. (6) at hand-computed values."""
 import math
 
 import numpy as np
@@ -92,7 +95,50 @@ def test_constraints_termination_and_exact_cuts():
     assert exact >= 3
 
 
-def test_qpu_runtime_of_one_uncut_circuit():
-    # Eq. (6) with no cuts: 2^w shots of (t layers * t_g + t_m)
-    assert math.isclose(cutfind.qpu_runtime([(0, 0, 10, 20)]), 2 ** 10 * (20e-7 + 1e-6))
-    assert math.isclose(cutfind.qpu_runtime([(1, 2, 3, 4)]), 3 * 16 * 8 * (4e-7 + 1e-6))
+# A chain of four two-qubit gates CZ(0,1), CZ(1,2), CZ(2,3), CZ(3,4): DAG
+# vertices v0..v3, edges e0 = v0-v1 (qubit 1), e1 = v1-v2 (qubit 2), e2 =
+# v2-v3 (qubit 3).  Worked by hand with K_t = 1, w_max = 4, s_max = 100:
+#   every first trial has w = 3, s = 2, and K_trial = 2: the union of its cut
+#   edges with those of a neighbour (e.g. {v0,v1}: {e1} | cuts({v2}) = {e1,e2};
+#   {v1,v2}: {e0,e2}), so its cost is 3/4 + 2/100 + (4^(2-1) + 1) = 5.77.
+#   With Q_max = 6 the tie goes to (v0, v1); then {v0,v1,v2} costs
+#   4/4 + 3/100 + 1/1 = 2.03 (its only neighbour v3 shares e2 alone), while
+#   the untouched pair (v2, v3) keeps its earlier 5.77 (Alg. 2 updates only
+#   the edges on the new partition), so v2 joins; adding v3 would make w = 5.
+#   With Q_max = 5.5 no trial is allowed and every gate stays alone.
+# Plausible misreadings give other partitions: K_trial = |cuts(T)| alone
+# makes (v0,v1) and (v2,v3) cost 1.77 each -> [0, 0, 1, 1] at Q_max = 6;
+# a penalty of 4^(x - K_t) without the +1 (4.77) or 2^(x - K_t) + 1 (3.77)
+# lets merges through at Q_max = 5.5.
+CHAIN4 = [(0, 1), (1, 2), (2, 3), (3, 4)]
+
+
+def test_contraction_edge_penalty_decides_the_merge():
+    lab = cutfind.greedy_graph_growing(5, CHAIN4, w_max=4, s_max=100, k_t=1, q_max=6.0)
+    assert [lab[g] for g in range(4)] == [0, 0, 0, 1]
+
+
+def test_penalty_plus_one_keeps_every_gate_alone_below_its_cutoff():
+    lab = cutfind.greedy_graph_growing(5, CHAIN4, w_max=4, s_max=100, k_t=1, q_max=5.5)
+    assert [lab[g] for g in range(4)] == [0, 1, 2, 3]
+
+
+def test_below_threshold_contraction_edges_cost_x_over_t():
+    # K_t = 2: every first trial costs 3/4 + 2/100 + 2/2 = 1.77 (ties to
+    # (v0, v1)); then {v0,v1,v2} costs 1 + 0.03 + 1/2 = 1.53 < 1.77, and v3
+    # cannot join (w = 5 > 4)
+    lab = cutfind.greedy_graph_growing(5, CHAIN4, w_max=4, s_max=100, k_t=2, q_max=1e4)
+    assert [lab[g] for g in range(4)] == [0, 0, 0, 1]
+    # the same chain with a binding gate count: s_max = 2 stops at pairs
+    lab = cutfind.greedy_graph_growing(5, CHAIN4, w_max=10, s_max=2, k_t=2, q_max=1e4)
+    assert [lab[g] for g in range(4)] == [0, 0, 1, 1]
+
+
+def test_qpu_runtime_worked_values():
+    # Eq. (6) with the paper's t_g = 1e-7 s and t_m = 1e-6 s, worked by hand:
+    # one uncut 10-qubit, 20-layer circuit: 1024 * (2e-6 + 1e-6) = 3.072e-3 s;
+    # u = 1, d = 1, w = 3, t = 5: 3 * 4 * 8 * 1.5e-6 = 1.44e-4 s;
+    # (u, d) = (2, 0) and (0, 2) at w = 4, t = 10: (144 + 256) * 2e-6 = 8e-4 s
+    assert math.isclose(cutfind.qpu_runtime([(0, 0, 10, 20)]), 3.072e-3, rel_tol=1e-12)
+    assert math.isclose(cutfind.qpu_runtime([(1, 1, 3, 5)]), 1.44e-4, rel_tol=1e-12)
+    assert math.isclose(cutfind.qpu_runtime([(2, 0, 4, 10), (0, 2, 4, 10)]), 8.0e-4, rel_tol=1e-12)
