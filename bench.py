@@ -31,6 +31,19 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 HBM_PEAK = 8.0e12
 TOL = 1e-6
 TOPK = 1000
+CPU_SHARE = 16  # host cores that belong to one GPU's share of the node
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 _SPEC = None
@@ -567,9 +580,11 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / count, live[-1]
 
-    # sample of output entries checked against the oracle
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
+    # sample of output entries checked against the oracle: one worker per
+    # host core of this GPU's CPU share (16 cores per GPU on the MI355X hosts
+    # this runs on, however many cores the host shows)
+    host_cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(host_cores, CPU_SHARE))
     rng = np.random.default_rng(20250207)
 
     forms = args.forms.split(",")
@@ -706,7 +721,7 @@ def main():
     }
     if not args.no_cpu and cpu_dt is not None:
         line["cpu_baseline"] = {"value": len(xs_all) / cpu_dt, "unit": "probs/s", "cores": cores,
-                                "kind": "oracle",
+                                "kind": "oracle", "cpu_model": cpu_model(), "host_cores_visible": host_cores,
                                 "sample": f"{len(xs_all)} entries ({sample_n} seeded uniform + "
                                           f"{len(tops)} GPU top entries), float64 brute force over "
                                           f"4^{spec.num_cuts} cut assignments, {cpu_dt:.1f} s"}

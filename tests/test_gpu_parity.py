@@ -170,6 +170,30 @@ def test_split_k_steps(case, form):
     assert np.all(err <= GAMMA[form] * A + 2.0 ** -149), (SPLITK_CASES[case], form, (err / A).max(), P.steps)
 
 
+def _nonnegative(spec):
+    """The same network with |T_j| for every tensor: no cancellation, so
+    sum_sigma prod_j |T_j| = P(x) and each reduced form's float32 chains
+    carry only their own rounding, ~1e-8 of P per entry (a CPU emulation of
+    256-long float32 chains folded in float64 over K = 65536 positive terms
+    gave 1.6e-8).  Dropping one of 256 k splits would lose ~0.4 % of P."""
+    from workloads.cutting import Network, TensorSpec
+    ts = [TensorSpec(cut_ids=list(t.cut_ids), outputs=list(t.outputs), basis=t.basis, data=np.abs(t.data))
+          for t in spec.tensors]
+    return Network(n=spec.n, cuts=list(spec.cuts), tensors=ts)
+
+
+@pytest.mark.parametrize("case", range(len(SPLITK_CASES)))
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x6", "fp16x3", "bf16x3"])
+def test_split_k_steps_without_cancellation(case, form):
+    (m, K, outs), sliced = SPLITK_CASES[case]
+    spec = _nonnegative(synthetic.random_network(m, K, outs, seed=1300 + case))
+    got, P = run(spec, precision=form, sliced=sliced)
+    assert any(st["log2_k"] >= 9 for st in P.steps)
+    ref = entries_variable_elimination(spec, np.arange(1 << spec.n, dtype=np.uint64))
+    ok, e = tol_ok(form, got, ref)
+    assert ok, (SPLITK_CASES[case], form, e, P.steps)
+
+
 def test_orders_agree_fp64():
     spec = synthetic.random_network(4, 6, [3, 3, 3, 3], seed=77)
     orders = [[(0, 1), (4, 2), (5, 3)], [(2, 3), (0, 1), (4, 5)], [(3, 1), (4, 0), (5, 2)]]
@@ -196,7 +220,7 @@ def test_slicing_is_exact(form, out_dtype):
 
 
 def test_budget_slicing_and_resume():
-    spec = synthetic.random_network(5, 12, [2, 2, 2, 2, 2], seed=9)
+    spec = synthetic.random_network(5, 14, [2, 2, 2, 2, 2], seed=9)
     ref = oracle_full(spec)
     N = tqc.Network.from_spec(spec)
     free = tqc.Plan(N, precision="fp64", out_dtype="f64")
@@ -415,6 +439,78 @@ def test_summary_qaoa32_full_size():
         torch.cuda.empty_cache()
 
 
+def test_qaoa32_sampled_and_top_entries_against_oracle():
+    """The benchmark's workload at full size (2^32 float32 entries): 10^4
+    seeded uniform entries plus each form's top-1000 against the oracle
+    (variable elimination, which equals the 4^8-term brute force), in the
+    forms the benchmark may choose, at 1e-6 * max P; bf16x3 at its bound."""
+    spec = qaoa.qaoa_network()
+    N = tqc.Network.from_spec(spec)
+    rng = np.random.default_rng(20251203)
+    sample = rng.integers(0, 1 << 32, size=10000, dtype=np.uint64)
+    got, tops = {}, []
+    forms = ("fp32", "fp16x3", "bf16x6", "bf16x3")
+    out = torch.empty(1 << 32, dtype=torch.float32, device="cuda")
+    for form in forms:
+        P = tqc.Plan(N, precision=form)
+        _, idx, val, tot, _ = P.execute_summary(out, k=1000)
+        top = idx.cpu().numpy().astype(np.uint64)
+        tops.append(top)
+        xs = np.concatenate([sample, top])
+        got[form] = (xs, out[torch.from_numpy(xs.astype(np.int64)).cuda()].double().cpu().numpy(),
+                     abs(tot.item() - 1.0))
+        del P
+    del out
+    torch.cuda.empty_cache()
+    xs_all = np.unique(np.concatenate([sample] + tops))
+    ref_all = entries_variable_elimination(spec, xs_all)
+    for form in forms:
+        xs, g, dtot = got[form]
+        ref = ref_all[np.searchsorted(xs_all, xs)]
+        scale = np.abs(ref).max()
+        bound = 3e-5 if form == "bf16x3" else 1e-6
+        assert np.abs(g - ref).max() <= bound * scale, (form, np.abs(g - ref).max() / scale)
+        assert dtot <= 1e-6, (form, dtot)
+    # the top-1000 of every form are the 1000 largest of the checked set
+    # under the oracle, up to entries within the form's error of the cut
+    ref_top = np.sort(ref_all)[::-1][:1000]
+    for form, top in zip(forms, tops):
+        vals = ref_all[np.searchsorted(xs_all, top)]
+        bound = 3e-5 if form == "bf16x3" else 1e-6
+        assert vals.min() >= ref_top[-1] - 2 * bound * ref_top[0], form
+
+
+# ------------------------------------------ large jobs of the batch workload
+# n 20..28 qubits, 2..5 subcircuits, 2..10 cuts (exact subcircuit tensors):
+# 10^3 seeded entries plus the top-100 of each job against the oracle, run
+# through the graph executor like the batch benchmark; the total is 1
+LARGE_JOBS = [18, 7, 1, 5, 28, 3, 22, 2, 16, 11, 19, 46]
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16x3"])
+def test_large_batch_jobs_against_oracle(form):
+    from oracle.pauli import network_pauli_tensors as npt
+    from workloads import batch
+    specs = [batch.job(i) for i in LARGE_JOBS]
+    assert sorted({s.n for s in specs}) == [20, 21, 22, 23, 24, 25, 26, 27, 28]
+    nets = [tqc.Network.from_spec(s) for s in specs]
+    plans = [tqc.Plan(n, precision=form) for n in nets]
+    mj = tqc.Multi(plans, use_graph=True, streams=8)
+    mj.execute()
+    torch.cuda.synchronize()
+    for i, (spec, o) in enumerate(zip(specs, mj.outs)):
+        rng = np.random.default_rng(4000 + LARGE_JOBS[i])
+        sample = rng.integers(0, 1 << spec.n, size=1000, dtype=np.uint64)
+        top, _ = tqc.topk(o, 100)
+        xs = np.concatenate([sample, top.cpu().numpy().astype(np.uint64)])
+        ref = entries_variable_elimination(spec, xs, tensors=npt(spec))
+        g = o[torch.from_numpy(xs.astype(np.int64)).cuda()].double().cpu().numpy()
+        scale = np.abs(ref).max()
+        assert np.abs(g - ref).max() <= 1e-6 * scale, (LARGE_JOBS[i], spec.n, np.abs(g - ref).max() / scale)
+        tot = tqc.marginal(o, spec.n, []).item()
+        assert abs(tot - 1.0) <= 1e-6, (LARGE_JOBS[i], tot)
+
+
 # ------------------------------------------ persistent final-step kernel
 # roots with 128 x 128 tiles, K <= 256 and float32 output run on the
 # persistent kernel; tile_policy = 2 forces the general kernel for comparison
@@ -469,9 +565,9 @@ def test_precision_network_slice_full_size():
     got = ref[torch.from_numpy(local.astype(np.int64)).cuda()].cpu().numpy()
     assert np.abs(got - want).max() <= 1e-12, np.abs(got - want).max()
     scale = ref.abs().max().item()
-    # fp16x3: float32 pairwise steps, then 22-bit final operands (two bits
-    # fewer than float32): up to 4x the float32 error of this network
-    bounds = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5, "fp16x3": 4e-6}
+    # bf16x3 misses 1e-6 here (6.7e-6 measured, inherent to 2^-16 products)
+    # and is held to its analytic bound; it is never the chosen form
+    bounds = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5, "fp16x3": 1e-6}
     for form, bound in bounds.items():
         P = tqc.Plan(N, precision=form, out_dtype="f32", fixed=fixed)
         out = P.execute()
