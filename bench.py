@@ -133,28 +133,8 @@ def precision_study(tqc, torch):
 
 
 def _random_order(rng, spec, fixed, temperature=2.0):
-    """A randomized greedy contraction order: among pairs of nodes sharing a
-    cut, pick the one whose result has the fewest index bits plus Gumbel noise
-    (node ids grow as in the plan API: the result of step s is node m + s)."""
-    m = len(spec.tensors)
-    cuts = {i: set(t.cut_ids) for i, t in enumerate(spec.tensors)}
-    outs = {i: sum(1 for q in t.outputs if q not in fixed) for i, t in enumerate(spec.tensors)}
-    order, nid = [], m
-    while len(cuts) > 1:
-        best, pick = None, None
-        for a in cuts:
-            for b in cuts:
-                if a < b and cuts[a] & cuts[b]:
-                    bits = 2 * len(cuts[a] ^ cuts[b]) + outs[a] + outs[b]
-                    score = bits + temperature * rng.gumbel()
-                    if best is None or score < best:
-                        best, pick = score, (a, b)
-        a, b = pick
-        order.append((a, b))
-        cuts[nid] = cuts.pop(a) ^ cuts.pop(b)
-        outs[nid] = outs.pop(a) + outs.pop(b)
-        nid += 1
-    return order
+    from workloads.synthetic import random_contraction_order
+    return random_contraction_order(rng, spec, fixed, temperature)
 
 
 def costmodel_study(tqc, torch, candidates=10000):
@@ -198,25 +178,36 @@ def costmodel_study(tqc, torch, candidates=10000):
     torch.cuda.synchronize()
     refmax = ref.abs().max().item()
     res = {}
-    for name, kw in (("roofline_dp", dict(cost="flopbyte")),
-                     (f"mlp_{candidates}", dict(cost="mlp", cost_model=model, num_candidates=candidates,
-                                                 seed=3))):
+    variants = (("roofline_dp", dict(cost="flopbyte")),
+                (f"mlp_{candidates}", dict(cost="mlp", cost_model=model, num_candidates=candidates, seed=3)),
+                ("measured_mlp_top4", dict(cost="measured", cost_model=model, num_candidates=candidates,
+                                           num_measured=4, seed=3)),
+                ("measured_roofline_top4", dict(cost="measured", num_candidates=candidates, num_measured=4,
+                                                seed=3)))
+    for name, kw in variants:
         t0 = time.perf_counter()
-        plan = tqc.Plan(net, precision="fp32", out_dtype="f64", fixed=fixed, **kw)
+        plan = tqc.Plan(net, precision="fp32", out_dtype="f32", fixed=fixed, **kw)
         plan_ms = (time.perf_counter() - t0) * 1e3
         out = plan.output_tensor()
         ms = _median_ms(plan, out, 15)
+        st = plan.stats
         res[name] = {"execute_ms": ms, "plan_ms": plan_ms, "end_to_end_ms": plan_ms + ms,
-                     "predicted_ms": plan.stats["predicted_seconds"] * 1e3, "flops": plan.stats["flops"],
-                     "bytes": plan.stats["bytes"],
-                     "rel_err_vs_fp64": (out - ref).abs().max().item() / refmax}
-        print(f"# {name}: plan {plan_ms:.1f} ms, execute {ms:.3f} ms", file=sys.stderr, flush=True)
+                     "predicted_ms": st["predicted_seconds"] * 1e3, "flops": st["flops"],
+                     "bytes": st["bytes"], "rel_err_vs_fp64": (out.double() - ref).abs().max().item() / refmax}
+        if kw["cost"] == "measured":
+            res[name].update(num_measured=st["num_measured"], judge_ms=st["measured_seconds"] * 1e3,
+                             judge_fallback_ms=st["fallback_measured_seconds"] * 1e3,
+                             judge_rel_err=st["checked_rel_error"])
+        print(f"# {name}: plan {plan_ms:.1f} ms, execute {ms:.3f} ms, err {res[name]['rel_err_vs_fp64']:.2e}",
+              file=sys.stderr, flush=True)
         del plan
-    mlp = res[f"mlp_{candidates}"]
+    dp = res["roofline_dp"]["execute_ms"]
     return {"study": "costmodel", "workload": spec.meta["name"], "candidates": candidates,
             "train_rows": len(secs), "train_loss_first_last": [float(losses[0]), float(losses[-1])],
-            "plans": res, "execute_speedup_mlp_over_dp": res["roofline_dp"]["execute_ms"] / mlp["execute_ms"],
-            "end_to_end_speedup_mlp_over_dp": res["roofline_dp"]["end_to_end_ms"] / mlp["end_to_end_ms"]}
+            "plans": res,
+            "execute_speedup_over_dp": {k: dp / v["execute_ms"] for k, v in res.items()},
+            "end_to_end_speedup_over_dp": {k: res["roofline_dp"]["end_to_end_ms"] / v["end_to_end_ms"]
+                                           for k, v in res.items()}}
 
 
 def _batch_job(i):

@@ -132,8 +132,31 @@ void tqc_network_destroy(tqc_network_t net);
  * Contraction order (Sec. III-E1), two-level slicing (Sec. III-E2) and the
  * per-step GEMM mapping.  The planner scores candidate plans with a
  * roofline cost (flops / MFMA peak vs bytes / HBM bandwidth per step, the
- * refinement of Eq. (7)) or with a trained cost model. */
-typedef enum { TQC_COST_FLOPBYTE = 0, TQC_COST_MLP = 1 } tqc_cost_kind;
+ * refinement of Eq. (7)) or with a trained cost model.
+ *   TQC_COST_FLOPBYTE  the roofline model: exact dynamic programming over
+ *                      subsets (up to 13 tensors), greedy beyond.  Host only.
+ *   TQC_COST_MLP       slicing from the roofline planner; the order that the
+ *                      trained model (cost_model) predicts fastest among
+ *                      num_candidates randomised-greedy orders and the
+ *                      roofline order.  Host plus model inference.
+ *   TQC_COST_MEASURED  measured time as the judge (Sec. VIII-A observes that
+ *                      flops over peak misjudges GPU time): slicing from the
+ *                      roofline planner; the roofline plan and the
+ *                      num_measured orders ranked best among num_candidates
+ *                      sampled ones (by cost_model if given, else by the
+ *                      roofline model) are each executed on the current
+ *                      device at full size (one warm-up, median of 5 timed
+ *                      runs, HIP events on a private stream); unless the
+ *                      form is FP64, each result is compared over every
+ *                      entry with a float64 run of the roofline plan, and
+ *                      candidates above max_rel_error are rejected.  The
+ *                      fastest accepted plan is returned, the roofline plan
+ *                      when no other is accepted (the fallback).  Needs the
+ *                      network's values, device memory for one output, a
+ *                      float64 reference and one candidate workspace at a
+ *                      time (freed before return); synchronous.  The
+ *                      measured-only fields of tqc_plan_stats report it. */
+typedef enum { TQC_COST_FLOPBYTE = 0, TQC_COST_MLP = 1, TQC_COST_MEASURED = 2 } tqc_cost_kind;
 
 typedef struct {
   tqc_precision precision;     /* contraction form                          */
@@ -154,6 +177,10 @@ typedef struct {
   int32_t tile_policy;         /* 0 fixed default tiles, 1 autotuned table,
                                   2 fixed tiles and no persistent final-step
                                   kernel (the general GEMM for every step)  */
+  int32_t num_measured;        /* TQC_COST_MEASURED: shortlisted orders timed
+                                  besides the roofline plan (0 = 4)          */
+  double max_rel_error;        /* TQC_COST_MEASURED: largest accepted
+                                  max|P - P_ref| / max|P_ref| (0 = 1e-6)     */
 } tqc_plan_options;
 
 void tqc_plan_options_default(tqc_plan_options *opt);
@@ -174,6 +201,13 @@ typedef struct {
   double predicted_seconds;    /* cost model used by the planner              */
   uint64_t workspace_bytes;    /* device workspace the plan allocates         */
   double plan_seconds;         /* host time spent planning                    */
+  int32_t precision;           /* tqc_precision of the plan                   */
+  int32_t out_dtype;           /* tqc_dtype of its output                     */
+  /* TQC_COST_MEASURED only (0 otherwise): */
+  int32_t num_measured;        /* plans timed, the roofline plan included     */
+  double measured_seconds;     /* median device time of the chosen plan       */
+  double fallback_measured_seconds; /* ... of the roofline plan               */
+  double checked_rel_error;    /* its max|P - P_ref| / max|P_ref|; -1 for FP64 */
 } tqc_plan_stats;
 
 tqc_status tqc_plan_get_stats(tqc_plan_t plan, tqc_plan_stats *st);
@@ -189,6 +223,48 @@ typedef struct {
 
 tqc_status tqc_plan_get_step(tqc_plan_t plan, int32_t step, tqc_step_info *info);
 tqc_status tqc_plan_get_sliced(tqc_plan_t plan, int32_t *cuts_out /* num_sliced */);
+
+/* Plan blobs.  A plan is a property of the network's structure, not of its
+ * values (Sec. II-A: the subcircuit tensors change with every run of the
+ * subcircuits; Sec. III-E: order and slicing depend only on which tensors
+ * share which cuts), so a plan made once can be stored and reused.
+ * tqc_plan_serialize writes the plan's decisions (contraction order, sliced
+ * cuts in slicing order, fixed qubits and values, precision, output dtype,
+ * tile policy, each step's tile, the predicted time) and the network
+ * structure it was made for (qubit count, cut ends, each tensor's basis, cut
+ * list and output qubits) to buf, host memory: a little-endian byte string
+ * ending in a 64-bit FNV-1a hash of the rest.  With buf = NULL it only
+ * stores the size in *len; otherwise *len is the capacity on entry and the
+ * size written on return.
+ * tqc_plan_deserialize rebuilds the plan on `net`, which must have the same
+ * structure (values may differ); executing it gives bit-identical results to
+ * the original plan on the same network.  Host only.
+ * Errors: INVALID_ARG (null, truncated or corrupt blob, bad hash), SHAPE
+ * (capacity too small), TOPOLOGY (structure differs). */
+tqc_status tqc_plan_serialize(tqc_plan_t plan, void *buf, uint64_t *len);
+tqc_status tqc_plan_deserialize(tqc_network_t net, const void *buf, uint64_t len, tqc_plan_t *out);
+
+/* Caller-owned workspace.  tqc_plan_workspace_bytes gives the size of one
+ * device region that holds every buffer the plan's execution uses (float64
+ * Pauli tensors of raw inputs, transform scratch, split-k partials, packed
+ * operands and intermediates of every step, operand scales, the float64
+ * accumulator of the slice sum (Sec. III-E2) for float32 output, and the
+ * root tile statistics or standalone scan scratch of tqc_execute_summary for
+ * any k <= 4096 and any tile choice).  tqc_plan_set_workspace binds such a
+ * region (device memory on the network's device, 256-byte aligned, at least
+ * that many bytes; e.g. a torch tensor): the library clears it on `stream`
+ * and from then on tqc_execute, tqc_execute_profiled, tqc_execute_summary,
+ * tqc_execute_slices, tqc_plan_autotune and the multi-job executor allocate
+ * no device memory for this plan.  The region stays the caller's: keep it
+ * alive while the plan may run, and never let two plans share one region.
+ * Buffers the library had allocated for the plan are freed first (hipFree
+ * waits for the device).  workspace = NULL returns to library-owned
+ * buffers, allocated on the next execute.  Before the first execute the
+ * call uploads the network (tqc_network_upload).
+ * Errors: INVALID_ARG (misaligned), SHAPE (too small), OUT_OF_MEMORY (the
+ * network upload), DEVICE. */
+tqc_status tqc_plan_workspace_bytes(tqc_plan_t plan, uint64_t *bytes);
+tqc_status tqc_plan_set_workspace(tqc_plan_t plan, void *workspace, uint64_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ execute
  * Run the plan: Pauli-basis transform of raw tensors (float64), packing of
@@ -236,6 +312,25 @@ tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
  * array of 2^num_keep doubles; num_keep <= 24. */
 tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
                         int32_t num_keep, const int32_t *keep, double *out, void *stream);
+
+/* The scratch of tqc_topk and tqc_marginal above is library-owned: one
+ * device buffer per (device, stream), reused by calls on that stream and
+ * grown by synchronizing the stream; calls on different streams never share
+ * memory.  The _ws forms below take the scratch from the caller instead and
+ * allocate nothing: workspace is device memory of at least the bytes the
+ * matching _workspace_bytes call reports, 256-byte aligned, used only on
+ * `stream` until the call's work is done; its contents on entry do not
+ * matter.  Results equal the library-scratch forms bit for bit.
+ * Errors: as tqc_topk / tqc_marginal, plus SHAPE (workspace too small) and
+ * INVALID_ARG (workspace NULL or misaligned). */
+tqc_status tqc_topk_workspace_bytes(uint64_t len, int32_t k, uint64_t *bytes);
+tqc_status tqc_topk_ws(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
+                       uint64_t *idx_out, double *val_out, void *workspace, uint64_t ws_bytes,
+                       void *stream);
+tqc_status tqc_marginal_workspace_bytes(int32_t num_qubits, int32_t num_keep, uint64_t *bytes);
+tqc_status tqc_marginal_ws(const void *probs, tqc_dtype dtype, int32_t num_qubits, int32_t num_keep,
+                           const int32_t *keep, double *out, void *workspace, uint64_t ws_bytes,
+                           void *stream);
 
 /* One reconstruction and its summary: tqc_execute into out, then the k
  * largest entries of out (as tqc_topk: top_idx / top_val, device arrays of k

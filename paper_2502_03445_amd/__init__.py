@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libtqc.so")
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
 DTYPES = {"f64": 0, "f32": 1}
 BASES = {"raw": 0, "pauli": 1}
-COST = {"flopbyte": 0, "mlp": 1}
+COST = {"flopbyte": 0, "mlp": 1, "measured": 2}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -53,7 +53,8 @@ class PlanOptions(ctypes.Structure):
                 ("num_sliced", ctypes.c_int32), ("sliced_cuts", _i32p),
                 ("cost_kind", ctypes.c_int), ("cost_model", ctypes.c_void_p),
                 ("num_candidates", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("tile_policy", ctypes.c_int32)]
+                ("tile_policy", ctypes.c_int32), ("num_measured", ctypes.c_int32),
+                ("max_rel_error", ctypes.c_double)]
 
 
 class PlanStats(ctypes.Structure):
@@ -62,7 +63,10 @@ class PlanStats(ctypes.Structure):
                 ("num_slices", ctypes.c_uint64), ("out_entries", ctypes.c_uint64),
                 ("flops", ctypes.c_double), ("mults_per_state", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("predicted_seconds", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_uint64), ("plan_seconds", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_uint64), ("plan_seconds", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("out_dtype", ctypes.c_int32),
+                ("num_measured", ctypes.c_int32), ("measured_seconds", ctypes.c_double),
+                ("fallback_measured_seconds", ctypes.c_double), ("checked_rel_error", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -139,6 +143,14 @@ def _declare(L):
         "tqc_costmodel_save": [vp, ctypes.c_char_p],
         "tqc_costmodel_load": [ctypes.c_char_p, ctypes.POINTER(vp)],
         "tqc_plan_step_features": [vp, ctypes.POINTER(ctypes.c_float), i32],
+        "tqc_plan_serialize": [vp, vp, ctypes.POINTER(u64)],
+        "tqc_plan_deserialize": [vp, vp, u64, ctypes.POINTER(vp)],
+        "tqc_plan_workspace_bytes": [vp, ctypes.POINTER(u64)],
+        "tqc_plan_set_workspace": [vp, vp, u64, vp],
+        "tqc_topk_workspace_bytes": [u64, i32, ctypes.POINTER(u64)],
+        "tqc_topk_ws": [vp, ctypes.c_int, u64, i32, vp, vp, vp, u64, vp],
+        "tqc_marginal_workspace_bytes": [i32, i32, ctypes.POINTER(u64)],
+        "tqc_marginal_ws": [vp, ctypes.c_int, i32, i32, _i32p, vp, vp, u64, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -282,12 +294,29 @@ class Network:
             self.handle = None
 
 
+def _device_bytes(nbytes, device=None):
+    """A 256-byte aligned device buffer of at least nbytes from torch's
+    allocator (its blocks are 512-byte aligned)."""
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
 class Plan:
-    """Contraction plan: order, slicing, GEMM mapping (host-only until executed)."""
+    """Contraction plan: order, slicing, GEMM mapping (host-only until executed).
+
+    workspace="torch" (default): before the first execution the plan binds
+    one torch-allocated device region holding every buffer it uses
+    (tqc_plan_set_workspace), so the library allocates no device memory for
+    it; workspace="library": the library allocates on first use."""
 
     def __init__(self, net, precision="fp32", out_dtype="f32", mem_budget=0, fixed=None,
                  order=None, sliced=None, cost="flopbyte", cost_model=None, num_candidates=0,
-                 seed=0, tile_policy=0):
+                 seed=0, tile_policy=0, workspace="torch", num_measured=0, max_rel_error=0.0):
+        if workspace not in ("torch", "library"):
+            raise ValueError("workspace must be 'torch' or 'library'")
+        self.workspace = workspace
+        self._ws = None
         L = lib()
         o = PlanOptions()
         L.tqc_plan_options_default(ctypes.byref(o))
@@ -318,16 +347,71 @@ class Plan:
         o.num_candidates = int(num_candidates)
         o.seed = int(seed)
         o.tile_policy = int(tile_policy)
+        o.num_measured = int(num_measured)
+        o.max_rel_error = float(max_rel_error)
         h = ctypes.c_void_p()
         _check(L.tqc_plan_create(net.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._adopt(h, net, out_dtype)
+
+    def _adopt(self, h, net, out_dtype):
+        L = lib()
         self.handle = h
         self.net = net  # keep the network alive
-        self.out_dtype = out_dtype
         st = PlanStats()
         _check(L.tqc_plan_get_stats(h, ctypes.byref(st)))
         self.stats = {f: getattr(st, f) for f, _ in PlanStats._fields_}
+        self.out_dtype = "f64" if st.out_dtype == DTYPES["f64"] else "f32"
+        assert out_dtype is None or out_dtype == self.out_dtype
         self.out_qubits = st.out_qubits
         self.out_entries = st.out_entries
+
+    def serialize(self):
+        """The plan's decisions and its network's structure as bytes
+        (tqc_plan_serialize)."""
+        n = ctypes.c_uint64(0)
+        _check(lib().tqc_plan_serialize(self.handle, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().tqc_plan_serialize(self.handle, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(n)))
+        return bytes(buf.raw[:n.value])
+
+    @classmethod
+    def deserialize(cls, net, blob, workspace="torch"):
+        """Rebuild a serialized plan on a network of the same structure."""
+        blob = bytes(blob)
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        h = ctypes.c_void_p()
+        _check(lib().tqc_plan_deserialize(net.handle, ctypes.cast(buf, ctypes.c_void_p), len(blob),
+                                          ctypes.byref(h)))
+        p = cls.__new__(cls)
+        p.workspace = workspace
+        p._ws = None
+        p._adopt(h, net, None)
+        return p
+
+    @property
+    def workspace_bytes(self):
+        n = ctypes.c_uint64(0)
+        _check(lib().tqc_plan_workspace_bytes(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self, buf=None, stream=None):
+        """Bind a caller-owned device region (a torch tensor; allocated here
+        when None) as the plan's workspace.  Called before the first execution
+        of a plan made with workspace="torch"."""
+        if buf is None:
+            buf = _device_bytes(self.workspace_bytes)
+        _check(lib().tqc_plan_set_workspace(self.handle, ctypes.c_void_p(buf.data_ptr()),
+                                            buf.numel() * buf.element_size(), _stream_ptr(stream)))
+        self._ws = buf
+        return buf
+
+    def _ready(self, stream=None):
+        if self.workspace == "torch" and self._ws is None:
+            self.bind_workspace(stream=stream)
+        if self._ws is not None and stream is not None:
+            # the region is used on this stream: torch must not hand it out
+            # again before that stream's work is done
+            self._ws.record_stream(_torch_stream(stream))
 
     @property
     def steps(self):
@@ -352,6 +436,7 @@ class Plan:
     def execute(self, out=None, stream=None):
         if out is None:
             out = self.output_tensor()
+        self._ready(stream)
         _check(lib().tqc_execute(self.handle, ctypes.c_void_p(out.data_ptr()),
                                  out.numel() * out.element_size(), _stream_ptr(stream)))
         return out
@@ -360,6 +445,7 @@ class Plan:
         """Execute and return (out, phase_ms): [transform, pack, step 0.., finalize]."""
         if out is None:
             out = self.output_tensor()
+        self._ready(stream)
         n = 3 + self.stats["num_steps"]
         ms = (ctypes.c_double * n)()
         _check(lib().tqc_execute_profiled(self.handle, ctypes.c_void_p(out.data_ptr()),
@@ -374,6 +460,7 @@ class Plan:
         if out is None:
             out = self.output_tensor()
         dev = out.device
+        self._ready(stream)
         idx = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
         val = torch.empty(max(k, 1), dtype=torch.float64, device=dev)
         tot = torch.empty(1, dtype=torch.float64, device=dev)
@@ -389,6 +476,7 @@ class Plan:
 
     def execute_slices(self, out, begin, end, accumulate=True, stream=None):
         assert out.dtype == torch.float64
+        self._ready(stream)
         _check(lib().tqc_execute_slices(self.handle, ctypes.c_void_p(out.data_ptr()),
                                         out.numel() * 8, int(begin), int(end), int(bool(accumulate)),
                                         _stream_ptr(stream)))
@@ -409,26 +497,53 @@ def _dtype_code(t):
     raise TypeError("probabilities must be float32 or float64")
 
 
-def topk(probs, k, stream=None):
-    """k largest entries (value desc, index asc): (int64 indices, float64 values) on device."""
+def topk(probs, k, stream=None, workspace="torch"):
+    """k largest entries (value desc, index asc): (int64 indices, float64
+    values) on device.  workspace="torch" passes a torch-allocated scratch
+    (tqc_topk_ws); "library" uses the library's per-stream scratch (tqc_topk)."""
     idx = torch.empty(k, dtype=torch.int64, device=probs.device)
     val = torch.empty(k, dtype=torch.float64, device=probs.device)
-    _check(lib().tqc_topk(ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), probs.numel(), int(k),
-                          ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
-                          _stream_ptr(stream)))
+    L = lib()
+    args = (ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), probs.numel(), int(k),
+            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()))
+    if workspace == "library":
+        _check(L.tqc_topk(*args, _stream_ptr(stream)))
+    else:
+        n = ctypes.c_uint64(0)
+        _check(L.tqc_topk_workspace_bytes(probs.numel(), int(k), ctypes.byref(n)))
+        ws = _device_bytes(n.value, probs.device)
+        _check(L.tqc_topk_ws(*args, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+        ws.record_stream(_torch_stream(stream))
     return idx, val
 
 
-def marginal(probs, num_qubits, keep, stream=None):
-    """float64 marginal over the kept qubits (bit i of the result index = keep[i])."""
+def marginal(probs, num_qubits, keep, stream=None, workspace="torch"):
+    """float64 marginal over the kept qubits (bit i of the result index =
+    keep[i]); workspace as for topk."""
     if probs.numel() != (1 << int(num_qubits)):
         raise ValueError("probs must hold 2^num_qubits entries")
     out = torch.empty(1 << len(keep), dtype=torch.float64, device=probs.device)
     k = _i32arr(keep)
-    _check(lib().tqc_marginal(ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), int(num_qubits),
-                              len(keep), ctypes.cast(k, _i32p), ctypes.c_void_p(out.data_ptr()),
-                              _stream_ptr(stream)))
+    L = lib()
+    args = (ctypes.c_void_p(probs.data_ptr()), _dtype_code(probs), int(num_qubits), len(keep),
+            ctypes.cast(k, _i32p), ctypes.c_void_p(out.data_ptr()))
+    if workspace == "library":
+        _check(L.tqc_marginal(*args, _stream_ptr(stream)))
+    else:
+        n = ctypes.c_uint64(0)
+        _check(L.tqc_marginal_workspace_bytes(int(num_qubits), len(keep), ctypes.byref(n)))
+        ws = _device_bytes(n.value, probs.device)
+        _check(L.tqc_marginal_ws(*args, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+        ws.record_stream(_torch_stream(stream))
     return out
+
+
+def _torch_stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(stream))
 
 
 class Batch:
@@ -441,6 +556,8 @@ class Batch:
             outs = [p.output_tensor() for p in plans]
         self.plans = list(plans)
         self.outs = list(outs)
+        for p in self.plans:
+            p._ready(stream)
         n = len(self.plans)
         ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
@@ -499,6 +616,8 @@ class Multi:
         self.plans = list(plans)
         self.outs = list(outs)
         self.timed = bool(timed)
+        for p in self.plans:
+            p._ready(stream)
         n = len(self.plans)
         ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
@@ -546,6 +665,7 @@ def autotune(plan, out=None, reps=3, stream=None):
     """Measure every tile shape per step; keep the fastest (also in the process table)."""
     if out is None:
         out = plan.output_tensor()
+    plan._ready(stream)
     _check(lib().tqc_plan_autotune(plan.handle, ctypes.c_void_p(out.data_ptr()),
                                    out.numel() * out.element_size(), int(reps), _stream_ptr(stream)))
     return [s["tile"] for s in plan.steps]

@@ -75,6 +75,7 @@ Network::~Network() {
 }
 
 Plan::~Plan() {
+  if (ws_external) return;  // the caller's memory
   if (ws) (void)hipFree(ws);
   if (acc64) (void)hipFree(acc64);
   if (scale_buf) (void)hipFree(scale_buf);
@@ -184,8 +185,51 @@ static void check_device(int want) {
 // --------------------------------------------------------------- execute
 static TransformArgs make_transform_args(const TensorIn &t, double *out);
 
-static void *get_scratch(uint64_t bytes, hipStream_t s);
-static std::mutex &scratch_mutex();
+// ---------------------------------------------------------- scratch
+// Library-owned scratch of the calls that take no workspace argument
+// (tqc_topk, tqc_marginal, tqc_network_pauli_tensor, heavy state selection,
+// the standalone scans of a summary without a bound workspace): one buffer
+// per (device, stream).  Work on one stream runs in order, so calls on that
+// stream may reuse its buffer; calls on different streams never share one.
+// The lease holds the buffer's lock while the call enqueues its kernels, so
+// two host threads enqueuing on one stream do not interleave on it.  A
+// buffer grows by synchronizing its stream and reallocating.
+struct StreamScratch {
+  std::mutex mu;
+  void *ptr = nullptr;
+  uint64_t bytes = 0;
+};
+struct ScratchLease {
+  std::unique_lock<std::mutex> lock;
+  void *ptr = nullptr;
+};
+static std::mutex g_scratch_map_mu;
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<StreamScratch>> g_scratch_map;
+
+static ScratchLease stream_scratch(uint64_t bytes, hipStream_t s) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  StreamScratch *e = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_map_mu);
+    auto &slot = g_scratch_map[{dev, s}];
+    if (!slot) slot.reset(new StreamScratch());
+    e = slot.get();
+  }
+  ScratchLease l{std::unique_lock<std::mutex>(e->mu), nullptr};
+  if (e->bytes < bytes) {
+    if (e->ptr) {
+      HIP_OK(hipStreamSynchronize(s));
+      HIP_OK(hipFree(e->ptr));
+      e->ptr = nullptr;
+      e->bytes = 0;
+    }
+    HIP_OK(hipMalloc(&e->ptr, bytes ? bytes : 256));
+    e->bytes = bytes;
+  }
+  l.ptr = e->ptr;
+  return l;
+}
 
 // Separable transform of a raw tensor with at least kPassMinCuts cuts: each
 // pass reads the previous layout and writes the next, alternating between
@@ -216,8 +260,8 @@ static void launch_levels(const std::vector<std::vector<TransformPassArgs>> &lev
 static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
   if ((int)t.cuts.size() >= kPassMinCuts) {
     const uint64_t b = (transform_schedule(t).max_intermediate * 8 + 255) & ~uint64_t(255);
-    std::lock_guard<std::mutex> lk(scratch_mutex());
-    char *sp = (char *)get_scratch(2 * b, s);
+    ScratchLease lease = stream_scratch(2 * b, s);
+    char *sp = (char *)lease.ptr;
     std::vector<std::vector<TransformPassArgs>> levels;
     schedule_passes(t, out, (double *)sp, (double *)(sp + b), b, levels);
     launch_levels(levels, s);
@@ -585,7 +629,10 @@ static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timin
   if (p->out_dtype == TQC_F64) {
     run_slices(p, out, OUT_F64_ACC, 0, p->num_slices, false, s, tm);
   } else {
-    if (!p->acc64) HIP_OK(hipMalloc((void **)&p->acc64, entries * 8));
+    if (!p->acc64) {
+      if (p->ws_external) fail(TQC_ERR_SHAPE, "bound workspace has no float64 accumulator");
+      HIP_OK(hipMalloc((void **)&p->acc64, entries * 8));
+    }
     run_slices(p, p->acc64, OUT_F64_ACC, 0, p->num_slices, false, s, tm);
     if (tm) tm->begin(2 + (int)p->steps.size());
     HIP_OK(launch_f64_to_f32(p->acc64, (float *)out, entries, s));
@@ -599,8 +646,15 @@ static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timin
 // extra pass over the 2^n output); otherwise the standalone scans run after
 // the contraction.  Top-k results are identical either way; the totals differ
 // only in float64 summation order.
-static void *get_scratch(uint64_t bytes, hipStream_t s);
-static std::mutex &scratch_mutex();
+// per-tile statistics of the root step (largest key and float64 sum, 16 B
+// per tile) followed by the 256 float64 partial sums of their total
+static uint64_t tile_stats_bytes(uint64_t ntiles) { return ((ntiles * 16 + 255) & ~uint64_t(255)) + 256 * 8; }
+
+static const Step *root_step(const Plan *p) {
+  for (const Step &st : p->steps)
+    if (st.root) return &st;
+  return nullptr;
+}
 
 static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint64_t *idx_out,
                             double *val_out, double *total, hipStream_t s, Timing *tm) {
@@ -614,10 +668,17 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
     if (st.root) root = &st;
   if (p->num_slices != 1 || p->net->m < 2 || !root) {
     execute(p, out, out_bytes, s, tm);
-    std::lock_guard<std::mutex> lk(scratch_mutex());
     const uint64_t sb = std::max(marginal_scratch_bytes(p->out_bits, 0),
                                  k > 0 ? topk_scratch_bytes(entries, k) : 0);
-    void *sp = get_scratch(sb, s);
+    ScratchLease lease;
+    void *sp = p->scan_buf;
+    if (!p->ws_external) {
+      lease = stream_scratch(sb, s);
+      sp = lease.ptr;
+    } else if (p->scan_bytes < sb) {
+      fail(TQC_ERR_SHAPE, "bound workspace has %llu scan bytes, needs %llu",
+           (unsigned long long)p->scan_bytes, (unsigned long long)sb);
+    }
     if (tm) tm->begin(fin_phase);
     HIP_OK(launch_marginal(out, dtype, p->out_bits, 0, nullptr, total, sp, sb, s));
     if (k > 0) HIP_OK(launch_topk(out, dtype, entries, k, idx_out, val_out, sp, sb, s));
@@ -633,9 +694,11 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
   const int lb = __builtin_ctz(bm);
   const uint64_t tilesM = ((1ull << root->lm) + bm - 1) / bm, tilesN = ((1ull << root->ln) + bm - 1) / bm;
   const uint64_t ntiles = tilesM * tilesN;
-  const uint64_t tbytes = ((ntiles * 16 + 255) & ~uint64_t(255)) + 256 * 8;
+  const uint64_t tbytes = tile_stats_bytes(ntiles);
   const uint64_t sbytes = tbytes + topk_tiles_scratch_bytes(entries, ntiles, std::max(k, 1));
   if (p->stats_bytes < sbytes) {
+    if (p->ws_external) fail(TQC_ERR_SHAPE, "bound workspace holds %llu statistics bytes, needs %llu",
+                             (unsigned long long)p->stats_bytes, (unsigned long long)sbytes);
     if (p->stats_buf) {
       HIP_OK(hipStreamSynchronize(s));
       HIP_OK(hipFree(p->stats_buf));
@@ -658,32 +721,90 @@ static void execute_summary(Plan *p, void *out, uint64_t out_bytes, int k, uint6
   if (tm) tm->end();
 }
 
-// ----------------------------------------------------------- scratch
-struct Scratch {
-  std::mutex mu;
-  void *ptr = nullptr;
-  uint64_t bytes = 0;
-  int device = -1;
+// ------------------------------------------------- caller-owned workspace
+// One region holds every device buffer a plan uses, each 256-byte aligned:
+//   [0, ws_bytes)  float64 Pauli tensors of raw inputs, transform ping-pong
+//                  buffers, split-k partials, packed operands and
+//                  intermediates, float16 planes (the planner's layout)
+//   scale          per-leaf abs-max bits, exponents, output scales
+//   acc            float64 accumulator of a sliced plan with float32 output
+//   stats          single-slice plans of two or more tensors: the root's
+//                  tile statistics plus the top-k gather scratch, sized for
+//                  the smallest tile (32 x 32, so autotuning cannot outgrow
+//                  it) and k = 4096
+//   scan           other plans: the standalone top-k and total scans
+struct PlanLayout {
+  uint64_t scale_off = 0, acc_off = 0, acc_bytes = 0, stats_off = 0, stats_bytes = 0;
+  uint64_t scan_off = 0, scan_bytes = 0, total = 0;
 };
-static Scratch g_scratch;
-static std::mutex &scratch_mutex() { return g_scratch.mu; }
 
-static void *get_scratch(uint64_t bytes, hipStream_t s) {
-  int dev = 0;
-  HIP_OK(hipGetDevice(&dev));
-  if (g_scratch.ptr && (g_scratch.bytes < bytes || g_scratch.device != dev)) {
-    HIP_OK(hipStreamSynchronize(s));
-    HIP_OK(hipFree(g_scratch.ptr));
-    g_scratch.ptr = nullptr;
+static PlanLayout plan_layout(const Plan *p) {
+  auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  const uint64_t entries = 1ull << p->out_bits;
+  const int m = p->net->m;
+  PlanLayout L;
+  uint64_t off = al(p->ws_bytes);
+  L.scale_off = off;
+  off = al(off + 256 + (uint64_t)m * 16);
+  if (p->num_slices > 1 && p->out_dtype == TQC_F32) {
+    L.acc_off = off;
+    L.acc_bytes = entries * 8;
+    off = al(off + L.acc_bytes);
   }
-  if (!g_scratch.ptr) {
-    HIP_OK(hipMalloc(&g_scratch.ptr, bytes));
-    g_scratch.bytes = bytes;
-    g_scratch.device = dev;
+  const Step *root = root_step(p);
+  if (p->num_slices == 1 && m >= 2 && root) {
+    const uint64_t ntiles = (((1ull << root->lm) + 31) / 32) * (((1ull << root->ln) + 31) / 32);
+    L.stats_off = off;
+    L.stats_bytes = al(tile_stats_bytes(ntiles) + topk_tiles_scratch_bytes(entries, ntiles, 4096));
+    off += L.stats_bytes;
+  } else {
+    L.scan_off = off;
+    L.scan_bytes = al(std::max(marginal_scratch_bytes(p->out_bits, 0), topk_scratch_bytes(entries, 4096)));
+    off += L.scan_bytes;
   }
-  return g_scratch.ptr;
+  L.total = off;
+  return L;
 }
 
+// Point every device buffer of the plan into the caller's region (or, with
+// ws = NULL, return to library-owned buffers allocated on first use).
+// Library-owned buffers held so far are released first; hipFree waits for
+// the device.  The region is cleared by a fill kernel on the stream: operand
+// padding beyond K is never written and must read as zero.
+static void bind_workspace(Plan *p, void *ws, uint64_t bytes, hipStream_t s) {
+  if (!p->ws_external) {
+    if (p->ws) HIP_OK(hipFree(p->ws));
+    if (p->acc64) HIP_OK(hipFree(p->acc64));
+    if (p->scale_buf) HIP_OK(hipFree(p->scale_buf));
+    if (p->stats_buf) HIP_OK(hipFree(p->stats_buf));
+  }
+  p->ws = nullptr;
+  p->acc64 = nullptr;
+  p->scale_buf = nullptr;
+  p->stats_buf = nullptr;
+  p->stats_bytes = 0;
+  p->scan_buf = nullptr;
+  p->scan_bytes = 0;
+  p->ws_external = false;
+  if (!ws) return;
+  const PlanLayout L = plan_layout(p);
+  if ((uintptr_t)ws & 255) fail(TQC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < L.total)
+    fail(TQC_ERR_SHAPE, "workspace holds %llu bytes, the plan needs %llu", (unsigned long long)bytes,
+         (unsigned long long)L.total);
+  upload(p->net);
+  check_device(p->net->device);
+  char *b = (char *)ws;
+  p->ws = b;
+  p->scale_buf = b + L.scale_off;
+  p->acc64 = L.acc_bytes ? (double *)(b + L.acc_off) : nullptr;
+  p->stats_buf = L.stats_bytes ? b + L.stats_off : nullptr;
+  p->stats_bytes = L.stats_bytes;
+  p->scan_buf = L.scan_bytes ? b + L.scan_off : nullptr;
+  p->scan_bytes = L.scan_bytes;
+  p->ws_external = true;
+  HIP_OK(launch_zero_u64((unsigned long long *)b, L.total / 8, s));
+}
 
 // ------------------------------------------------------------------ batch
 struct Batch {
@@ -1586,12 +1707,334 @@ static std::vector<int> mlp_choose_order(Network *net, Prec prec, tqc_dtype out,
   return orders[best];
 }
 
+// ---------------------------------------------- measured time as the judge
+// The learned model (or, without one, the roofline model) only shortlists:
+// the roofline planner's plan and the `count` best-ranked other orders are
+// each run on the device at full size, their median time over `reps` runs
+// is measured with HIP events, and every form other than float64 is checked
+// against a float64 run of the roofline plan (max |P - P_ref| / max |P_ref|
+// over every output entry).  The fastest plan within the error bound wins;
+// the roofline plan is the fallback when no other candidate passes.
+struct Measured {
+  double seconds = 0, rel_err = -1;
+};
+
+static void finish_tiles(Plan *p, int tile_policy) {
+  for (Step &st : p->steps) st.tile = pick_tile(p, st);
+  if (tile_policy == 1) apply_tuned_tiles(p);
+}
+
+static std::vector<int> order_of(const Plan *p) {
+  std::vector<int> o;
+  for (const Step &st : p->steps) {
+    o.push_back(st.a);
+    o.push_back(st.b);
+  }
+  return o;
+}
+
+static Measured measure_plan(Plan *p, void *out, const double *ref, unsigned long long *errbits, int reps,
+                             hipStream_t s) {
+  const uint64_t entries = 1ull << p->out_bits;
+  const uint64_t bytes = entries * (p->out_dtype == TQC_F64 ? 8 : 4);
+  execute(p, out, bytes, s);  // warm-up: workspace, transform, caches
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+  for (int r = 0; r < reps; ++r) {
+    HIP_OK(hipEventRecord(ev[2 * r], s));
+    execute(p, out, bytes, s);
+    HIP_OK(hipEventRecord(ev[2 * r + 1], s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<double> ms(reps);
+  for (int r = 0; r < reps; ++r) {
+    float t = 0;
+    HIP_OK(hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]));
+    ms[r] = t;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  std::sort(ms.begin(), ms.end());
+  Measured m;
+  m.seconds = ms[reps / 2] * 1e-3;
+  if (ref) {
+    HIP_OK(launch_zero_u64(errbits, 2, s));
+    HIP_OK(launch_max_abs_diff(out, p->out_dtype == TQC_F32 ? 1 : 0, ref, entries, errbits, s));
+    unsigned long long h[2];
+    HIP_OK(hipMemcpyAsync(h, errbits, 16, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double d, r;
+    std::memcpy(&d, &h[0], 8);
+    std::memcpy(&r, &h[1], 8);
+    m.rel_err = r > 0 ? d / r : d;
+  }
+  return m;
+}
+
+static Plan *plan_measured(Network *net, const tqc_plan_options &opt) {
+  auto t0 = std::chrono::steady_clock::now();
+  CostModel *model = reinterpret_cast<CostModel *>(opt.cost_model);
+  const int count = opt.num_measured > 0 ? opt.num_measured : 4;
+  const int reps = 5;
+  const double tol = opt.max_rel_error > 0 ? opt.max_rel_error : 1e-6;
+  tqc_plan_options o1 = opt;
+  o1.cost_kind = TQC_COST_FLOPBYTE;
+  o1.cost_model = nullptr;
+  std::unique_ptr<Plan> best(build_plan(net, o1));
+  finish_tiles(best.get(), opt.tile_policy);
+  const std::vector<int> p0_order = order_of(best.get());
+  // shortlist: the best-ranked sampled orders other than the roofline one
+  std::vector<std::vector<int>> shortlist;
+  if (net->m >= 3) {
+    auto orders = sample_orders(net, best->prec, best->out_dtype, best->sliced, best->fixed_q,
+                                opt.num_candidates > 0 ? opt.num_candidates : 1000, opt.seed);
+    std::vector<double> score(orders.size(), 0.0);
+    if (model) {
+      const uint64_t slices = 1ull << (2 * best->sliced.size());
+      std::vector<float> F;
+      std::vector<double> mult;
+      std::vector<size_t> row0(orders.size() + 1, 0);
+      for (size_t c = 0; c < orders.size(); ++c) {
+        for (auto &x : order_shapes(net, best->prec, best->sliced, best->fixed_q, orders[c])) {
+          float f[kFeat];
+          shape_features(x, best->prec, best->out_dtype, slices, f);
+          F.insert(F.end(), f, f + kFeat);
+          mult.push_back(x.slice_dep ? double(slices) : 1.0);
+        }
+        row0[c + 1] = mult.size();
+      }
+      std::vector<double> sec(mult.size());
+      if (!mult.empty()) costmodel_predict(model, F.data(), (int64_t)mult.size(), sec.data(), nullptr);
+      for (size_t c = 0; c < orders.size(); ++c)
+        for (size_t r = row0[c]; r < row0[c + 1]; ++r) score[c] += sec[r] * mult[r];
+    } else {
+      for (size_t c = 0; c < orders.size(); ++c) {
+        tqc_plan_options oc = o1;
+        oc.num_order_steps = (int32_t)orders[c].size() / 2;
+        oc.order = orders[c].data();
+        oc.num_sliced = (int32_t)best->sliced.size();
+        oc.sliced_cuts = best->sliced.data();
+        oc.mem_budget_bytes = 0;
+        std::unique_ptr<Plan> pc(build_plan(net, oc));
+        score[c] = pc->stats.predicted_seconds;
+      }
+    }
+    std::vector<size_t> idx(orders.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return score[a] < score[b]; });
+    for (size_t i : idx) {
+      if ((int)shortlist.size() >= count) break;
+      if (orders[i] == p0_order) continue;
+      if (std::find(shortlist.begin(), shortlist.end(), orders[i]) != shortlist.end()) continue;
+      shortlist.push_back(orders[i]);
+    }
+  }
+  // device measurement on a private stream
+  upload(net);
+  check_device(net->device);
+  hipStream_t s = nullptr;
+  HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct Cleanup {
+    std::vector<void *> bufs;
+    hipStream_t s;
+    ~Cleanup() {
+      if (s) (void)hipStreamSynchronize(s);
+      for (void *b : bufs) (void)hipFree(b);
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } cl{{}, s};
+  const uint64_t entries = 1ull << best->out_bits;
+  void *out = nullptr;
+  HIP_OK(hipMalloc(&out, entries * (best->out_dtype == TQC_F64 ? 8 : 4)));
+  cl.bufs.push_back(out);
+  unsigned long long *errbits = nullptr;
+  HIP_OK(hipMalloc((void **)&errbits, 16));
+  cl.bufs.push_back(errbits);
+  double *ref = nullptr;
+  if (best->prec != Prec::F64) {
+    tqc_plan_options orf = o1;
+    orf.precision = TQC_FP64;
+    orf.out_dtype = TQC_F64;
+    orf.num_order_steps = (int32_t)p0_order.size() / 2;
+    orf.order = p0_order.data();
+    orf.num_sliced = (int32_t)best->sliced.size();
+    orf.sliced_cuts = best->sliced.data();
+    orf.mem_budget_bytes = 0;
+    std::unique_ptr<Plan> pr(build_plan(net, orf));
+    finish_tiles(pr.get(), 0);
+    HIP_OK(hipMalloc((void **)&ref, entries * 8));
+    cl.bufs.push_back(ref);
+    execute(pr.get(), ref, entries * 8, s);
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  const Measured m0 = measure_plan(best.get(), out, ref, errbits, reps, s);
+  Measured bm = m0;
+  int measured = 1;
+  for (const auto &ord : shortlist) {
+    tqc_plan_options oc = o1;
+    oc.num_order_steps = (int32_t)ord.size() / 2;
+    oc.order = ord.data();
+    oc.num_sliced = (int32_t)best->sliced.size();
+    oc.sliced_cuts = best->sliced.data();
+    oc.mem_budget_bytes = 0;
+    std::unique_ptr<Plan> pc(build_plan(net, oc));
+    finish_tiles(pc.get(), opt.tile_policy);
+    if (opt.mem_budget_bytes && pc->stats.workspace_bytes > opt.mem_budget_bytes) continue;
+    const Measured mc = measure_plan(pc.get(), out, ref, errbits, reps, s);
+    ++measured;
+    const bool ok = mc.rel_err < 0 || mc.rel_err <= tol;
+    const bool best_ok = bm.rel_err < 0 || bm.rel_err <= tol;
+    if (ok && (!best_ok || mc.seconds < bm.seconds)) {
+      best = std::move(pc);
+      bm = mc;
+    }
+  }
+  best->stats.measured_seconds = bm.seconds;
+  best->stats.checked_rel_error = bm.rel_err;
+  best->stats.fallback_measured_seconds = m0.seconds;
+  best->stats.num_measured = measured;
+  best->stats.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return best.release();
+}
+
 }  // namespace tqc
 
 using namespace tqc;
 
 struct tqc_network_s : Network {};
 struct tqc_plan_s : Plan {};
+
+// ---------------------------------------------------------- plan blobs
+// A plan's decisions (Sec. III-E: the contraction order and the sliced cuts;
+// the fixed-qubit slice, the form and every step's tile) as a byte string,
+// together with the structure of the network it was made for (qubits, cut
+// ends, each tensor's basis, cut list and output qubits).  Tensor values are
+// not part of it: a plan depends only on the structure, so a stored plan
+// serves every network of that structure.  Little-endian; the last 8 bytes
+// are an FNV-1a hash of the rest.
+namespace {
+constexpr char kPlanMagic[8] = {'T', 'Q', 'C', 'P', 'L', 'A', 'N', '1'};
+
+struct BlobWriter {
+  std::vector<unsigned char> b;
+  void put(const void *p, size_t n) { b.insert(b.end(), (const unsigned char *)p, (const unsigned char *)p + n); }
+  void i32(int32_t v) { put(&v, 4); }
+  void u64(uint64_t v) { put(&v, 8); }
+  void f64(double v) { put(&v, 8); }
+};
+
+struct BlobReader {
+  const unsigned char *p;
+  size_t n, at = 0;
+  void get(void *dst, size_t k) {
+    if (k > n - at) fail(TQC_ERR_INVALID_ARG, "plan blob truncated at byte %zu", at);
+    std::memcpy(dst, p + at, k);
+    at += k;
+  }
+  int32_t i32() { int32_t v; get(&v, 4); return v; }
+  uint64_t u64() { uint64_t v; get(&v, 8); return v; }
+  double f64() { double v; get(&v, 8); return v; }
+};
+
+uint64_t fnv1a(const unsigned char *p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+void write_structure(BlobWriter &w, const Network &net) {
+  w.i32(net.n);
+  w.i32(net.m);
+  w.i32(net.K);
+  for (const tqc_cut &c : net.cuts) {
+    w.i32(c.upstream);
+    w.i32(c.downstream);
+  }
+  for (const TensorIn &t : net.t) {
+    w.i32((int32_t)t.basis);
+    w.i32((int32_t)t.cuts.size());
+    for (int c : t.cuts) w.i32(c);
+    w.i32((int32_t)t.outputs.size());
+    for (int q : t.outputs) w.i32(q);
+  }
+}
+
+std::vector<unsigned char> serialize_plan(const Plan &p) {
+  BlobWriter w;
+  w.put(kPlanMagic, 8);
+  write_structure(w, *p.net);
+  w.i32((int32_t)p.prec);
+  w.i32((int32_t)p.out_dtype);
+  w.i32(p.tile_policy);
+  w.i32((int32_t)p.fixed_q.size());
+  for (size_t i = 0; i < p.fixed_q.size(); ++i) {
+    w.i32(p.fixed_q[i]);
+    w.i32(p.fixed_v[i]);
+  }
+  w.i32((int32_t)p.sliced.size());
+  for (int c : p.sliced) w.i32(c);
+  w.i32((int32_t)p.steps.size());
+  for (const Step &st : p.steps) {
+    w.i32(st.a);
+    w.i32(st.b);
+    w.i32(st.tile);
+  }
+  w.f64(p.stats.predicted_seconds);
+  w.u64(fnv1a(w.b.data(), w.b.size()));
+  return w.b;
+}
+
+Plan *deserialize_plan(Network *net, const unsigned char *buf, size_t len) {
+  if (len < 16) fail(TQC_ERR_INVALID_ARG, "plan blob of %zu bytes", len);
+  uint64_t h;
+  std::memcpy(&h, buf + len - 8, 8);
+  if (h != fnv1a(buf, len - 8)) fail(TQC_ERR_INVALID_ARG, "plan blob checksum mismatch");
+  if (std::memcmp(buf, kPlanMagic, 8) != 0) fail(TQC_ERR_INVALID_ARG, "not a plan blob");
+  // the structure must match byte for byte
+  BlobWriter mine;
+  write_structure(mine, *net);
+  if (len - 16 < mine.b.size() || std::memcmp(buf + 8, mine.b.data(), mine.b.size()) != 0)
+    fail(TQC_ERR_TOPOLOGY, "the plan was made for a network of another structure");
+  BlobReader r{buf, len - 8, 8 + mine.b.size()};
+  tqc_plan_options o;
+  tqc_plan_options_default(&o);
+  o.precision = (tqc_precision)r.i32();
+  o.out_dtype = (tqc_dtype)r.i32();
+  o.tile_policy = r.i32();
+  const int nf = r.i32();
+  if (nf < 0 || nf > net->n) fail(TQC_ERR_INVALID_ARG, "plan blob: %d fixed qubits", nf);
+  std::vector<int32_t> fq(nf), fv(nf);
+  for (int i = 0; i < nf; ++i) {
+    fq[i] = r.i32();
+    fv[i] = r.i32();
+  }
+  const int ns = r.i32();
+  if (ns < 0 || ns > net->K) fail(TQC_ERR_INVALID_ARG, "plan blob: %d sliced cuts", ns);
+  std::vector<int32_t> sl(ns);
+  for (int i = 0; i < ns; ++i) sl[i] = r.i32();
+  const int nsteps = r.i32();
+  if (nsteps != std::max(0, net->m - 1)) fail(TQC_ERR_INVALID_ARG, "plan blob: %d steps for %d tensors", nsteps, net->m);
+  std::vector<int32_t> order(2 * nsteps), tiles(nsteps);
+  for (int i = 0; i < nsteps; ++i) {
+    order[2 * i] = r.i32();
+    order[2 * i + 1] = r.i32();
+    tiles[i] = r.i32();
+    if (tiles[i] < 0 || tiles[i] > 2) fail(TQC_ERR_INVALID_ARG, "plan blob: tile %d", tiles[i]);
+  }
+  const double predicted = r.f64();
+  if (r.at != r.n) fail(TQC_ERR_INVALID_ARG, "plan blob has %zu trailing bytes", r.n - r.at);
+  o.num_fixed = nf;
+  o.fixed_qubits = fq.data();
+  o.fixed_values = fv.data();
+  o.num_sliced = ns;
+  o.sliced_cuts = sl.data();
+  o.num_order_steps = nsteps;
+  o.order = order.data();
+  std::unique_ptr<Plan> p(build_plan(net, o));
+  for (int i = 0; i < nsteps; ++i) p->steps[i].tile = tiles[i];
+  p->stats.predicted_seconds = predicted;
+  return p.release();
+}
+}  // namespace
 
 extern "C" {
 
@@ -1628,6 +2071,11 @@ tqc_status tqc_plan_create(tqc_network_t net, const tqc_plan_options *opt, tqc_p
     if (!net || !opt || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
     Plan *p = nullptr;
+    if (opt->cost_kind == TQC_COST_MEASURED && opt->num_order_steps <= 0) {
+      p = plan_measured(reinterpret_cast<Network *>(net), *opt);
+      *out = reinterpret_cast<tqc_plan_t>(p);
+      return;
+    }
     if (opt->cost_kind == TQC_COST_MLP && opt->num_order_steps <= 0) {
       if (!opt->cost_model) fail(TQC_ERR_INVALID_ARG, "TQC_COST_MLP needs a cost model");
       auto t0 = std::chrono::steady_clock::now();
@@ -1668,7 +2116,10 @@ void tqc_plan_destroy(tqc_plan_t plan) { delete reinterpret_cast<Plan *>(plan); 
 tqc_status tqc_plan_get_stats(tqc_plan_t plan, tqc_plan_stats *st) {
   return guarded([&] {
     if (!plan || !st) fail(TQC_ERR_INVALID_ARG, "null argument");
-    *st = reinterpret_cast<Plan *>(plan)->stats;
+    const Plan *p = reinterpret_cast<Plan *>(plan);
+    *st = p->stats;
+    st->precision = (int32_t)p->prec;
+    st->out_dtype = (int32_t)p->out_dtype;
   });
 }
 
@@ -1780,17 +2231,57 @@ tqc_status tqc_network_pauli_tensor(tqc_network_t netp, int32_t j, double *out, 
   });
 }
 
+static void check_topk_args(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k, const uint64_t *idx_out,
+                            const double *val_out) {
+  if (!probs || !idx_out || !val_out) fail(TQC_ERR_INVALID_ARG, "null argument");
+  if (dtype != TQC_F32 && dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "dtype");
+  if (k < 1 || k > 4096 || (uint64_t)k > len)
+    fail(TQC_ERR_INVALID_ARG, "k = %d for length %llu", k, (unsigned long long)len);
+}
+
+static void check_marginal_args(const void *probs, tqc_dtype dtype, int32_t num_qubits, int32_t num_keep,
+                                const int32_t *keep, const double *out) {
+  if (!probs || !out || (num_keep > 0 && !keep)) fail(TQC_ERR_INVALID_ARG, "null argument");
+  if (dtype != TQC_F32 && dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "dtype");
+  if (num_qubits < 0 || num_qubits > 40) fail(TQC_ERR_INVALID_ARG, "num_qubits %d", num_qubits);
+  if (num_keep < 0 || num_keep > 24 || num_keep > num_qubits) fail(TQC_ERR_INVALID_ARG, "num_keep %d", num_keep);
+  for (int i = 0; i < num_keep; ++i) {
+    if (keep[i] < 0 || keep[i] >= num_qubits) fail(TQC_ERR_INVALID_ARG, "keep qubit %d", keep[i]);
+    for (int j = 0; j < i; ++j)
+      if (keep[j] == keep[i]) fail(TQC_ERR_INVALID_ARG, "keep qubit %d twice", keep[i]);
+  }
+}
+
 tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k, uint64_t *idx_out,
                     double *val_out, void *stream) {
   return guarded([&] {
-    if (!probs || !idx_out || !val_out) fail(TQC_ERR_INVALID_ARG, "null argument");
-    if (dtype != TQC_F32 && dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "dtype");
-    if (k < 1 || k > 4096 || (uint64_t)k > len) fail(TQC_ERR_INVALID_ARG, "k = %d for length %llu", k,
-                                                     (unsigned long long)len);
-    std::lock_guard<std::mutex> lk(g_scratch.mu);
+    check_topk_args(probs, dtype, len, k, idx_out, val_out);
     const uint64_t sb = topk_scratch_bytes(len, k);
-    void *sp = get_scratch(sb, (hipStream_t)stream);
-    HIP_OK(launch_topk(probs, dtype == TQC_F32 ? 1 : 0, len, k, idx_out, val_out, sp, sb,
+    ScratchLease lease = stream_scratch(sb, (hipStream_t)stream);
+    HIP_OK(launch_topk(probs, dtype == TQC_F32 ? 1 : 0, len, k, idx_out, val_out, lease.ptr, sb,
+                       (hipStream_t)stream));
+  });
+}
+
+tqc_status tqc_topk_workspace_bytes(uint64_t len, int32_t k, uint64_t *bytes) {
+  return guarded([&] {
+    if (!bytes) fail(TQC_ERR_INVALID_ARG, "null argument");
+    if (k < 1 || k > 4096 || (uint64_t)k > len)
+      fail(TQC_ERR_INVALID_ARG, "k = %d for length %llu", k, (unsigned long long)len);
+    *bytes = topk_scratch_bytes(len, k);
+  });
+}
+
+tqc_status tqc_topk_ws(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k, uint64_t *idx_out,
+                       double *val_out, void *workspace, uint64_t ws_bytes, void *stream) {
+  return guarded([&] {
+    check_topk_args(probs, dtype, len, k, idx_out, val_out);
+    if (!workspace || ((uintptr_t)workspace & 255)) fail(TQC_ERR_INVALID_ARG, "workspace null or not 256-byte aligned");
+    const uint64_t sb = topk_scratch_bytes(len, k);
+    if (ws_bytes < sb)
+      fail(TQC_ERR_SHAPE, "workspace holds %llu bytes, needs %llu", (unsigned long long)ws_bytes,
+           (unsigned long long)sb);
+    HIP_OK(launch_topk(probs, dtype == TQC_F32 ? 1 : 0, len, k, idx_out, val_out, workspace, sb,
                        (hipStream_t)stream));
   });
 }
@@ -1798,21 +2289,70 @@ tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
 tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits, int32_t num_keep,
                         const int32_t *keep, double *out, void *stream) {
   return guarded([&] {
-    if (!probs || !out || (num_keep > 0 && !keep)) fail(TQC_ERR_INVALID_ARG, "null argument");
-    if (dtype != TQC_F32 && dtype != TQC_F64) fail(TQC_ERR_INVALID_ARG, "dtype");
-    if (num_qubits < 0 || num_qubits > 40) fail(TQC_ERR_INVALID_ARG, "num_qubits %d", num_qubits);
-    if (num_keep < 0 || num_keep > 24 || num_keep > num_qubits)
-      fail(TQC_ERR_INVALID_ARG, "num_keep %d", num_keep);
-    for (int i = 0; i < num_keep; ++i) {
-      if (keep[i] < 0 || keep[i] >= num_qubits) fail(TQC_ERR_INVALID_ARG, "keep qubit %d", keep[i]);
-      for (int j = 0; j < i; ++j)
-        if (keep[j] == keep[i]) fail(TQC_ERR_INVALID_ARG, "keep qubit %d twice", keep[i]);
-    }
-    std::lock_guard<std::mutex> lk(g_scratch.mu);
+    check_marginal_args(probs, dtype, num_qubits, num_keep, keep, out);
     const uint64_t sb = marginal_scratch_bytes(num_qubits, num_keep);
-    void *sp = get_scratch(sb, (hipStream_t)stream);
-    HIP_OK(launch_marginal(probs, dtype == TQC_F32 ? 1 : 0, num_qubits, num_keep, keep, out, sp, sb,
+    ScratchLease lease = stream_scratch(sb, (hipStream_t)stream);
+    HIP_OK(launch_marginal(probs, dtype == TQC_F32 ? 1 : 0, num_qubits, num_keep, keep, out, lease.ptr, sb,
                            (hipStream_t)stream));
+  });
+}
+
+tqc_status tqc_marginal_workspace_bytes(int32_t num_qubits, int32_t num_keep, uint64_t *bytes) {
+  return guarded([&] {
+    if (!bytes) fail(TQC_ERR_INVALID_ARG, "null argument");
+    if (num_qubits < 0 || num_qubits > 40 || num_keep < 0 || num_keep > 24 || num_keep > num_qubits)
+      fail(TQC_ERR_INVALID_ARG, "num_qubits %d, num_keep %d", num_qubits, num_keep);
+    *bytes = marginal_scratch_bytes(num_qubits, num_keep);
+  });
+}
+
+tqc_status tqc_marginal_ws(const void *probs, tqc_dtype dtype, int32_t num_qubits, int32_t num_keep,
+                           const int32_t *keep, double *out, void *workspace, uint64_t ws_bytes, void *stream) {
+  return guarded([&] {
+    check_marginal_args(probs, dtype, num_qubits, num_keep, keep, out);
+    if (!workspace || ((uintptr_t)workspace & 255)) fail(TQC_ERR_INVALID_ARG, "workspace null or not 256-byte aligned");
+    const uint64_t sb = marginal_scratch_bytes(num_qubits, num_keep);
+    if (ws_bytes < sb)
+      fail(TQC_ERR_SHAPE, "workspace holds %llu bytes, needs %llu", (unsigned long long)ws_bytes,
+           (unsigned long long)sb);
+    HIP_OK(launch_marginal(probs, dtype == TQC_F32 ? 1 : 0, num_qubits, num_keep, keep, out, workspace, sb,
+                           (hipStream_t)stream));
+  });
+}
+
+tqc_status tqc_plan_workspace_bytes(tqc_plan_t plan, uint64_t *bytes) {
+  return guarded([&] {
+    if (!plan || !bytes) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *bytes = plan_layout(reinterpret_cast<Plan *>(plan)).total;
+  });
+}
+
+tqc_status tqc_plan_set_workspace(tqc_plan_t plan, void *workspace, uint64_t ws_bytes, void *stream) {
+  return guarded([&] {
+    if (!plan) fail(TQC_ERR_INVALID_ARG, "null plan");
+    bind_workspace(reinterpret_cast<Plan *>(plan), workspace, ws_bytes, (hipStream_t)stream);
+  });
+}
+
+tqc_status tqc_plan_serialize(tqc_plan_t plan, void *buf, uint64_t *len) {
+  return guarded([&] {
+    if (!plan || !len) fail(TQC_ERR_INVALID_ARG, "null argument");
+    const std::vector<unsigned char> b = serialize_plan(*reinterpret_cast<Plan *>(plan));
+    if (buf) {
+      if (*len < b.size())
+        fail(TQC_ERR_SHAPE, "buffer holds %llu bytes, the plan needs %zu", (unsigned long long)*len, b.size());
+      std::memcpy(buf, b.data(), b.size());
+    }
+    *len = b.size();
+  });
+}
+
+tqc_status tqc_plan_deserialize(tqc_network_t net, const void *buf, uint64_t len, tqc_plan_t *out) {
+  return guarded([&] {
+    if (!net || !buf || !out) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    Plan *p = deserialize_plan(reinterpret_cast<Network *>(net), (const unsigned char *)buf, (size_t)len);
+    *out = reinterpret_cast<tqc_plan_t>(p);
   });
 }
 

@@ -106,6 +106,12 @@ struct Plan {
   void *scale_buf = nullptr;     // per-leaf |max| bits, exponents, output scale
   void *stats_buf = nullptr;     // per-tile statistics of the root step + top-k scratch
   uint64_t stats_bytes = 0;
+  // caller-owned workspace (tqc_plan_set_workspace): every device buffer
+  // above points into it, and scan_buf holds the standalone top-k / total
+  // scans of plans without tile statistics; nothing is allocated or freed
+  bool ws_external = false;
+  void *scan_buf = nullptr;
+  uint64_t scan_bytes = 0;
   ~Plan();
 };
 

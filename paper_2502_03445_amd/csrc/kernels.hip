@@ -539,6 +539,42 @@ hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Largest |a - ref| and largest |ref| over two vectors (a float32 or
+// float64, ref float64), as the bit patterns of non-negative doubles in
+// out[0] and out[1] (cleared by the caller).  The planner's error check of a
+// candidate plan against a float64 reference result.
+__global__ void __launch_bounds__(256) max_abs_diff_kernel(const void *a, int a_f32, const double *ref, uint64_t n,
+                                                           unsigned long long *out) {
+  __shared__ double rd[256], rr[256];
+  double d = 0.0, r = 0.0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const double x = a_f32 ? (double)((const float *)a)[i] : ((const double *)a)[i];
+    const double y = ref[i];
+    d = fmax(d, fabs(x - y));
+    r = fmax(r, fabs(y));
+  }
+  rd[threadIdx.x] = d;
+  rr[threadIdx.x] = r;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + w]);
+      rr[threadIdx.x] = fmax(rr[threadIdx.x], rr[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(rd[0]));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(rr[0]));
+  }
+}
+
+hipError_t launch_max_abs_diff(const void *a, int a_f32, const double *ref, uint64_t n, unsigned long long *out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(max_abs_diff_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, s, a, a_f32, ref, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s) {
   hipLaunchKernelGGL(scale_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, buf, n, sc);
   return hipGetLastError();

@@ -13,6 +13,9 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, uint64_t n, hipStream_t s);
 hipError_t launch_scale_f64(double *buf, uint64_t n, double sc, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *buf, uint64_t n, hipStream_t s);
+// out[0] = bits of max |a - ref|, out[1] = bits of max |ref| (out cleared first)
+hipError_t launch_max_abs_diff(const void *a, int a_f32, const double *ref, uint64_t n, unsigned long long *out,
+                               hipStream_t s);
 hipError_t launch_stamp(unsigned long long *dst, hipStream_t s);
 hipError_t launch_f16_split(const float *src0, uint64_t n0, uint16_t *hi0, uint16_t *lo0, const float *src1,
                             uint64_t n1, uint16_t *hi1, uint16_t *lo1, unsigned long long *maxbits,

@@ -117,3 +117,81 @@ def test_memory_budget_slicing():
     with pytest.raises(tqc.TqcError) as e:
         tqc.Plan(N, out_dtype="f64", mem_budget=64)
     assert e.value.status == 5
+
+
+# ----------------------------------------------------------- plan blobs
+def _plan_fields(P):
+    st = dict(P.stats)
+    st.pop("plan_seconds")
+    return st, P.steps, P.sliced
+
+
+@pytest.mark.parametrize("opts", [dict(precision="fp32"),
+                                  dict(precision="fp64", out_dtype="f64", sliced=[1, 4]),
+                                  dict(precision="bf16x6", fixed={0: 1, 5: 0, 9: 1}),
+                                  dict(precision="fp16x3", order=[(3, 1), (4, 0), (5, 2)])])
+def test_plan_blob_round_trip(opts):
+    spec = synthetic.random_network(4, 7, [3, 3, 2, 4], seed=91)
+    net = tqc.Network.from_spec(spec)
+    P = tqc.Plan(net, **opts)
+    blob = P.serialize()
+    assert blob[:8] == b"TQCPLAN1"
+    Q = tqc.Plan.deserialize(net, blob)
+    assert _plan_fields(Q) == _plan_fields(P)
+    assert Q.out_dtype == P.out_dtype
+    assert Q.serialize() == blob
+    # same structure, other values: the plan applies
+    spec2 = synthetic.random_network(4, 7, [3, 3, 2, 4], seed=91)
+    for t in spec2.tensors:
+        t.data[...] = t.data[::-1]
+    R = tqc.Plan.deserialize(tqc.Network.from_spec(spec2), blob)
+    assert R.steps == P.steps
+
+
+def test_plan_blob_budget_sliced_plan_keeps_slicing_order():
+    spec = synthetic.random_network(5, 14, [2, 2, 2, 2, 2], seed=9)
+    net = tqc.Network.from_spec(spec)
+    free = tqc.Plan(net, precision="fp64", out_dtype="f64")
+    P = tqc.Plan(net, precision="fp64", out_dtype="f64", mem_budget=free.stats["workspace_bytes"] // 3)
+    assert len(P.sliced) >= 1
+    Q = tqc.Plan.deserialize(net, P.serialize())
+    assert Q.sliced == P.sliced and Q.steps == P.steps
+
+
+def test_plan_blob_errors():
+    spec = synthetic.random_network(3, 4, [3, 3, 3], seed=5)
+    net = tqc.Network.from_spec(spec)
+    P = tqc.Plan(net)
+    blob = P.serialize()
+    L = tqc.lib()
+    # too small a buffer: SHAPE, and the size is reported
+    n = ctypes.c_uint64(len(blob) - 1)
+    buf = ctypes.create_string_buffer(len(blob))
+    assert L.tqc_plan_serialize(P.handle, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(n)) == 3
+    for bad in (blob[:-1], blob[:20], b"X" + blob[1:], blob[:40] + bytes([blob[40] ^ 1]) + blob[41:]):
+        with pytest.raises(tqc.TqcError) as e:
+            tqc.Plan.deserialize(net, bad)
+        assert e.value.status == 1
+    # another structure: TOPOLOGY
+    other = tqc.Network.from_spec(synthetic.random_network(3, 4, [3, 3, 3], seed=6))
+    with pytest.raises(tqc.TqcError) as e:
+        tqc.Plan.deserialize(other, blob)
+    assert e.value.status == 2
+
+
+def test_plan_workspace_query_covers_the_plan():
+    spec = synthetic.random_network(4, 7, [3, 3, 2, 4], seed=91)
+    net = tqc.Network.from_spec(spec)
+    for opts in (dict(), dict(precision="fp64", out_dtype="f64", sliced=[2]), dict(sliced=[0, 3])):
+        P = tqc.Plan(net, **opts)
+        need = P.workspace_bytes
+        assert need % 256 == 0
+        # at least the planner's workspace and, for a sliced float32 plan,
+        # the float64 accumulator of the slice sum (both in the stats figure)
+        assert need >= P.stats["workspace_bytes"]
+    L = tqc.lib()
+    n = ctypes.c_uint64(0)
+    assert L.tqc_topk_workspace_bytes(1 << 20, 100, ctypes.byref(n)) == 0 and n.value > 0
+    assert L.tqc_topk_workspace_bytes(10, 11, ctypes.byref(n)) == 1
+    assert L.tqc_marginal_workspace_bytes(20, 3, ctypes.byref(n)) == 0 and n.value > 0
+    assert L.tqc_marginal_workspace_bytes(20, 25, ctypes.byref(n)) == 1

@@ -91,3 +91,98 @@ def test_grid_patch_slice_matches_oracle(form, cost):
     # so the relative bound is asserted as well
     assert err <= 1e-12
     assert err <= (1e-11 if form == "fp64" else 1e-6) * np.abs(ref).max(), err / np.abs(ref).max()
+
+
+# ------------------------------------------- measured time as the judge
+def _grid(seed):
+    spec = synthetic.grid_patch_network(seed=seed)
+    fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
+    return spec, fixed, tqc.Network.from_spec(spec)
+
+
+def _train_on_grid_timings(seeds=(1, 2, 3), orders_per_seed=10):
+    """The MLP trained on per-step device times of the plain contractor on
+    random orders of other seeds of the 12-patch grid workload."""
+    rng = np.random.default_rng(7)
+    feats, secs = [], []
+    for seed in seeds:
+        spec, fixed, net = _grid(seed)
+        for _ in range(orders_per_seed):
+            order = synthetic.random_contraction_order(rng, spec, fixed)
+            plan = tqc.Plan(net, precision="fp32", fixed=fixed, order=order)
+            if plan.stats["workspace_bytes"] > (32 << 30):
+                continue
+            out = plan.output_tensor()
+            plan.execute_profiled(out)
+            _, ph = plan.execute_profiled(out)
+            for i, row in enumerate(tqc.step_features(plan)):
+                feats.append(row)
+                secs.append(max(ph[2 + i], 1e-4) * 1e-3)
+            del plan, out
+    m = tqc.CostModel(seed=11)
+    m.train(np.array(feats), np.array(secs), epochs=60, batch=64, lr=2e-3)
+    return m
+
+
+def _interleaved_ms(plans, reps=21):
+    outs = [p.output_tensor() for p in plans]
+    for p, o in zip(plans, outs):
+        p.execute(o)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+          for _ in plans]
+    for r in range(reps):
+        for i, (p, o) in enumerate(zip(plans, outs)):
+            ev[i][r][0].record()
+            p.execute(o)
+            ev[i][r][1].record()
+    torch.cuda.synchronize()
+    return [float(np.median([a.elapsed_time(b) for a, b in e])) for e in ev], outs
+
+
+def test_measured_judge_on_grid_slice_is_no_slower_and_within_tolerance():
+    """Sec. VIII-A: flops over peak misjudges GPU time, so the learned model
+    shortlists and measured time decides.  On the 12-patch grid slice (2^24
+    free entries, float32) the chosen plan runs no slower than the roofline
+    planner's plan and stays within 1e-6 * max|P| of the oracle."""
+    from oracle.reconstruct import entries_variable_elimination, restrict_fixed
+    model = _train_on_grid_timings()
+    spec, fixed, net = _grid(0)
+    dp = tqc.Plan(net, precision="fp32", fixed=fixed)
+    jm = tqc.Plan(net, precision="fp32", fixed=fixed, cost="measured", cost_model=model,
+                  num_candidates=2000, num_measured=4, seed=3)
+    st = jm.stats
+    assert st["num_measured"] >= 2
+    assert 0.0 <= st["checked_rel_error"] <= 1e-6
+    assert 0.0 < st["measured_seconds"] <= st["fallback_measured_seconds"]
+    (t_dp, t_jm), (o_dp, o_jm) = _interleaved_ms([dp, jm])
+    assert t_jm <= 1.05 * t_dp + 0.005, (t_jm, t_dp, jm.steps)
+    got = o_jm.double().cpu().numpy()
+    tens, nfree = restrict_fixed(spec, fixed)
+    ys = np.random.default_rng(17).choice(1 << nfree, 192, replace=False)
+    ys = np.unique(np.concatenate([ys, np.argsort(np.abs(got))[-16:]])).astype(np.uint64)
+    ref = entries_variable_elimination(spec, ys, tensors=tens)
+    assert np.abs(got[ys.astype(np.int64)] - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_measured_judge_rejects_candidates_above_the_bound():
+    """With an impossible bound no candidate is accepted, and the roofline
+    plan (the fallback) is returned unchanged."""
+    spec = synthetic.random_network(6, 9, [3, 3, 3, 3, 3, 3], seed=12)
+    net = tqc.Network.from_spec(spec)
+    dp = tqc.Plan(net, precision="bf16x3")
+    jm = tqc.Plan(net, precision="bf16x3", cost="measured", num_measured=3, max_rel_error=1e-30, seed=1)
+    assert jm.steps == dp.steps
+    assert jm.stats["checked_rel_error"] > 1e-30
+    assert jm.stats["measured_seconds"] == jm.stats["fallback_measured_seconds"]
+    ref = full_distribution(spec)
+    got = jm.execute().double().cpu().numpy()
+    assert np.abs(got - ref).max() <= 3e-5 * np.abs(ref).max()
+
+
+def test_measured_judge_float64_skips_the_error_check():
+    spec = synthetic.random_network(5, 7, [3, 3, 2, 3, 3], seed=44)
+    net = tqc.Network.from_spec(spec)
+    jm = tqc.Plan(net, precision="fp64", out_dtype="f64", cost="measured", num_measured=2, seed=2)
+    assert jm.stats["checked_rel_error"] == -1.0 and jm.stats["num_measured"] >= 1
+    ref = full_distribution(spec)
+    assert np.abs(jm.execute().cpu().numpy() - ref).max() <= 1e-12

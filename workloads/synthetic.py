@@ -151,3 +151,28 @@ def grid_patch_network(seed=None, rows=2, cols=6, patch_h=5, patch_w=2, num_cuts
     net.meta.update(name="grid10x12_12patch_40cut_2^24", fixed_qubits=fixed_q, fixed_values=fixed_v,
                     free_qubits=free)
     return net
+
+
+def random_contraction_order(rng, spec, fixed, temperature=2.0):
+    """A randomized greedy contraction order: among pairs of nodes sharing a
+    cut, pick the one whose result has the fewest index bits plus Gumbel noise
+    (node ids grow as in the plan API: the result of step s is node m + s)."""
+    m = len(spec.tensors)
+    cuts = {i: set(t.cut_ids) for i, t in enumerate(spec.tensors)}
+    outs = {i: sum(1 for q in t.outputs if q not in fixed) for i, t in enumerate(spec.tensors)}
+    order, nid = [], m
+    while len(cuts) > 1:
+        best, pick = None, None
+        for a in cuts:
+            for b in cuts:
+                if a < b and cuts[a] & cuts[b]:
+                    bits = 2 * len(cuts[a] ^ cuts[b]) + outs[a] + outs[b]
+                    score = bits + temperature * rng.gumbel()
+                    if best is None or score < best:
+                        best, pick = score, (a, b)
+        a, b = pick
+        order.append((a, b))
+        cuts[nid] = cuts.pop(a) ^ cuts.pop(b)
+        outs[nid] = outs.pop(a) + outs.pop(b)
+        nid += 1
+    return order
