@@ -107,26 +107,44 @@ def _median_ms(plan, out, reps=7):
     return float(np.median([sum(plan.execute_profiled(out)[1]) for _ in range(reps)]))
 
 
-def precision_study(tqc, torch):
+def precision_study(tqc, torch, forms=("fp32", "bf16x6", "bf16x3", "fp16x3")):
     """18-cut synthetic network, 34 qubits, 4 fixed (a 2^30 slice): device time
     and max error of every form against the float64 form over all 2^30
     entries (the float64 form itself is checked against the oracle in the GPU
-    tests)."""
+    tests); per step the median device time, and for the step with the most
+    flops its rate against the MFMA peak of the form's operand type (products
+    counted: bf16x3 and fp16x3 three, bf16x6 six)."""
     from workloads import synthetic
     spec = synthetic.precision_network()
     fixed = dict(zip(spec.meta["fixed_qubits"], spec.meta["fixed_values"]))
     net = tqc.Network.from_spec(spec)
     res, ref = {}, None
-    for form in ("fp64", "fp32", "bf16x6", "bf16x3", "fp16x3"):
+    for form in ("fp64",) + tuple(f for f in forms if f != "fp64"):
         plan = tqc.Plan(net, precision=form, out_dtype="f64" if form == "fp64" else "f32", fixed=fixed)
         out = plan.output_tensor()
-        ms = _median_ms(plan, out)
+        plan.execute_profiled(out)
+        phases = np.median(np.array([plan.execute_profiled(out)[1] for _ in range(5)]), axis=0)
+        ms = float(phases.sum())
         if ref is None:
             ref, err = out, 0.0
         else:
             err = (out.double() - ref).abs().max().item() / ref.abs().max().item()
+        steps = plan.steps
+        big = max(range(len(steps)), key=lambda i: steps[i]["flops"])
+        step_ms = float(phases[2 + big])
+        rate = steps[big]["flops"] / (step_ms * 1e-3)
         res[form] = {"ms": ms, "rel_err_vs_fp64": err, "tflops": plan.stats["flops"] / ms / 1e9,
-                     "steps": [(st["log2_m"], st["log2_n"], st["log2_k"]) for st in plan.steps]}
+                     "steps": [(st["log2_m"], st["log2_n"], st["log2_k"]) for st in steps],
+                     "phase_ms": [round(float(x), 4) for x in phases],
+                     "largest_step": {"index": big, "shape_log2_mnk": [steps[big]["log2_m"], steps[big]["log2_n"],
+                                                                        steps[big]["log2_k"]],
+                                      "ms": step_ms, "tflops": rate / 1e12,
+                                      "mfma_frac": rate * PRODUCTS[form] / MFMA_PEAK[form]}}
+        print(f"# {form}: {ms:.2f} ms, largest step {step_ms:.2f} ms "
+              f"({res[form]['largest_step']['mfma_frac']:.3f} of its MFMA peak), err {err:.2e}",
+              file=sys.stderr, flush=True)
+        if form != "fp64":
+            del out
         del plan
         torch.cuda.empty_cache()
     return {"study": "precision", "workload": spec.meta["name"], "entries": 1 << 30, "forms": res}
@@ -186,14 +204,14 @@ def costmodel_study(tqc, torch, candidates=10000):
                                                 seed=3)))
     for name, kw in variants:
         t0 = time.perf_counter()
-        plan = tqc.Plan(net, precision="fp32", out_dtype="f32", fixed=fixed, **kw)
+        plan = tqc.Plan(net, precision="fp32", out_dtype="f64", fixed=fixed, **kw)
         plan_ms = (time.perf_counter() - t0) * 1e3
         out = plan.output_tensor()
         ms = _median_ms(plan, out, 15)
         st = plan.stats
         res[name] = {"execute_ms": ms, "plan_ms": plan_ms, "end_to_end_ms": plan_ms + ms,
                      "predicted_ms": st["predicted_seconds"] * 1e3, "flops": st["flops"],
-                     "bytes": st["bytes"], "rel_err_vs_fp64": (out.double() - ref).abs().max().item() / refmax}
+                     "bytes": st["bytes"], "rel_err_vs_fp64": (out - ref).abs().max().item() / refmax}
         if kw["cost"] == "measured":
             res[name].update(num_measured=st["num_measured"], judge_ms=st["measured_seconds"] * 1e3,
                              judge_fallback_ms=st["fallback_measured_seconds"] * 1e3,
@@ -272,6 +290,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
     probs = float(sum(o.numel() for o in outs))
     for name, kw in (("graph_4streams", dict(use_graph=True, streams=4)),
                      ("graph_8streams", dict(use_graph=True, streams=8)),
+                     ("graph_8streams_batched_final", dict(use_graph=True, streams=8, batched_final=True)),
+                     ("graph_4streams_batched_final", dict(use_graph=True, streams=4, batched_final=True)),
                      ("sequential_plain", dict(use_graph=False, streams=1))):
         mj = tqc.Multi(plans, outs=outs, **kw)
         timed = tqc.Multi(plans, outs=outs, timed=True, **kw)
@@ -292,7 +312,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
         runs[name] = {"batch_ms": batch_ms, "batch_ms_all": [round(x, 4) for x in ms],
                       "jobs_per_s": num_jobs / batch_ms * 1e3, "probs_per_s": probs / batch_ms * 1e3,
                       "per_job_ms": _pcts(en - st), "completion_ms": _pcts(en),
-                      "timed_batch_ms": float(en.max())}
+                      "timed_batch_ms": float(en.max()),
+                      "final_steps_in_shared_launches": mj.info()[0], "shared_launches": mj.info()[1]}
         print(f"# {name}: {batch_ms:.3f} ms per batch", file=sys.stderr, flush=True)
         del mj, timed
     # every output equals the job's own plain execution
@@ -311,6 +332,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
                                              runs["graph_4streams"]["batch_ms"],
             "speedup_graph8_over_sequential": runs["sequential_plain"]["batch_ms"] /
                                               runs["graph_8streams"]["batch_ms"],
+            "speedup_batched_final_over_sequential": runs["sequential_plain"]["batch_ms"] /
+                                                     runs["graph_8streams_batched_final"]["batch_ms"],
             "outputs_equal_plain_execution": same,
             "largest_jobs": sorted(meta, reverse=True)[:3]}
 
@@ -511,7 +534,7 @@ def main():
     from workloads import qaoa
 
     if args.study == "precision":
-        print(json.dumps(precision_study(tqc, torch)))
+        print(json.dumps(precision_study(tqc, torch, tuple(args.forms.split(",")))))
         return
     if args.study == "costmodel":
         print(json.dumps(costmodel_study(tqc, torch)))

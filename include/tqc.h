@@ -426,6 +426,27 @@ typedef struct tqc_multi_s *tqc_multi_t;
 tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams,
                             int32_t timed, void *stream, tqc_multi_t *out);
+/* As tqc_multi_create, with options.  batched_final = 1: every job whose
+ * final pairwise step (the one that writes its 2^n output) runs on the
+ * persistent final-step kernel (float32 output, K <= 256, at least 2^7
+ * rows and columns) leaves that step out of its own launches; after all
+ * jobs' other launches, one persistent launch per (form, K) runs those final
+ * steps for all such jobs, each job on a row of the launch grid with a
+ * device table of the jobs' step records (most tiles first).  The
+ * arithmetic per output entry is unchanged, so results still equal
+ * tqc_execute's bit for bit.  With timed = 1 such a job's end time is the
+ * end of its shared launch.  tqc_multi_info reports how many jobs were
+ * batched so and in how many launches. */
+typedef struct {
+  int32_t use_graph;      /* as tqc_multi_create                          */
+  int32_t num_streams;    /* as tqc_multi_create (0 = 4, at most 16)       */
+  int32_t timed;          /* as tqc_multi_create                          */
+  int32_t batched_final;  /* 1: final steps in shared persistent launches */
+} tqc_multi_options;
+tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                               const uint64_t *out_bytes, const tqc_multi_options *opt, void *stream,
+                               tqc_multi_t *out);
+tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *batched_jobs, int32_t *batched_launches);
 tqc_status tqc_multi_execute(tqc_multi_t multi, void *stream);
 tqc_status tqc_multi_job_times(tqc_multi_t multi, double *start_ms, double *end_ms);
 void tqc_multi_destroy(tqc_multi_t multi);
@@ -456,6 +477,23 @@ typedef struct {
                                   flag and skips its work (the launch still
                                   completes); tqc_batch_job_times reports it. */
 } tqc_batch_options;
+
+/* Host emulation of the batch launch for these plans (no device work, no
+ * GPU needed): the plans' device pointers are replaced by synthetic
+ * addresses for the duration of the call (each buffer its own region), the
+ * work tables are built exactly as tqc_batch_create builds them, and every
+ * loop bound and address of the pre-pass kernels (Pauli transform, leaf
+ * abs-max, exponents) and of every item of the persistent part (unit
+ * lookup, pack chunks, GEMM tiles: operand rows, k step, output addresses,
+ * staged compact index) is walked, as are the level and dependency order of
+ * the units.  out_bytes may be NULL (each job's exact output size).  Returns
+ * OK when every access stays inside the buffer it is made through, else
+ * INTERNAL with the first violation in tqc_last_error() and in report
+ * (optional, report_cap bytes, NUL-terminated).  The plans must not run
+ * meanwhile.  Cost: every transform term, pack entry and output entry once;
+ * meant for checking small batches. */
+tqc_status tqc_batch_validate(int32_t num_jobs, const tqc_plan_t *plans, const uint64_t *out_bytes,
+                              char *report, uint64_t report_cap);
 
 tqc_status tqc_batch_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, const tqc_batch_options *opt,

@@ -82,6 +82,11 @@ class BatchOptions(ctypes.Structure):
                 ("dependency_waits", ctypes.c_int32), ("spin_limit", ctypes.c_uint64)]
 
 
+class MultiOptions(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("timed", ctypes.c_int32),
+                ("batched_final", ctypes.c_int32)]
+
+
 class TrainOptions(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("seed", ctypes.c_uint64)]
@@ -122,6 +127,9 @@ def _declare(L):
         "tqc_multi_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64), i32, i32,
                              i32, vp, ctypes.POINTER(vp)],
         "tqc_multi_execute": [vp, vp],
+        "tqc_multi_create_ex": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64),
+                                ctypes.POINTER(MultiOptions), vp, ctypes.POINTER(vp)],
+        "tqc_multi_info": [vp, _i32p, _i32p],
         "tqc_hss_select": [vp, u64, _i32p, _i32p, u64, _dp, u64, vp],
         "tqc_find_cuts": [i32, i32, _i32p, i32, i32, i32, ctypes.c_double, _i32p, _i32p],
         "tqc_network_select_states": [vp, _i32p, _i32p, vp, ctypes.POINTER(vp)],
@@ -143,6 +151,7 @@ def _declare(L):
         "tqc_costmodel_save": [vp, ctypes.c_char_p],
         "tqc_costmodel_load": [ctypes.c_char_p, ctypes.POINTER(vp)],
         "tqc_plan_step_features": [vp, ctypes.POINTER(ctypes.c_float), i32],
+        "tqc_batch_validate": [i32, ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.c_char_p, u64],
         "tqc_plan_serialize": [vp, vp, ctypes.POINTER(u64)],
         "tqc_plan_deserialize": [vp, vp, u64, ctypes.POINTER(vp)],
         "tqc_plan_workspace_bytes": [vp, ctypes.POINTER(u64)],
@@ -609,7 +618,8 @@ class Multi:
     streams; ``streams=1, use_graph=False`` runs them one after another.
     Outputs equal each plan's own ``execute`` bit for bit."""
 
-    def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None):
+    def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None,
+                 batched_final=False):
         L = lib()
         if outs is None:
             outs = [p.output_tensor() for p in plans]
@@ -623,12 +633,18 @@ class Multi:
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
         ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
         h = ctypes.c_void_p()
-        _check(L.tqc_multi_create(n, ph, oh, ob, int(bool(use_graph)), int(streams), int(self.timed),
-                                  _stream_ptr(stream), ctypes.byref(h)))
+        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(batched_final)))
+        _check(L.tqc_multi_create_ex(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 
     def execute(self, stream=None):
         _check(lib().tqc_multi_execute(self.handle, _stream_ptr(stream)))
+
+    def info(self):
+        """(jobs whose final step runs in a shared launch, shared launches)."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tqc_multi_info(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def job_times(self):
         """(start_ms, end_ms) per job, from the start of the last execute."""
@@ -659,6 +675,19 @@ def find_cuts(num_qubits, gates, w_max, s_max, k_t=10, q_max=1e4):
     _check(lib().tqc_find_cuts(int(num_qubits), n, ctypes.cast(g, _i32p), int(w_max), int(s_max), int(k_t),
                                float(q_max), ctypes.cast(labels, _i32p), ctypes.byref(parts)))
     return np.array(labels[:n], dtype=np.int32), parts.value
+
+
+def batch_validate(plans, out_bytes=None):
+    """Host emulation of the batch launch of these plans (tqc_batch_validate):
+    '' when every access stays in bounds, else the first violation."""
+    n = len(plans)
+    ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    ob = (ctypes.c_uint64 * n)(*out_bytes) if out_bytes is not None else None
+    rep = ctypes.create_string_buffer(1024)
+    st = lib().tqc_batch_validate(n, ph, ob, rep, 1024)
+    if st not in (0, 8):
+        _check(st)
+    return rep.value.decode()
 
 
 def autotune(plan, out=None, reps=3, stream=None):

@@ -534,9 +534,15 @@ struct Timing {
 };
 
 // run slices [s0, s1); root output goes to `root_out` (dtype per kind)
+// True when the plan's final step runs on the persistent final-step kernel
+// (the same test run_slices applies before launching it).
+static bool root_on_persistent(const Plan *p, const Step &st, const GemmArgs &g) {
+  return st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(step_prec(p, st), g);
+}
+
 static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint64_t s1,
                        bool accumulate_first, hipStream_t s, Timing *tm = nullptr,
-                       unsigned long long *tkey = nullptr, double *tsum = nullptr) {
+                       unsigned long long *tkey = nullptr, double *tsum = nullptr, bool defer_root = false) {
   Network &net = *p->net;
   const int m = net.m;
   if (tm) tm->begin(0);
@@ -606,16 +612,20 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
                                 nb.elems(), (uint16_t *)hb, (uint16_t *)(hb + p->h16_plane[1]), sb.maxbits16,
                                 sb.root_scale, sb.root_scale2, s));
       }
-      if (st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(sp, g))
-        HIP_OK(launch_root_gemm(sp, g, s));
-      else HIP_OK(launch_gemm(sp, g, st.tile, s));
+      if (root_on_persistent(p, st, g)) {
+        // deferred: the caller runs it in a launch shared with other jobs
+        if (!defer_root) HIP_OK(launch_root_gemm(sp, g, s));
+      } else {
+        HIP_OK(launch_gemm(sp, g, st.tile, s));
+      }
       if (tm) tm->end();
     }
     first_done = true;
   }
 }
 
-static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timing *tm = nullptr) {
+static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timing *tm = nullptr,
+                    bool defer_root = false) {
   const uint64_t entries = 1ull << p->out_bits;
   const uint64_t need = entries * (p->out_dtype == TQC_F64 ? 8 : 4);
   if (!out) fail(TQC_ERR_INVALID_ARG, "output pointer is null");
@@ -623,7 +633,8 @@ static void execute(Plan *p, void *out, uint64_t out_bytes, hipStream_t s, Timin
                              (unsigned long long)out_bytes, (unsigned long long)need);
   ensure_workspace(p, s);
   if (p->num_slices == 1) {
-    run_slices(p, out, p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32, 0, 1, false, s, tm);
+    run_slices(p, out, p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32, 0, 1, false, s, tm, nullptr, nullptr,
+               defer_root);
     return;
   }
   if (p->out_dtype == TQC_F64) {
@@ -836,41 +847,36 @@ struct Batch {
 
 constexpr bool kBatchLaunchEnabled = false;
 
-static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
-                           const tqc_batch_options &opt, hipStream_t s) {
-  if (njobs < 1) fail(TQC_ERR_INVALID_ARG, "no jobs");
-  std::unique_ptr<Batch> b(new Batch());
-  b->njobs = njobs;
-  b->use_graph = opt.use_graph != 0;
-  b->by_level = opt.dependency_waits ? 0 : 1;
-  b->prec = int(plans[0]->prec);
+// Work tables of a batch: per-job pre-pass records (Pauli transform of raw
+// tensors, leaf abs-max), pack and GEMM argument records, and the work units
+// in level order with their item ranges.  Built from the plans' device
+// pointers (workspaces, Pauli tensors, outputs); the device addresses of
+// the batch's own buffers (leaf exponents, job scales, abs-max bits) are
+// filled in later through `fixes`.
+struct BatchTables {
+  struct Fix { int kind; size_t idx; int leaf; int job; };
+  std::vector<BatchUnit> fin;
+  std::vector<TransformArgs> targs;
+  std::vector<AbsMaxArgs> aargs;
+  std::vector<PackArgs> pargs;
+  std::vector<GemmArgs> gargs;
+  std::vector<Fix> fixes;
+  std::vector<int> job_leaf0{0}, job_cuts;
+  std::vector<unsigned long long> level_first;
+  uint64_t max_t = 0, max_l = 0, total = 0;
+  int nleaves = 0;
+};
+
+static BatchTables build_batch_tables(int njobs, Plan *const *plans, void *const *outs, int prec) {
+  BatchTables T;
   struct TmpUnit {
     BatchUnit u;
     int level;
     double cost;
   };
   std::vector<TmpUnit> units;
-  std::vector<TransformArgs> targs;
-  std::vector<AbsMaxArgs> aargs;
-  std::vector<PackArgs> pargs;
-  std::vector<GemmArgs> gargs;
-  std::vector<int> job_leaf0(1, 0), job_cuts;
-  uint64_t max_t = 0, max_l = 0;
-  // leaf exponents and output scales live in the batch's own buffer; its
-  // device address is known only after allocation, so record indices first
-  struct Fix { int kind; size_t idx; int leaf; int job; };
-  std::vector<Fix> fixes;
   for (int j = 0; j < njobs; ++j) {
     Plan *p = plans[j];
-    if (!p || !outs || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
-    if (int(p->prec) != b->prec) fail(TQC_ERR_INVALID_ARG, "job %d: all jobs need one precision", j);
-    if (p->prec == Prec::F16X3) fail(TQC_ERR_UNSUPPORTED, "job %d: float16-split plans are not batched", j);
-    if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not batched", j);
-    const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
-    if (out_bytes && out_bytes[j] < need) fail(TQC_ERR_SHAPE, "job %d: output too small", j);
-    ensure_workspace(p, s);
-    b->plans.push_back(p);
-    b->outs.push_back(outs[j]);
     Network &net = *p->net;
     const int m = net.m;
     const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
@@ -879,10 +885,19 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
     for (int t = 0; t < m; ++t) {
       const TensorIn &ti = net.t[t];
       if (ti.basis != TQC_BASIS_RAW) continue;
-      targs.push_back(make_transform_args(ti, ti.dev_pauli));
-      max_t = std::max<uint64_t>(max_t, ti.pauli_entries());
+      const TransformArgs ta = make_transform_args(ti, ti.dev_pauli);
+      // the transform kernel's loop bounds: 4^c x 2^o entries, 2 bits of
+      // option state per cut in 32 bits, raw rows x 2^(o+u) columns
+      if (ta.c > kMaxCutsT || ta.o + ta.u > 62 || 2 * ta.c + ta.o > 62 || !ta.raw || !ta.out)
+        fail(TQC_ERR_UNSUPPORTED, "job %d tensor %d: transform of %d cuts, %d outputs", j, t, ta.c, ta.o);
+      uint64_t rows = 1;
+      for (int i = 0; i < ta.c; ++i) rows *= ta.up[i] ? 3 : 4;
+      if (rows != ti.rows || (1ull << (ta.o + ta.u)) != ti.cols)
+        fail(TQC_ERR_INTERNAL, "job %d tensor %d: transform record does not match its raw layout", j, t);
+      T.targs.push_back(ta);
+      T.max_t = std::max<uint64_t>(T.max_t, ti.pauli_entries());
     }
-    const int leaf0 = job_leaf0.back();
+    const int leaf0 = T.job_leaf0.back();
     if (m >= 2) {
       // abs-max of every leaf, as in compute_scales
       for (int t = 0; t < m; ++t) {
@@ -890,23 +905,28 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
         PackArgs pa = make_pack_args(p, t, nullptr, nullptr, nullptr, 0, 0);
         AbsMaxArgs a{};
         a.src = ti.dev_pauli;
-        const int c = (int)ti.cuts.size(), o = (int)ti.outputs.size();
+        const int o = (int)ti.outputs.size();
         for (int i = 0; i < o; ++i) {
           auto it = std::find(p->fixed_q.begin(), p->fixed_q.end(), ti.outputs[i]);
           if (it != p->fixed_q.end()) a.base |= (uint64_t)p->fixed_v[it - p->fixed_q.begin()] << i;
         }
         a.nbits = pa.nbits;
         for (int i = 0; i < pa.nbits; ++i) a.inpos[i] = pa.inpos[i];
-        (void)c;
-        fixes.push_back({0, aargs.size(), leaf0 + t, j});
-        aargs.push_back(a);
-        max_l = std::max<uint64_t>(max_l, 1ull << a.nbits);
+        // largest source index the abs-max kernel forms: every gathered bit set
+        uint64_t hi = a.base;
+        for (int i = 0; i < a.nbits; ++i) hi += 1ull << a.inpos[i];
+        if (a.nbits > kMaxBits || !a.src || hi >= ti.pauli_entries())
+          fail(TQC_ERR_INTERNAL, "job %d leaf %d: abs-max reads index %llu of %llu", j, t, (unsigned long long)hi,
+               (unsigned long long)ti.pauli_entries());
+        T.fixes.push_back({0, T.aargs.size(), leaf0 + t, j});
+        T.aargs.push_back(a);
+        T.max_l = std::max<uint64_t>(T.max_l, 1ull << a.nbits);
       }
-      job_leaf0.push_back(leaf0 + m);
+      T.job_leaf0.push_back(leaf0 + m);
     } else {
-      job_leaf0.push_back(leaf0);
+      T.job_leaf0.push_back(leaf0);
     }
-    job_cuts.push_back(net.K);
+    T.job_cuts.push_back(net.K);
     for (int t = 0; t < m; ++t) {
       const Node &nd = p->nodes[t];
       TmpUnit u{};
@@ -914,17 +934,15 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
       u.u.job = j;
       u.u.dep0 = -1;
       u.u.dep1 = -1;
-      u.u.arg = (int)pargs.size();
+      u.u.arg = (int)T.pargs.size();
       if (m == 1) {
-        pargs.push_back(make_pack_args(p, t, outs[j], nullptr, nullptr,
-                                       p->out_dtype == TQC_F64 ? 0 : 1, 0));
+        T.pargs.push_back(make_pack_args(p, t, outs[j], nullptr, nullptr, p->out_dtype == TQC_F64 ? 0 : 1, 0));
         u.u.is_root = 1;
       } else {
         char *bp = (char *)p->ws + nd.offset;
-        pargs.push_back(make_pack_args(p, t, bp, nd.planes > 1 ? bp + nd.plane_bytes : nullptr,
-                                       nd.planes > 2 ? bp + 2 * nd.plane_bytes : nullptr,
-                                       int(p->prec), 0));
-        fixes.push_back({1, pargs.size() - 1, leaf0 + t, j});
+        T.pargs.push_back(make_pack_args(p, t, bp, nd.planes > 1 ? bp + nd.plane_bytes : nullptr,
+                                         nd.planes > 2 ? bp + 2 * nd.plane_bytes : nullptr, int(p->prec), 0));
+        T.fixes.push_back({1, T.pargs.size() - 1, leaf0 + t, j});
       }
       u.u.ntiles = ((1ull << nd.labels.size()) + 4095) / 4096;
       u.level = 1;
@@ -938,15 +956,15 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
       u.u.job = j;
       u.u.dep0 = node_unit[st.a];
       u.u.dep1 = node_unit[st.b];
-      u.u.arg = (int)gargs.size();
+      u.u.arg = (int)T.gargs.size();
       u.u.tile = st.tile;
       u.u.is_root = st.root ? 1 : 0;
       GemmArgs g = make_gemm_args(p, st, outs[j], root_kind);
       const int bm = tile_bm(st.tile);
-      prepare_gemm_args(g, b->prec, bm, bm);
+      prepare_gemm_args(g, prec, bm, bm);
       g.swz = 0;  // the work queue decides placement
-      if (st.root) fixes.push_back({2, gargs.size(), -1, j});
-      gargs.push_back(g);
+      if (st.root) T.fixes.push_back({2, T.gargs.size(), -1, j});
+      T.gargs.push_back(g);
       const uint64_t tm = ((1ull << st.lm) + bm - 1) / bm, tn = ((1ull << st.ln) + bm - 1) / bm;
       u.u.ntiles = tm * tn;
       depth[st.out] = 1 + std::max(depth[st.a], depth[st.b]);
@@ -956,7 +974,9 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
       units.push_back(u);
     }
   }
-  const int nleaves = job_leaf0.back();
+  T.nleaves = T.job_leaf0.back();
+  // the pre-pass grids index records by blockIdx.y
+  if (T.targs.size() > 65535 || T.nleaves > 65535) fail(TQC_ERR_UNSUPPORTED, "too many tensors in one batch");
   // level order; inside a level, the most expensive jobs first
   std::vector<int> order(units.size());
   std::iota(order.begin(), order.end(), 0);
@@ -966,7 +986,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   });
   std::vector<int> newid(units.size());
   for (size_t i = 0; i < order.size(); ++i) newid[order[i]] = (int)i;
-  std::vector<BatchUnit> fin(units.size());
+  T.fin.resize(units.size());
   uint64_t first = 0;
   for (size_t i = 0; i < order.size(); ++i) {
     BatchUnit u = units[order[i]].u;
@@ -974,19 +994,53 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
     if (u.dep1 >= 0) u.dep1 = newid[u.dep1];
     u.first = first;
     first += u.ntiles;
-    fin[i] = u;
+    T.fin[i] = u;
   }
-  b->nunits = (int)fin.size();
-  b->total = first;
+  T.total = first;
   // item ranges of the levels (units are sorted by level)
-  {
-    std::vector<int> lev(order.size());
-    for (size_t i = 0; i < order.size(); ++i) lev[i] = units[order[i]].level;
-    b->level_first.clear();
-    for (size_t i = 0; i < fin.size(); ++i)
-      if (i == 0 || lev[i] != lev[i - 1]) b->level_first.push_back(fin[i].first);
-    b->level_first.push_back(first);
+  std::vector<int> lev(order.size());
+  for (size_t i = 0; i < order.size(); ++i) lev[i] = units[order[i]].level;
+  for (size_t i = 0; i < T.fin.size(); ++i)
+    if (i == 0 || lev[i] != lev[i - 1]) T.level_first.push_back(T.fin[i].first);
+  T.level_first.push_back(first);
+  return T;
+}
+
+static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
+                           const tqc_batch_options &opt, hipStream_t s) {
+  if (njobs < 1) fail(TQC_ERR_INVALID_ARG, "no jobs");
+  std::unique_ptr<Batch> b(new Batch());
+  b->njobs = njobs;
+  b->use_graph = opt.use_graph != 0;
+  b->by_level = opt.dependency_waits ? 0 : 1;
+  b->prec = int(plans[0]->prec);
+  for (int j = 0; j < njobs; ++j) {
+    Plan *p = plans[j];
+    if (!p || !outs || !outs[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan or output", j);
+    if (int(p->prec) != b->prec) fail(TQC_ERR_INVALID_ARG, "job %d: all jobs need one precision", j);
+    if (p->prec == Prec::F16X3) fail(TQC_ERR_UNSUPPORTED, "job %d: float16-split plans are not batched", j);
+    if (p->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not batched", j);
+    const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
+    if (out_bytes && out_bytes[j] < need) fail(TQC_ERR_SHAPE, "job %d: output too small", j);
+    for (int i = 0; i < j; ++i)
+      if (plans[i] == p || plans[i]->net == p->net)
+        fail(TQC_ERR_INVALID_ARG, "jobs %d and %d share a plan or network", i, j);
+    ensure_workspace(p, s);
+    b->plans.push_back(p);
+    b->outs.push_back(outs[j]);
   }
+  BatchTables T = build_batch_tables(njobs, plans, outs, b->prec);
+  std::vector<BatchUnit> &fin = T.fin;
+  std::vector<TransformArgs> &targs = T.targs;
+  std::vector<AbsMaxArgs> &aargs = T.aargs;
+  std::vector<PackArgs> &pargs = T.pargs;
+  std::vector<GemmArgs> &gargs = T.gargs;
+  std::vector<int> &job_leaf0 = T.job_leaf0, &job_cuts = T.job_cuts;
+  const int nleaves = T.nleaves;
+  const uint64_t max_t = T.max_t, max_l = T.max_l;
+  b->nunits = (int)fin.size();
+  b->total = T.total;
+  b->level_first = T.level_first;
   // host-side checks before anything runs: dependencies point backwards,
   // and every argument record is within the ranges the kernels assume
   for (size_t i = 0; i < fin.size(); ++i) {
@@ -1030,7 +1084,7 @@ static Batch *create_batch(int njobs, Plan *const *plans, void *const *outs, con
   unsigned long long *d_max = (unsigned long long *)(dm + o_mx);
   int *d_exp = (int *)(dm + o_ex);
   double *d_rs = (double *)(dm + o_rs);
-  for (const Fix &f : fixes) {
+  for (const BatchTables::Fix &f : T.fixes) {
     if (f.kind == 0) aargs[f.idx].out = d_max + f.leaf;
     else if (f.kind == 1) pargs[f.idx].dexp = d_exp + f.leaf;
     else gargs[f.idx].dscale = d_rs + f.job;
@@ -1148,6 +1202,331 @@ static void batch_times(Batch *b, double *start_ms, double *end_ms, uint32_t *er
     if (end_ms) end_ms[j] = en[j] >= t0 ? double(en[j] - t0) / b->tick_khz : -1.0;
   }
   if (error) *error = err;
+}
+
+// ----------------------------------------------- host emulation of a batch
+// Replays on the host what the batch launch would do for these plans, with
+// no device work: the plans' and networks' device pointers are replaced by
+// distinct synthetic addresses (each buffer its own region, far apart), the
+// work tables are built exactly as for the launch, and then every kernel's
+// loop bounds and every address it would read or write are walked:
+//   pre-pass: the Pauli transform's option odometer per entry (iteration
+//     count, raw reads, Pauli writes), every abs-max read, the exponent and
+//     scale writes;
+//   persistent part: every item's unit lookup (the kernel's binary search),
+//     each pack chunk's reads and writes, each GEMM tile's operand rows and
+//     k range against the tile's k step, its output addresses (direct, or
+//     through the staged compact index, which must equal the direct ones),
+//     and the level / dependency order of units.
+// An access must stay inside the region of the pointer it is made through.
+// Returns an empty string, or a description of the first violation.
+namespace {
+struct EmuRegions {
+  struct R { uint64_t lo, hi; std::string what; };
+  std::vector<R> r;
+  uint64_t next = 1ull << 44;
+  void *fresh(uint64_t bytes, const std::string &what) {
+    const uint64_t lo = next;
+    next += (((bytes + 4095) >> 12) << 12) + (1ull << 36);
+    r.push_back({lo, lo + bytes, what});
+    return (void *)lo;
+  }
+  void add(const void *p, uint64_t bytes, const std::string &what) {
+    r.push_back({(uint64_t)p, (uint64_t)p + bytes, what});
+  }
+  const R *find(const void *p) const {
+    const uint64_t a = (uint64_t)p;
+    const R *best = nullptr;
+    for (const R &x : r)
+      if (a >= x.lo && a < x.hi + (x.hi == x.lo ? 1 : 0) && (!best || x.hi - x.lo < best->hi - best->lo)) best = &x;
+    return best;
+  }
+};
+
+struct EmuFail {
+  std::string msg;
+};
+
+[[noreturn]] void emu_fail(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw EmuFail{buf};
+}
+
+void emu_access(const EmuRegions &R, const void *base, uint64_t elem, uint64_t esz, const char *what) {
+  const EmuRegions::R *reg = R.find(base);
+  if (!reg) emu_fail("%s: pointer %p lies in no buffer", what, base);
+  const uint64_t a = (uint64_t)base + elem * esz;
+  if (a < reg->lo || a + esz > reg->hi)
+    emu_fail("%s: element %llu (%llu bytes) beyond %s (%llu bytes)", what, (unsigned long long)elem,
+             (unsigned long long)esz, reg->what.c_str(), (unsigned long long)(reg->hi - reg->lo));
+}
+
+uint64_t emu_deposit(uint64_t v, const uint8_t *pos, int nbits) {
+  uint64_t r = 0;
+  for (int i = 0; i < nbits; ++i) r |= ((v >> i) & 1ull) << pos[i];
+  return r;
+}
+
+int emu_down_opts(int s) { return (s == 1 || s == 2) ? 3 : 2; }
+int emu_down_prep(int s, int o) { return (s == 1 || s == 2) ? (o == 0 ? s + 1 : o - 1) : o; }
+
+// transform_elem's enumeration for one entry: returns the number of terms
+uint64_t emu_transform_entry(const EmuRegions &R, const TransformArgs &a, uint64_t e) {
+  if (a.c < 0 || a.c > kMaxCutsT || a.o < 0 || a.u < 0 || a.o + a.u > 62) emu_fail("transform: c %d o %d u %d", a.c, a.o, a.u);
+  const uint64_t cols = 1ull << (a.o + a.u);
+  const uint64_t x = e & ((1ull << a.o) - 1);
+  const uint64_t row = e >> a.o;
+  uint32_t opt = 0;
+  uint64_t terms = 0;
+  while (true) {
+    uint64_t rin = 0, b = 0;
+    for (int t = 0; t < a.c; ++t) {
+      const int s = (int)((row >> (2 * (a.c - 1 - t))) & 3);
+      const int o = (int)((opt >> (2 * t)) & 3u);
+      if (a.up[t]) {
+        if (a.bbit[t] < 0 || a.bbit[t] >= a.u) emu_fail("transform: measured bit %d of %d", a.bbit[t], a.u);
+        rin += (uint64_t)((s == 3) ? 0 : s) * a.w[t];
+        b |= (uint64_t)o << a.bbit[t];
+      } else {
+        rin += (uint64_t)emu_down_prep(s, o) * a.w[t];
+      }
+    }
+    emu_access(R, a.raw, rin * cols + ((x << a.u) | b), 8, "transform read");
+    if (++terms > 43046721ull) emu_fail("transform: option loop does not end");
+    int t = a.c - 1;
+    for (; t >= 0; --t) {
+      const int s = (int)((row >> (2 * (a.c - 1 - t))) & 3);
+      const uint32_t n = a.up[t] ? 2u : (uint32_t)emu_down_opts(s);
+      const uint32_t o = ((opt >> (2 * t)) & 3u) + 1u;
+      opt &= ~(3u << (2 * t));
+      if (o < n) {
+        opt |= o << (2 * t);
+        break;
+      }
+    }
+    if (t < 0) break;
+  }
+  emu_access(R, a.out, e, 8, "transform write");
+  return terms;
+}
+
+int emu_plane_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+
+void emu_pack_entry(const EmuRegions &R, const PackArgs &a, uint64_t e) {
+  uint64_t src = a.base;
+  for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
+  emu_access(R, a.src, src, 8, "pack read");
+  if (a.dexp) emu_access(R, a.dexp, 0, 4, "pack exponent read");
+  const uint64_t kmask = (1ull << a.lk) - 1;
+  const uint64_t d = ((e >> a.lk) << a.kpad) | (e & kmask);
+  const int eb = emu_plane_bytes(a.prec);
+  emu_access(R, a.dst0, d, eb, "pack write (plane 0)");
+  if (a.prec >= 2) emu_access(R, a.dst1, d, eb, "pack write (plane 1)");
+  if (a.prec >= 3) emu_access(R, a.dst2, d, eb, "pack write (plane 2)");
+}
+
+void emu_gemm_tile(const EmuRegions &R, const GemmArgs &g, int prec, int tile, uint64_t t) {
+  const int BM = tile_bm(tile), BN = BM;
+  int BK = 32;
+  if (prec == 0) BK = 16;
+  else if (prec == 1) BK = (g.lk > 8 || g.kpad >= 5) ? 32 : 16;
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln, KP = 1ull << g.kpad;
+  if (g.ksplit) emu_fail("gemm: split k inside the batch");
+  if (KP % BK) emu_fail("gemm: row stride 2^%d is not a multiple of the k step %d", g.kpad, BK);
+  const uint64_t tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  if (t >= tilesM * tilesN) emu_fail("gemm: tile %llu of %llu", (unsigned long long)t,
+                                     (unsigned long long)(tilesM * tilesN));
+  if (g.swz) emu_fail("gemm: swizzled placement inside the batch");
+  const uint64_t tm = t / tilesN, tn = t % tilesN;
+  const uint64_t m0 = tm * BM, n0 = tn * BN;
+  const int planes = prec == 2 ? 2 : (prec == 3 ? 3 : 1);
+  const int eb = emu_plane_bytes(prec);
+  const void *A[3] = {g.a0, g.a1, g.a2}, *B[3] = {g.b0, g.b1, g.b2};
+  for (int p = 0; p < planes; ++p)
+    for (uint64_t r = m0; r < std::min(M, m0 + BM); ++r) {
+      emu_access(R, A[p], r * KP, eb, "gemm A row start");
+      emu_access(R, A[p], r * KP + KP - 1, eb, "gemm A row end");
+    }
+  for (int p = 0; p < planes; ++p)
+    for (uint64_t r = n0; r < std::min(N, n0 + BN); ++r) {
+      emu_access(R, B[p], r * KP, eb, "gemm B row start");
+      emu_access(R, B[p], r * KP + KP - 1, eb, "gemm B row end");
+    }
+  if (g.dscale) emu_access(R, g.dscale, 0, 8, "gemm scale read");
+  const int oeb = g.out_kind == OUT_F64 || g.out_kind == OUT_F64_ACC ? 8 : (g.out_kind == OUT_F32 ? 4 : 2);
+  const int lbm = __builtin_ctz(BM), lbn = __builtin_ctz(BN);
+  const bool staged = prec != 0 && g.staged;
+  const uint64_t base = emu_deposit(m0, g.posM, g.lm) + emu_deposit(n0, g.posN, g.ln);
+  for (uint64_t i = 0; i < (uint64_t)BM && m0 + i < M; ++i)
+    for (uint64_t j = 0; j < (uint64_t)BN && n0 + j < N; ++j) {
+      const uint64_t addr = emu_deposit(m0 + i, g.posM, g.lm) + emu_deposit(n0 + j, g.posN, g.ln);
+      if (staged) {
+        const uint64_t x = emu_deposit(i, g.rankM, lbm) | emu_deposit(j, g.rankN, lbn);
+        if (x >= (uint64_t)(BM * BN)) emu_fail("gemm: staged index %llu", (unsigned long long)x);
+        if (base + emu_deposit(x, g.lpos, g.ncompact) != addr) emu_fail("gemm: staged address differs");
+        if (g.vec4 && (addr & 3) != (x & 3)) emu_fail("gemm: float4 run misaligned");
+      }
+      emu_access(R, g.c0, addr, oeb, "gemm write (plane 0)");
+      if (g.out_kind == OUT_SPLIT2 || g.out_kind == OUT_SPLIT3) emu_access(R, g.c1, addr, oeb, "gemm write (plane 1)");
+      if (g.out_kind == OUT_SPLIT3) emu_access(R, g.c2, addr, oeb, "gemm write (plane 2)");
+    }
+}
+}  // namespace
+
+static std::string batch_emulate(int njobs, Plan *const *plans, const uint64_t *out_bytes, uint64_t max_terms) {
+  if (njobs < 1 || !plans) return "no jobs";
+  // swap in synthetic addresses
+  struct Saved { Plan *p; void *ws; std::vector<std::pair<double *, double *>> t; };
+  std::vector<Saved> saved;
+  for (int j = 0; j < njobs; ++j) {
+    for (int i = 0; i < j; ++i)
+      if (plans[i] == plans[j] || plans[i]->net == plans[j]->net) return "two jobs share a plan or network";
+    Saved sv{plans[j], plans[j]->ws, {}};
+    for (auto &t : plans[j]->net->t) sv.t.push_back({t.dev_raw, t.dev_pauli});
+    saved.push_back(sv);
+  }
+  EmuRegions R;
+  std::vector<void *> outs(njobs);
+  std::string err;
+  try {
+    const int prec = int(plans[0]->prec);
+    for (int j = 0; j < njobs; ++j) {
+      Plan *p = plans[j];
+      if (int(p->prec) != prec || p->prec == Prec::F16X3 || p->num_slices != 1)
+        return "jobs must share one precision other than fp16x3 and be unsliced";
+      char nm[64];
+      for (size_t ti = 0; ti < p->net->t.size(); ++ti) {
+        auto &t = p->net->t[ti];
+        snprintf(nm, sizeof(nm), "job %d tensor %zu input", j, ti);
+        t.dev_raw = (double *)R.fresh(t.rows * t.cols * 8, nm);
+      }
+      snprintf(nm, sizeof(nm), "job %d workspace", j);
+      p->ws = R.fresh(p->ws_bytes, nm);
+      uint64_t off = 0;
+      for (auto &t : p->net->t) {
+        if (t.basis == TQC_BASIS_RAW) {
+          t.dev_pauli = (double *)((char *)p->ws + off);
+          off = (off + t.pauli_entries() * 8 + 255) & ~uint64_t(255);
+        } else {
+          t.dev_pauli = t.dev_raw;
+        }
+      }
+      const uint64_t need = (1ull << p->out_bits) * (p->out_dtype == TQC_F64 ? 8 : 4);
+      snprintf(nm, sizeof(nm), "job %d output", j);
+      outs[j] = R.fresh(out_bytes ? out_bytes[j] : need, nm);
+    }
+    BatchTables T = build_batch_tables(njobs, plans, outs.data(), prec);
+    // finer regions inside each workspace: every node plane and Pauli tensor
+    for (int j = 0; j < njobs; ++j) {
+      Plan *p = plans[j];
+      for (size_t i = 0; i < p->nodes.size(); ++i) {
+        const Node &nd = p->nodes[i];
+        if (nd.plane_bytes == 0) continue;
+        for (int q = 0; q < nd.planes; ++q)
+          R.add((char *)p->ws + nd.offset + q * nd.plane_bytes, nd.elems() * emu_plane_bytes(prec == 4 ? 1 : prec),
+                "job " + std::to_string(j) + " node " + std::to_string(i) + " plane " + std::to_string(q));
+      }
+      for (size_t ti = 0; ti < p->net->t.size(); ++ti) {
+        const auto &t = p->net->t[ti];
+        if (t.basis == TQC_BASIS_RAW)
+          R.add(t.dev_pauli, t.pauli_entries() * 8, "job " + std::to_string(j) + " Pauli tensor " + std::to_string(ti));
+      }
+    }
+    unsigned long long *d_max = (unsigned long long *)R.fresh(std::max(1, T.nleaves) * 8, "leaf abs-max bits");
+    int *d_exp = (int *)R.fresh(std::max(1, T.nleaves) * 4, "leaf exponents");
+    double *d_rs = (double *)R.fresh(njobs * 8, "job scales");
+    for (const BatchTables::Fix &f : T.fixes) {
+      if (f.kind == 0) T.aargs[f.idx].out = d_max + f.leaf;
+      else if (f.kind == 1) T.pargs[f.idx].dexp = d_exp + f.leaf;
+      else T.gargs[f.idx].dscale = d_rs + f.job;
+    }
+    // pre-pass: transform
+    uint64_t terms = 0;
+    for (const TransformArgs &a : T.targs) {
+      const uint64_t n = (1ull << (2 * a.c)) << a.o;
+      for (uint64_t e = 0; e < n; ++e) {
+        terms += emu_transform_entry(R, a, e);
+        if (terms > max_terms) emu_fail("emulation budget exceeded (transform)");
+      }
+    }
+    // pre-pass: abs-max, exponents, scales
+    if ((int)T.aargs.size() != T.nleaves) emu_fail("abs-max records %zu for %d leaves", T.aargs.size(), T.nleaves);
+    for (const AbsMaxArgs &a : T.aargs) {
+      if (a.nbits < 0 || a.nbits > kMaxBits) emu_fail("abs-max: %d bits", a.nbits);
+      for (uint64_t e = 0; e < (1ull << a.nbits); ++e) {
+        uint64_t src = a.base;
+        for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
+        emu_access(R, a.src, src, 8, "abs-max read");
+      }
+      emu_access(R, a.out, 0, 8, "abs-max result");
+    }
+    if ((int)T.job_leaf0.size() != njobs + 1) emu_fail("leaf offsets");
+    for (int j = 0; j < njobs; ++j) {
+      if (T.job_leaf0[j] > T.job_leaf0[j + 1] || T.job_leaf0[j + 1] > T.nleaves) emu_fail("leaf range of job %d", j);
+      for (int l = T.job_leaf0[j]; l < T.job_leaf0[j + 1]; ++l) {
+        emu_access(R, d_max, l, 8, "scale: abs-max read");
+        emu_access(R, d_exp, l, 4, "scale: exponent write");
+      }
+      emu_access(R, d_rs, j, 8, "scale: job scale write");
+    }
+    // units, levels, items
+    const int nunits = (int)T.fin.size();
+    std::vector<int> level_of(nunits, -1);
+    for (size_t L = 0; L + 1 < T.level_first.size(); ++L)
+      for (int u = 0; u < nunits; ++u)
+        if (T.fin[u].first >= T.level_first[L] && T.fin[u].first < T.level_first[L + 1]) level_of[u] = (int)L;
+    for (int u = 0; u < nunits; ++u) {
+      const BatchUnit &bu = T.fin[u];
+      if (level_of[u] < 0) emu_fail("unit %d in no level", u);
+      if (bu.ntiles == 0 || bu.ntiles >= (1ull << 32)) emu_fail("unit %d: %llu items", u, (unsigned long long)bu.ntiles);
+      if (bu.first + bu.ntiles > T.level_first[level_of[u] + 1]) emu_fail("unit %d crosses a level", u);
+      for (int d : {bu.dep0, bu.dep1})
+        if (d >= 0 && (d >= u || level_of[d] >= level_of[u])) emu_fail("unit %d depends on unit %d of a later level", u, d);
+      if (bu.kind == UNIT_PACK) {
+        if (bu.arg < 0 || bu.arg >= (int)T.pargs.size()) emu_fail("unit %d: pack record %d", u, bu.arg);
+      } else if (bu.kind == UNIT_GEMM) {
+        if (bu.arg < 0 || bu.arg >= (int)T.gargs.size()) emu_fail("unit %d: gemm record %d", u, bu.arg);
+        if (bu.tile < 0 || bu.tile > 2) emu_fail("unit %d: tile %d", u, bu.tile);
+      } else {
+        emu_fail("unit %d: kind %d", u, bu.kind);
+      }
+    }
+    for (uint64_t item = 0; item < T.total; ++item) {
+      int lo = 0, hi = nunits - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T.fin[mid].first <= item) lo = mid;
+        else hi = mid - 1;
+      }
+      const BatchUnit &bu = T.fin[lo];
+      if (item < bu.first || item >= bu.first + bu.ntiles) emu_fail("item %llu maps to unit %d", (unsigned long long)item, lo);
+      const uint64_t t = item - bu.first;
+      if (bu.kind == UNIT_PACK) {
+        const PackArgs &a = T.pargs[bu.arg];
+        const uint64_t total = 1ull << a.nbits;
+        const uint64_t e1 = std::min(total, (t + 1) * 4096);
+        for (uint64_t e = t * 4096; e < e1; ++e) emu_pack_entry(R, a, e);
+      } else {
+        emu_gemm_tile(R, T.gargs[bu.arg], prec, bu.tile, t);
+      }
+    }
+  } catch (const EmuFail &f) {
+    err = f.msg;
+  } catch (const Error &e) {
+    err = e.msg;
+  }
+  for (const Saved &sv : saved) {
+    sv.p->ws = sv.ws;
+    for (size_t i = 0; i < sv.t.size(); ++i) {
+      sv.p->net->t[i].dev_raw = sv.t[i].first;
+      sv.p->net->t[i].dev_pauli = sv.t[i].second;
+    }
+  }
+  return err;
 }
 
 // --------------------------------------------------------------- autotune
@@ -1371,7 +1750,19 @@ struct Multi {
   std::vector<hipEvent_t> join;
   hipStream_t last_stream = nullptr;
   bool ran = false;
+  // batched final steps: jobs whose final step runs on the persistent
+  // kernel are grouped by (form, kpad); each group is one launch over a
+  // device table of the jobs' final-step records, after every job's
+  // earlier launches
+  struct RootClass {
+    int prec, kpad, count, blocks;
+    uint64_t first;  // first record in root_tab
+  };
+  std::vector<RootClass> classes;
+  std::vector<int> class_of;      // job -> class (-1: its final step runs with the job)
+  RootJob *root_tab = nullptr;
   ~Multi() {
+    if (root_tab) (void)hipFree(root_tab);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto e : join) (void)hipEventDestroy(e);
@@ -1383,7 +1774,7 @@ struct Multi {
 };
 
 static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
-                           int use_graph, int nstreams, int timed, hipStream_t s) {
+                           int use_graph, int nstreams, int timed, hipStream_t s, int batched_final = 0) {
   if (njobs < 1 || !plans || !outs) fail(TQC_ERR_INVALID_ARG, "no jobs");
   if (nstreams < 0 || nstreams > 16) fail(TQC_ERR_INVALID_ARG, "streams %d (0..16)", nstreams);
   if (nstreams == 0) nstreams = 4;
@@ -1423,13 +1814,56 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
     b->stream_of[j] = k;
     load[k] += cost[j];
   }
+  b->class_of.assign(njobs, -1);
+  if (batched_final) {
+    // the final-step record of every job whose final step runs on the
+    // persistent kernel, exactly as run_slices would launch it
+    std::map<std::pair<int, int>, std::vector<std::pair<int, RootJob>>> groups;
+    for (int j : b->order) {
+      Plan *p = b->plans[j];
+      if (p->net->m < 2) continue;
+      const Step *root = root_step(p);
+      if (!root) continue;
+      const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+      GemmArgs g = make_gemm_args(p, *root, b->outs[j], root_kind, scale_buffers(p).root_scale);
+      if (!root_on_persistent(p, *root, g)) continue;
+      const int sp = step_prec(p, *root);
+      groups[{sp, g.kpad}].push_back({j, make_root_job(sp, g)});
+    }
+    std::vector<RootJob> tab;
+    const int cus = std::max(1, root_gemm_warm());
+    for (auto &kv : groups) {
+      Multi::RootClass c{kv.first.first, kv.first.second, (int)kv.second.size(), 8, tab.size()};
+      // jobs in launch order (largest first: their workgroups start first);
+      // workgroups per job: enough that the largest job's share per
+      // workgroup stays below twice the class's share per compute unit
+      uint64_t total = 0, most = 0;
+      for (auto &x : kv.second) {
+        total += x.second.ntiles;
+        most = std::max<uint64_t>(most, x.second.ntiles);
+      }
+      uint64_t want = (2 * (uint64_t)cus * most + total - 1) / std::max<uint64_t>(total, 1);
+      want = std::min<uint64_t>(std::max<uint64_t>(want, 8), (uint64_t)cus);
+      c.blocks = (int)((want + 7) & ~7ull);
+      for (auto &x : kv.second) {
+        b->class_of[x.first] = (int)b->classes.size();
+        tab.push_back(x.second);
+      }
+      b->classes.push_back(c);
+    }
+    if (!tab.empty()) {
+      HIP_OK(hipMalloc((void **)&b->root_tab, tab.size() * sizeof(RootJob)));
+      HIP_OK(hipMemcpy(b->root_tab, tab.data(), tab.size() * sizeof(RootJob), hipMemcpyHostToDevice));
+    }
+  }
   if (b->timed) {
     int khz = 0;
     HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
     if (khz <= 0) fail(TQC_ERR_DEVICE, "device reports no clock rate for timestamps");
     b->tick_ms = 1.0 / khz;
-    HIP_OK(hipMalloc((void **)&b->stamps, (1 + 2 * (size_t)njobs) * 8));
-    HIP_OK(launch_zero_u64(b->stamps, 1 + 2 * (uint64_t)njobs, s));
+    const uint64_t nst = 1 + 2 * (uint64_t)njobs + b->classes.size();
+    HIP_OK(hipMalloc((void **)&b->stamps, nst * 8));
+    HIP_OK(launch_zero_u64(b->stamps, nst, s));
   }
   HIP_OK(hipStreamSynchronize(s));
   b->streams.resize(nstreams);
@@ -1448,13 +1882,21 @@ static void multi_enqueue(Multi *b, hipStream_t origin) {
   for (auto st : b->streams) HIP_OK(hipStreamWaitEvent(st, b->fork, 0));
   for (int j : b->order) {
     hipStream_t st = b->streams[b->stream_of[j]];
+    const bool deferred = b->class_of[j] >= 0;
     if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * j, st));
-    execute(b->plans[j], b->outs[j], b->out_bytes[j], st);
-    if (b->timed) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
+    execute(b->plans[j], b->outs[j], b->out_bytes[j], st, nullptr, deferred);
+    if (b->timed && !deferred) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
   }
   for (size_t k = 0; k < b->streams.size(); ++k) {
     HIP_OK(hipEventRecord(b->join[k], b->streams[k]));
     HIP_OK(hipStreamWaitEvent(origin, b->join[k], 0));
+  }
+  // the deferred final steps, one persistent launch per (form, kpad)
+  const uint64_t cls0 = 1 + 2 * (uint64_t)b->plans.size();
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    const Multi::RootClass &rc = b->classes[c];
+    HIP_OK(launch_root_multi(rc.prec, rc.kpad, b->root_tab + rc.first, rc.count, rc.blocks, origin));
+    if (b->timed) HIP_OK(launch_stamp(b->stamps + cls0 + c, origin));
   }
 }
 
@@ -1496,11 +1938,13 @@ static void multi_times(Multi *b, double *start_ms, double *end_ms) {
   check_device(b->device);
   HIP_OK(hipStreamSynchronize(b->last_stream));
   const size_t n = b->plans.size();
-  std::vector<unsigned long long> st(1 + 2 * n);
+  std::vector<unsigned long long> st(1 + 2 * n + b->classes.size());
   HIP_OK(hipMemcpy(st.data(), b->stamps, st.size() * 8, hipMemcpyDeviceToHost));
   for (size_t j = 0; j < n; ++j) {
+    // a job whose final step ran in a shared launch ends with that launch
+    const uint64_t e = b->class_of[j] >= 0 ? 1 + 2 * n + b->class_of[j] : 2 + 2 * j;
     if (start_ms) start_ms[j] = double((long long)(st[1 + 2 * j] - st[0])) * b->tick_ms;
-    if (end_ms) end_ms[j] = double((long long)(st[2 + 2 * j] - st[0])) * b->tick_ms;
+    if (end_ms) end_ms[j] = double((long long)(st[e] - st[0])) * b->tick_ms;
   }
 }
 
@@ -2419,6 +2863,29 @@ tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *con
   });
 }
 
+tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
+                               const uint64_t *out_bytes, const tqc_multi_options *opt, void *stream,
+                               tqc_multi_t *out) {
+  return guarded([&] {
+    if (!out || !opt) fail(TQC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    Multi *m = create_multi(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, opt->use_graph,
+                            opt->num_streams, opt->timed, (hipStream_t)stream, opt->batched_final);
+    *out = reinterpret_cast<tqc_multi_t>(static_cast<tqc_multi_s *>(m));
+  });
+}
+
+tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *batched_jobs, int32_t *batched_launches) {
+  return guarded([&] {
+    if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
+    const Multi *m = static_cast<Multi *>(multi);
+    int32_t n = 0;
+    for (int c : m->class_of) n += c >= 0 ? 1 : 0;
+    if (batched_jobs) *batched_jobs = n;
+    if (batched_launches) *batched_launches = (int32_t)m->classes.size();
+  });
+}
+
 tqc_status tqc_multi_execute(tqc_multi_t multi, void *stream) {
   return guarded([&] {
     if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
@@ -2449,6 +2916,22 @@ tqc_status tqc_batch_create(int32_t num_jobs, const tqc_plan_t *plans, void *con
     Batch *b = create_batch(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, o,
                             (hipStream_t)stream);
     *out = reinterpret_cast<tqc_batch_t>(b);
+  });
+}
+
+tqc_status tqc_batch_validate(int32_t num_jobs, const tqc_plan_t *plans, const uint64_t *out_bytes,
+                              char *report, uint64_t report_cap) {
+  return guarded([&] {
+    if (num_jobs < 1 || !plans) fail(TQC_ERR_INVALID_ARG, "no jobs");
+    for (int j = 0; j < num_jobs; ++j)
+      if (!plans[j]) fail(TQC_ERR_INVALID_ARG, "job %d: null plan", j);
+    const std::string r = batch_emulate(num_jobs, reinterpret_cast<Plan *const *>(plans), out_bytes, 1ull << 32);
+    if (report && report_cap) {
+      const size_t n = std::min<size_t>(r.size(), report_cap - 1);
+      std::memcpy(report, r.data(), n);
+      report[n] = 0;
+    }
+    if (!r.empty()) fail(TQC_ERR_INTERNAL, "batch emulation: %s", r.c_str());
   });
 }
 

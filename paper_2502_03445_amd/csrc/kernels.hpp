@@ -38,6 +38,18 @@ hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s);
 // when the step does not qualify
 bool root_gemm_eligible(int prec, const GemmArgs &g);
 hipError_t launch_root_gemm(int prec, const GemmArgs &g, hipStream_t s);
+// the persistent final step of many reconstructions in one launch: one
+// record per job (arguments prepared for 128 x 128 tiles, tile counts),
+// all of one form and one kpad (4..8), each job eligible as above;
+// blocks_per_job workgroups per job (a multiple of 8), jobs on grid y
+struct RootJob {
+  GemmArgs g;
+  uint32_t ntiles;
+  int lgtm, lgtn;
+};
+RootJob make_root_job(int prec, const GemmArgs &g);
+hipError_t launch_root_multi(int prec, int kpad, const RootJob *jobs, int njobs, int blocks_per_job,
+                             hipStream_t s);
 
 // output forms
 hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,

@@ -91,8 +91,17 @@ __device__ inline uint64_t wave_or(uint64_t v) {
   return v;
 }
 
-template <int P, int KP, bool STATS>
-__global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t ntiles, int lgtm, int lgtn) {
+// MULTI: one launch for the final steps of many reconstructions that share
+// the form and K; blockIdx.y selects the job, whose arguments and tile
+// counts come from a device table, and blockIdx.x plays the role of the
+// workgroup id of a single-job launch of gridDim.x workgroups.
+template <int P, int KP, bool STATS, bool MULTI>
+__global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g_in, uint32_t ntiles_in, int lgtm_in, int lgtn_in,
+                                                        const RootJob *jobs) {
+  const GemmArgs &g = MULTI ? jobs[blockIdx.y].g : g_in;
+  const uint32_t ntiles = MULTI ? jobs[blockIdx.y].ntiles : ntiles_in;
+  const int lgtm = MULTI ? jobs[blockIdx.y].lgtm : lgtm_in;
+  const int lgtn = MULTI ? jobs[blockIdx.y].lgtn : lgtn_in;
   using RT = RootTraits<P>;
   using Frag = typename RT::Frag;
   constexpr int KG = RT::KG, NP = RT::NP, ES = RT::ES;
@@ -484,11 +493,36 @@ __global__ void __launch_bounds__(512) root_gemm_kernel(GemmArgs g, uint32_t nti
 template <int P, int KP>
 hipError_t launch_root_kp(const GemmArgs &g, uint32_t ntiles, int lgtn, int grid, hipStream_t s) {
   const int lgtm = g.lm - 7;
+  const RootJob *none = nullptr;
   if (g.tkey)
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, true, false>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn,
+                       none);
   else
-    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn);
+    hipLaunchKernelGGL((root_gemm_kernel<P, KP, false, false>), dim3(grid), dim3(512), 0, s, g, ntiles, lgtm, lgtn,
+                       none);
   return hipGetLastError();
+}
+
+template <int P, int KP>
+hipError_t launch_root_multi_kp(const RootJob *jobs, int njobs, int blocks_per_job, hipStream_t s) {
+  GemmArgs unused{};
+  hipLaunchKernelGGL((root_gemm_kernel<P, KP, false, true>), dim3(blocks_per_job, njobs), dim3(512), 0, s, unused,
+                     0u, 0, 0, jobs);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_root_multi_p(int kpad, const RootJob *jobs, int njobs, int blocks_per_job, hipStream_t s) {
+  switch (kpad) {
+    case 4:
+      if constexpr (P == 1) return launch_root_multi_kp<P, 16>(jobs, njobs, blocks_per_job, s);
+      return hipErrorNotSupported;
+    case 5: return launch_root_multi_kp<P, 32>(jobs, njobs, blocks_per_job, s);
+    case 6: return launch_root_multi_kp<P, 64>(jobs, njobs, blocks_per_job, s);
+    case 7: return launch_root_multi_kp<P, 128>(jobs, njobs, blocks_per_job, s);
+    case 8: return launch_root_multi_kp<P, 256>(jobs, njobs, blocks_per_job, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 template <int P>
@@ -529,6 +563,28 @@ bool root_gemm_eligible(int prec, const GemmArgs &g) {
   GemmArgs h = g;
   prepare_gemm_args(h, prec, kRT, kRT);
   return h.staged && h.vec4 && h.ncompact == 14;
+}
+
+RootJob make_root_job(int prec, const GemmArgs &g_in) {
+  RootJob j{};
+  j.g = g_in;
+  prepare_gemm_args(j.g, prec, kRT, kRT);
+  j.lgtm = j.g.lm - 7;
+  j.lgtn = j.g.ln - 7;
+  j.ntiles = 1u << (j.lgtm + j.lgtn);
+  return j;
+}
+
+hipError_t launch_root_multi(int prec, int kpad, const RootJob *jobs, int njobs, int blocks_per_job,
+                             hipStream_t s) {
+  if (njobs < 1 || njobs > 65535 || blocks_per_job < 8 || (blocks_per_job & 7)) return hipErrorInvalidValue;
+  switch (prec) {
+    case 1: return launch_root_multi_p<1>(kpad, jobs, njobs, blocks_per_job, s);
+    case 2: return launch_root_multi_p<2>(kpad, jobs, njobs, blocks_per_job, s);
+    case 3: return launch_root_multi_p<3>(kpad, jobs, njobs, blocks_per_job, s);
+    case 4: return launch_root_multi_p<4>(kpad, jobs, njobs, blocks_per_job, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 hipError_t launch_root_gemm(int prec, const GemmArgs &g_in, hipStream_t s) {

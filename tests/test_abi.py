@@ -195,3 +195,32 @@ def test_plan_workspace_query_covers_the_plan():
     assert L.tqc_topk_workspace_bytes(10, 11, ctypes.byref(n)) == 1
     assert L.tqc_marginal_workspace_bytes(20, 3, ctypes.byref(n)) == 0 and n.value > 0
     assert L.tqc_marginal_workspace_bytes(20, 25, ctypes.byref(n)) == 1
+
+
+# ----------------------------------------- batch launch emulated on the host
+def _batch_jobs(form):
+    from workloads import configs
+    specs = [configs.config1(), configs.ghz(12, 3), configs.aqft(10, 3, 2),
+             configs.random_cut_circuit(9, 3, 4, 3, 4)]
+    for i, (m, K, outs) in enumerate([(2, 3, [7, 8]), (3, 4, [4, 5, 5]), (4, 6, [3, 3, 3, 4]),
+                                      (5, 7, [2, 3, 3, 2, 3]), (1, 0, [9]), (3, 2, [0, 6, 6]),
+                                      (2, 2, [10, 9]), (4, 5, [2, 4, 4, 4])]):
+        specs.append(synthetic.random_network(m, K, outs, seed=500 + i))
+    dt = "f64" if form == "fp64" else "f32"
+    return [tqc.Plan(tqc.Network.from_spec(s), precision=form, out_dtype=dt) for s in specs]
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6", "fp64"])
+def test_batch_launch_emulation_finds_every_access_in_bounds(form):
+    """The twelve jobs of the GPU batch tests: every pre-pass and item access
+    inside its buffer, loops bounded, levels and dependencies ordered."""
+    plans = _batch_jobs(form)
+    assert tqc.batch_validate(plans) == ""
+
+
+def test_batch_launch_emulation_catches_an_undersized_output():
+    plans = _batch_jobs("fp32")
+    need = [p.out_entries * 4 for p in plans]
+    need[3] -= 4
+    rep = tqc.batch_validate(plans, need)
+    assert "job 3 output" in rep, rep

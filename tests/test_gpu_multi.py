@@ -126,3 +126,50 @@ def test_generated_batch_jobs_match_oracle(form, rtol):
         bound = rtol * np.abs(ref).max()
         assert np.abs(got[xs.astype(np.int64)] - ref).max() <= bound, (i, spec.num_cuts)
         assert abs(got.sum() - 1.0) <= 1e-4
+
+
+# ------------------------------------------- final steps in shared launches
+@pytest.mark.parametrize("form,use_graph", [("fp32", True), ("fp32", False), ("bf16x3", True),
+                                            ("bf16x6", True), ("fp16x3", False)])
+def test_batched_final_steps_equal_plain_execution(form, use_graph):
+    """The jobs whose final step runs on the persistent kernel leave it to one
+    shared launch per (form, K); every output still equals the plan's own
+    execution bit for bit, also over graph replays."""
+    specs, nets, plans = jobs(form)
+    plain = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=use_graph, streams=4, timed=True, batched_final=True)
+    nb, nl = mj.info()
+    assert nb >= 3 and 1 <= nl <= nb, (nb, nl)
+    for rep in range(3):
+        for o in mj.outs:
+            o.fill_(-7.0)
+        mj.execute()
+        torch.cuda.synchronize()
+        for i, (o, ref_gpu) in enumerate(zip(mj.outs, plain)):
+            assert torch.equal(o, ref_gpu), (rep, i)
+        st, en = mj.job_times()
+        assert np.all(st >= 0) and np.all(en >= st), rep
+    for spec, o in zip(specs, mj.outs):
+        ref = full_distribution(spec)
+        assert np.abs(o.double().cpu().numpy() - ref).max() <= tol(form, ref)
+
+
+def test_batched_final_steps_of_many_shapes_and_ks():
+    """Forty final steps of different shapes (2^7..2^11 rows and columns) and
+    K = 16..256 in float32: grouped into one launch per K, each output equal
+    to its plan's own execution."""
+    rng = np.random.default_rng(77)
+    specs = []
+    for i in range(40):
+        K = int(rng.integers(2, 5))
+        outs = [int(rng.integers(7, 12)), int(rng.integers(7, 12))]
+        specs.append(synthetic.random_network(2, K, outs, seed=1900 + i))
+    plans = [tqc.Plan(tqc.Network.from_spec(s), precision="fp32") for s in specs]
+    plain = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=True, streams=4, batched_final=True)
+    nb, nl = mj.info()
+    assert nb == 40 and nl == len({p.steps[-1]["log2_k"] for p in plans}), (nb, nl)
+    mj.execute()
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(mj.outs, plain)):
+        assert torch.equal(o, r), i
