@@ -324,6 +324,21 @@ tqc_status tqc_marginal(const void *probs, tqc_dtype dtype, int32_t num_qubits,
  * Errors: as tqc_topk / tqc_marginal, plus SHAPE (workspace too small) and
  * INVALID_ARG (workspace NULL or misaligned). */
 tqc_status tqc_topk_workspace_bytes(uint64_t len, int32_t k, uint64_t *bytes);
+
+/* tqc_topk for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as tqc_topk, bit for bit, with their scratch in
+ * a fixed 8 MiB device array that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates and frees nothing.  That
+ * covers len <= 2^32 for every k <= 4096; a longer vector is rejected with
+ * INVALID_ARG before any device work.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (two streams, or two host
+ * threads) race and give wrong results; one call after another on a stream,
+ * or with the stream synchronized in between, is safe.  The kernels
+ * initialize every scratch entry they read, so nothing needs clearing.
+ * Errors: as tqc_topk, plus DEVICE (the array's address cannot be found). */
+tqc_status tqc_topk_noalloc(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
+                            uint64_t *idx_out, double *val_out, void *stream);
 tqc_status tqc_topk_ws(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
                        uint64_t *idx_out, double *val_out, void *workspace, uint64_t ws_bytes,
                        void *stream);

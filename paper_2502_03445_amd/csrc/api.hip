@@ -185,6 +185,30 @@ static void check_device(int want) {
 // --------------------------------------------------------------- execute
 static TransformArgs make_transform_args(const TensorIn &t, double *out);
 
+// ------------------------------------------------- allocation-free top-k
+// Scratch of tqc_topk_noalloc: a fixed device array, present on every GPU
+// the library runs on for the life of the process.  Host code never uses
+// the array's name as an address: the device address is looked up once per
+// device with hipGetSymbolAddress and kept.
+constexpr uint64_t kNoAllocScratchBytes = 8ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[64] = {};
+
+static void *noalloc_scratch() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(TQC_ERR_UNSUPPORTED, "device %d", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(TQC_ERR_DEVICE, "no device address for the top-k scratch on device %d", dev);
+    g_noalloc_ptr[dev] = ptr;
+  }
+  return g_noalloc_ptr[dev];
+}
+
 // ---------------------------------------------------------- scratch
 // Library-owned scratch of the calls that take no workspace argument
 // (tqc_topk, tqc_marginal, tqc_network_pauli_tensor, heavy state selection,
@@ -2704,6 +2728,19 @@ tqc_status tqc_topk(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k,
     ScratchLease lease = stream_scratch(sb, (hipStream_t)stream);
     HIP_OK(launch_topk(probs, dtype == TQC_F32 ? 1 : 0, len, k, idx_out, val_out, lease.ptr, sb,
                        (hipStream_t)stream));
+  });
+}
+
+tqc_status tqc_topk_noalloc(const void *probs, tqc_dtype dtype, uint64_t len, int32_t k, uint64_t *idx_out,
+                            double *val_out, void *stream) {
+  return guarded([&] {
+    check_topk_args(probs, dtype, len, k, idx_out, val_out);
+    const uint64_t sb = topk_scratch_bytes(len, k);
+    if (sb > kNoAllocScratchBytes)
+      fail(TQC_ERR_INVALID_ARG, "top-k of %llu entries needs %llu scratch bytes; the fixed scratch holds %llu",
+           (unsigned long long)len, (unsigned long long)sb, (unsigned long long)kNoAllocScratchBytes);
+    void *ptr = noalloc_scratch();
+    HIP_OK(launch_topk(probs, dtype == TQC_F32 ? 1 : 0, len, k, idx_out, val_out, ptr, sb, (hipStream_t)stream));
   });
 }
 
