@@ -238,7 +238,13 @@ def _pcts(x):
             "max": float(np.max(x)), "mean": float(np.mean(x))}
 
 
-def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
+BATCH_MODES = {"graph_4streams": dict(use_graph=True, streams=4),
+               "graph_8streams": dict(use_graph=True, streams=8),
+               "graph_grouped": dict(use_graph=True, grouped=True),
+               "sequential_plain": dict(use_graph=False, streams=1)}
+
+
+def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5, modes=tuple(BATCH_MODES)):
     """Batched execution of uneven reconstructions: num_jobs seeded cut
     circuits (n uniform in 16..28 qubits, 2..5 subcircuits, 2..10 cuts, line
     or grid layouts, exact subcircuit tensors) with autotuned tiles, run as one
@@ -288,11 +294,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
     outs = [p.output_tensor() for p in plans]
     runs = {}
     probs = float(sum(o.numel() for o in outs))
-    for name, kw in (("graph_4streams", dict(use_graph=True, streams=4)),
-                     ("graph_8streams", dict(use_graph=True, streams=8)),
-                     ("graph_8streams_batched_final", dict(use_graph=True, streams=8, batched_final=True)),
-                     ("graph_4streams_batched_final", dict(use_graph=True, streams=4, batched_final=True)),
-                     ("sequential_plain", dict(use_graph=False, streams=1))):
+    for name in modes:
+        kw = BATCH_MODES[name]
         mj = tqc.Multi(plans, outs=outs, **kw)
         timed = tqc.Multi(plans, outs=outs, timed=True, **kw)
         mj.execute()
@@ -313,7 +316,9 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
                       "jobs_per_s": num_jobs / batch_ms * 1e3, "probs_per_s": probs / batch_ms * 1e3,
                       "per_job_ms": _pcts(en - st), "completion_ms": _pcts(en),
                       "timed_batch_ms": float(en.max()),
-                      "final_steps_in_shared_launches": mj.info()[0], "shared_launches": mj.info()[1]}
+                      "launches_per_batch": mj.info()[0], "final_steps_in_shared_launches": mj.info()[1],
+                      "shared_final_launches": mj.info()[2],
+                      "tile0_roots": sum(1 for p in plans if p.steps and p.steps[-1]["tile"] == 0)}
         print(f"# {name}: {batch_ms:.3f} ms per batch", file=sys.stderr, flush=True)
         del mj, timed
     # every output equals the job's own plain execution
@@ -328,12 +333,8 @@ def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5):
             "form": form, "jobs": num_jobs, "distribution": dist, "generation_s": gen_s,
             "autotune": {"plans_tuned": ntuned, "step_shapes": len(tuned), "seconds": tune_s},
             "runs": runs,
-            "speedup_graph_over_sequential": runs["sequential_plain"]["batch_ms"] /
-                                             runs["graph_4streams"]["batch_ms"],
-            "speedup_graph8_over_sequential": runs["sequential_plain"]["batch_ms"] /
-                                              runs["graph_8streams"]["batch_ms"],
-            "speedup_batched_final_over_sequential": runs["sequential_plain"]["batch_ms"] /
-                                                     runs["graph_8streams_batched_final"]["batch_ms"],
+            "speedup_over_sequential": {k: runs["sequential_plain"]["batch_ms"] / v["batch_ms"]
+                                        for k, v in runs.items()} if "sequential_plain" in runs else None,
             "outputs_equal_plain_execution": same,
             "largest_jobs": sorted(meta, reverse=True)[:3]}
 
@@ -518,6 +519,8 @@ def main():
                          "prior-method / tensor-network multiplication ratio (host only), or the "
                          "cut search with the runtime model of Eqs. (6)-(8)")
     ap.add_argument("--jobs", type=int, default=512, help="jobs of the batch study")
+    ap.add_argument("--batch-modes", default=",".join(BATCH_MODES),
+                    help="executor variants of the batch study: " + ", ".join(BATCH_MODES))
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle check (profiling runs): errors are reported as null")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -550,7 +553,8 @@ def main():
         return
     if args.study == "batch":
         for form in args.forms.split(","):
-            print(json.dumps(batch_study(tqc, torch, form, num_jobs=args.jobs)), flush=True)
+            print(json.dumps(batch_study(tqc, torch, form, num_jobs=args.jobs,
+                                         modes=tuple(args.batch_modes.split(",")))), flush=True)
             torch.cuda.empty_cache()
         return
 

@@ -441,27 +441,34 @@ typedef struct tqc_multi_s *tqc_multi_t;
 tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams,
                             int32_t timed, void *stream, tqc_multi_t *out);
-/* As tqc_multi_create, with options.  batched_final = 1: every job whose
- * final pairwise step (the one that writes its 2^n output) runs on the
- * persistent final-step kernel (float32 output, K <= 256, at least 2^7
- * rows and columns) leaves that step out of its own launches; after all
- * jobs' other launches, one persistent launch per (form, K) runs those final
- * steps for all such jobs, each job on a row of the launch grid with a
- * device table of the jobs' step records (most tiles first).  The
- * arithmetic per output entry is unchanged, so results still equal
- * tqc_execute's bit for bit.  With timed = 1 such a job's end time is the
- * end of its shared launch.  tqc_multi_info reports how many jobs were
- * batched so and in how many launches. */
+/* As tqc_multi_create, with options.  grouped = 1: the jobs' work runs as
+ * a short list of shared launches on `stream` (one graph with use_graph)
+ * instead of each job's own launches: the Pauli-transform passes of all
+ * jobs level by level, their per-entry transforms, operand scales (zero,
+ * abs-max, exponents) and leaf packs in one launch each, then the pairwise
+ * steps depth by depth, one launch per kernel variant and depth (a step the
+ * plain launcher would split over k, and the float16 split of a final step,
+ * run alone), and last every final step that runs on the persistent
+ * final-step kernel (float32 output, K <= 256, at least 2^7 rows and
+ * columns): one persistent launch per (form, K), each job on a row of the
+ * launch grid, jobs with the most tiles first.  Each record is the one the
+ * job's own tqc_execute launches and a workgroup of a shared launch runs as
+ * the same workgroup of that launch would, so results equal tqc_execute's
+ * bit for bit.  num_streams is unused in this mode.  With timed = 1 every
+ * job starts with the first launch and ends with the launch that runs its
+ * final step.  tqc_multi_info: launches per execute (-1 unless grouped),
+ * final steps in shared persistent launches, and those launches. */
 typedef struct {
   int32_t use_graph;      /* as tqc_multi_create                          */
   int32_t num_streams;    /* as tqc_multi_create (0 = 4, at most 16)       */
   int32_t timed;          /* as tqc_multi_create                          */
-  int32_t batched_final;  /* 1: final steps in shared persistent launches */
+  int32_t grouped;        /* 1: every kind of work in shared launches     */
 } tqc_multi_options;
 tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                                const uint64_t *out_bytes, const tqc_multi_options *opt, void *stream,
                                tqc_multi_t *out);
-tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *batched_jobs, int32_t *batched_launches);
+tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *launches, int32_t *shared_root_jobs,
+                          int32_t *shared_root_launches);
 tqc_status tqc_multi_execute(tqc_multi_t multi, void *stream);
 tqc_status tqc_multi_job_times(tqc_multi_t multi, double *start_ms, double *end_ms);
 void tqc_multi_destroy(tqc_multi_t multi);

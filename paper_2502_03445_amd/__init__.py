@@ -84,7 +84,7 @@ class BatchOptions(ctypes.Structure):
 
 class MultiOptions(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("timed", ctypes.c_int32),
-                ("batched_final", ctypes.c_int32)]
+                ("grouped", ctypes.c_int32)]
 
 
 class TrainOptions(ctypes.Structure):
@@ -129,7 +129,7 @@ def _declare(L):
         "tqc_multi_execute": [vp, vp],
         "tqc_multi_create_ex": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64),
                                 ctypes.POINTER(MultiOptions), vp, ctypes.POINTER(vp)],
-        "tqc_multi_info": [vp, _i32p, _i32p],
+        "tqc_multi_info": [vp, _i32p, _i32p, _i32p],
         "tqc_hss_select": [vp, u64, _i32p, _i32p, u64, _dp, u64, vp],
         "tqc_find_cuts": [i32, i32, _i32p, i32, i32, i32, ctypes.c_double, _i32p, _i32p],
         "tqc_network_select_states": [vp, _i32p, _i32p, vp, ctypes.POINTER(vp)],
@@ -619,7 +619,7 @@ class Multi:
     Outputs equal each plan's own ``execute`` bit for bit."""
 
     def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None,
-                 batched_final=False):
+                 grouped=False):
         L = lib()
         if outs is None:
             outs = [p.output_tensor() for p in plans]
@@ -633,7 +633,7 @@ class Multi:
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
         ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
         h = ctypes.c_void_p()
-        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(batched_final)))
+        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(grouped)))
         _check(L.tqc_multi_create_ex(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 
@@ -641,10 +641,11 @@ class Multi:
         _check(lib().tqc_multi_execute(self.handle, _stream_ptr(stream)))
 
     def info(self):
-        """(jobs whose final step runs in a shared launch, shared launches)."""
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().tqc_multi_info(self.handle, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(launches per execute in grouped mode, else -1; final steps in
+        shared persistent launches; those launches)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tqc_multi_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def job_times(self):
         """(start_ms, end_ms) per job, from the start of the last execute."""

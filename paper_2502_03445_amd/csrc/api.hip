@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <numeric>
@@ -407,10 +408,9 @@ static ScaleBuf scale_buffers(Plan *p) {
                   (unsigned long long *)(b + 16)};
 }
 
-static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
+static std::vector<AbsMaxArgs> absmax_records(Plan *p, const ScaleBuf &sb) {
   Network &net = *p->net;
   const int m = net.m;
-  HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
   std::vector<AbsMaxArgs> all(m);
   for (int j = 0; j < m; ++j) {
     const TensorIn &t = net.t[j];
@@ -438,8 +438,15 @@ static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
     std::sort(a.inpos, a.inpos + a.nbits);
     all[j] = a;
   }
+  return all;
+}
+
+static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
+  const int m = p->net->m;
+  HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
+  const std::vector<AbsMaxArgs> all = absmax_records(p, sb);
   HIP_OK(launch_absmax(all.data(), m, s));
-  HIP_OK(launch_scale_exponents(sb.maxbits, m, net.K, sb.exps, sb.root_scale, s));
+  HIP_OK(launch_scale_exponents(sb.maxbits, m, p->net->K, sb.exps, sb.root_scale, s));
 }
 
 static TransformArgs make_transform_args(const TensorIn &t, double *out) {
@@ -1588,9 +1595,19 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
     for (int tile = 0; tile < 3; ++tile) {
       const int bm = tile_bm(tile);
       if (tile != 2 && (st.lm < 5 || st.ln < 5) && bm > 32) continue;
-      HIP_OK(launch_gemm(step_prec(p, st), g, tile, s));  // warm
+      // time the step as execute runs it: a final step with tile 0 that
+      // qualifies runs on the persistent final-step kernel
+      Step trial = st;
+      trial.tile = tile;
+      const int sp = step_prec(p, st);
+      const bool persistent = root_on_persistent(p, trial, g);
+      auto run = [&]() {
+        if (persistent) HIP_OK(launch_root_gemm(sp, g, s));
+        else HIP_OK(launch_gemm(sp, g, tile, s));
+      };
+      run();  // warm
       HIP_OK(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) HIP_OK(launch_gemm(step_prec(p, st), g, tile, s));
+      for (int r = 0; r < reps; ++r) run();
       HIP_OK(hipEventRecord(e1, s));
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0;
@@ -1771,25 +1788,24 @@ struct Multi {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t fork = nullptr;
-  std::vector<hipEvent_t> join;
+  std::vector<hipEvent_t> join, mid;
   hipStream_t last_stream = nullptr;
   bool ran = false;
-  // batched final steps: jobs whose final step runs on the persistent
-  // kernel are grouped by (form, kpad); each group is one launch over a
-  // device table of the jobs' final-step records, after every job's
-  // earlier launches
-  struct RootClass {
-    int prec, kpad, count, blocks;
-    uint64_t first;  // first record in root_tab
-  };
-  std::vector<RootClass> classes;
-  std::vector<int> class_of;      // job -> class (-1: its final step runs with the job)
-  RootJob *root_tab = nullptr;
+  // grouped mode: the work of all jobs as a short list of shared launches
+  // (built at creation, replayed by each execute); stamp slot of each step
+  // and, per job, the step that completes it
+  bool grouped = false;
+  std::vector<std::function<void(hipStream_t)>> gsteps;
+  std::vector<int> done_at;       // job -> index of its completing step
+  int shared_roots = 0;           // persistent final-step launches
+  int shared_root_jobs = 0;       // jobs whose final step runs in one of them
+  void *gtab = nullptr;           // device tables of the grouped launches
   ~Multi() {
-    if (root_tab) (void)hipFree(root_tab);
+    if (gtab) (void)hipFree(gtab);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto e : join) (void)hipEventDestroy(e);
+    for (auto e : mid) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     for (auto st : streams) (void)hipStreamDestroy(st);
     if (cap) (void)hipStreamDestroy(cap);
@@ -1797,8 +1813,340 @@ struct Multi {
   }
 };
 
+// ----------------------------------------------------------- grouped mode
+// The launches one single-slice execute makes (run_slices), as records:
+// transform passes by pass level, per-entry transforms, the operand scales
+// (zero, abs-max, exponents), the leaf packs, and the pairwise steps with
+// their depth in the contraction tree (1 + the deeper operand's depth).
+struct JobOps {
+  std::vector<std::vector<TransformPassArgs>> pass_levels;
+  std::vector<TransformArgs> transforms;
+  bool scaled = false;  // m >= 2: zero / abs-max / exponents
+  ZeroRec zero{};
+  std::vector<AbsMaxArgs> absmax;
+  ScaleRec scale{};
+  std::vector<PackArgs> packs;
+  struct GemmOp {
+    GemmArgs g;
+    int sp, tile, depth;
+    bool root, persistent;
+  };
+  std::vector<GemmOp> gemms;
+  // float16-split plans: the split of the final step's operands
+  bool f16 = false;
+  const float *f16_src[2] = {nullptr, nullptr};
+  uint64_t f16_n[2] = {0, 0};
+  uint16_t *f16_hi[2] = {nullptr, nullptr}, *f16_lo[2] = {nullptr, nullptr};
+  unsigned long long *f16_max = nullptr;
+  const double *f16_rs = nullptr;
+  double *f16_rs2 = nullptr;
+};
+
+static JobOps job_ops(Plan *p, void *out) {
+  JobOps o;
+  Network &net = *p->net;
+  const int m = net.m;
+  const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+  for (int j = 0; j < m; ++j) {
+    TensorIn &t = net.t[j];
+    if (t.basis != TQC_BASIS_RAW) continue;
+    if ((int)t.cuts.size() >= kPassMinCuts) {
+      char *b = (char *)p->ws + p->tscr_off[j];
+      schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], o.pass_levels);
+    } else {
+      o.transforms.push_back(make_transform_args(t, t.dev_pauli));
+    }
+  }
+  if (m == 1) {
+    o.packs.push_back(make_pack_args(p, 0, out, nullptr, nullptr, root_kind == OUT_F64 ? 0 : 1, 0));
+    return o;
+  }
+  const ScaleBuf sb = scale_buffers(p);
+  o.scaled = true;
+  o.zero = ZeroRec{sb.maxbits, (uint64_t)m};
+  o.absmax = absmax_records(p, sb);
+  o.scale = ScaleRec{sb.maxbits, m, net.K, sb.exps, sb.root_scale};
+  for (int j = 0; j < m; ++j) {
+    Node &nd = p->nodes[j];
+    char *b = (char *)p->ws + nd.offset;
+    o.packs.push_back(make_pack_args(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
+                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pack_prec(p), 0, sb.exps + j));
+  }
+  std::vector<int> depth(p->nodes.size(), 0);
+  for (const Step &st : p->steps) {
+    depth[st.out] = 1 + std::max(depth[st.a], depth[st.b]);
+    JobOps::GemmOp op;
+    op.g = make_gemm_args(p, st, out, root_kind, sb.root_scale);
+    op.sp = step_prec(p, st);
+    op.tile = st.tile;
+    op.depth = depth[st.out];
+    op.root = st.root;
+    op.persistent = root_on_persistent(p, st, op.g);
+    if (st.root && p->prec == Prec::F16X3) {
+      const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
+      char *ha = (char *)p->ws + p->h16_off[0], *hb = (char *)p->ws + p->h16_off[1];
+      o.f16 = true;
+      o.f16_src[0] = (const float *)((char *)p->ws + na.offset);
+      o.f16_src[1] = (const float *)((char *)p->ws + nb.offset);
+      o.f16_n[0] = na.elems();
+      o.f16_n[1] = nb.elems();
+      o.f16_hi[0] = (uint16_t *)ha;
+      o.f16_lo[0] = (uint16_t *)(ha + p->h16_plane[0]);
+      o.f16_hi[1] = (uint16_t *)hb;
+      o.f16_lo[1] = (uint16_t *)(hb + p->h16_plane[1]);
+      o.f16_max = sb.maxbits16;
+      o.f16_rs = sb.root_scale;
+      o.f16_rs2 = sb.root_scale2;
+    }
+    o.gemms.push_back(op);
+  }
+  return o;
+}
+
+// Device tables of the grouped launches, laid out in one allocation.
+struct TableArena {
+  std::vector<unsigned char> host;
+  uint64_t add(const void *p, uint64_t bytes) {
+    const uint64_t off = (host.size() + 255) & ~uint64_t(255);
+    host.resize(off + bytes);
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+  template <typename T>
+  uint64_t add_vec(const std::vector<T> &v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+// A grouped launch over records of one kind: the records' own workgroup
+// counts become the first-workgroup offsets.
+template <typename T>
+struct Group {
+  std::vector<T> recs;
+  std::vector<uint32_t> first{0};
+  void push(const T &r, uint32_t blocks) {
+    recs.push_back(r);
+    const uint64_t next = (uint64_t)first.back() + blocks;
+    if (next > 0x7fffffffull) fail(TQC_ERR_UNSUPPORTED, "grouped launch of more than 2^31 workgroups");
+    first.push_back((uint32_t)next);
+  }
+  bool empty() const { return recs.empty(); }
+};
+
+// The whole batch as a short list of launches on one stream: pass levels,
+// per-entry transforms, scales (zero, abs-max, exponents), packs, then the
+// pairwise steps depth by depth (one launch per kernel variant and depth;
+// steps the plain launcher would split over k run alone, with that split;
+// float16 splits before their final step), and last the final steps that run
+// on the persistent kernel, one launch per (form, K).  Every record is the
+// one the job's own execute would launch, so outputs match bit for bit.
+static void build_grouped(Multi *b) {
+  b->grouped = true;
+  const int njobs = (int)b->plans.size();
+  std::vector<JobOps> ops(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    if (b->plans[j]->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not grouped", j);
+    // points the network's Pauli tensors into this plan's workspace (jobs
+    // may share a network); the workspace itself exists already
+    ensure_workspace(b->plans[j], nullptr);
+    ops[j] = job_ops(b->plans[j], b->outs[j]);
+  }
+  TableArena A;
+  // each planned launch: a closure over device pointers resolved after the
+  // tables are uploaded
+  std::vector<std::function<std::function<void(hipStream_t)>(char *)>> plan;
+  std::vector<std::vector<int>> completes;  // jobs each launch completes
+  auto add_launch = [&](std::function<std::function<void(hipStream_t)>(char *)> f, std::vector<int> jobs = {}) {
+    plan.push_back(std::move(f));
+    completes.push_back(std::move(jobs));
+  };
+  // 1. transform passes, level by level, then per-entry transforms
+  size_t nlev = 0;
+  for (auto &o : ops) nlev = std::max(nlev, o.pass_levels.size());
+  for (size_t L = 0; L < nlev; ++L) {
+    Group<TransformPassArgs> g;
+    for (auto &o : ops)
+      if (L < o.pass_levels.size())
+        for (auto &a : o.pass_levels[L]) {
+          if (a.nseg < 1 || a.nseg > kPassSegs || a.g < 1 || a.g > 2) fail(TQC_ERR_INTERNAL, "transform pass record");
+          g.push(a, grouped_pass_blocks(a));
+        }
+    if (g.empty()) continue;
+    const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+    const int n = (int)g.recs.size();
+    const uint32_t blocks = g.first.back();
+    add_launch([=](char *d) {
+      return [=](hipStream_t s) {
+        HIP_OK(launch_grouped_passes((const TransformPassArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
+      };
+    });
+  }
+  {
+    Group<TransformArgs> g;
+    for (auto &o : ops)
+      for (auto &a : o.transforms) g.push(a, grouped_transform_blocks(a));
+    if (!g.empty()) {
+      const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+      const int n = (int)g.recs.size();
+      const uint32_t blocks = g.first.back();
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) {
+          HIP_OK(launch_grouped_transforms((const TransformArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
+        };
+      });
+    }
+  }
+  // 2. scales
+  {
+    std::vector<ZeroRec> zr;
+    std::vector<ScaleRec> sr;
+    Group<AbsMaxArgs> g;
+    for (auto &o : ops) {
+      if (!o.scaled) continue;
+      zr.push_back(o.zero);
+      sr.push_back(o.scale);
+      for (auto &a : o.absmax) g.push(a, grouped_absmax_blocks(a));
+    }
+    if (!zr.empty()) {
+      const uint64_t zo = A.add_vec(zr), so = A.add_vec(sr), ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+      const int nz = (int)zr.size(), n = (int)g.recs.size();
+      const uint32_t blocks = g.first.back();
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) { HIP_OK(launch_grouped_zero((const ZeroRec *)(d + zo), nz, s)); };
+      });
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) {
+          HIP_OK(launch_grouped_absmax((const AbsMaxArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
+        };
+      });
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) { HIP_OK(launch_grouped_scales((const ScaleRec *)(d + so), nz, s)); };
+      });
+    }
+  }
+  // 3. packs (a single-tensor job's pack is its whole result)
+  {
+    Group<PackArgs> g;
+    std::vector<int> done;
+    for (int j = 0; j < njobs; ++j) {
+      for (auto &a : ops[j].packs) g.push(a, grouped_pack_blocks(a));
+      if (b->plans[j]->net->m == 1) done.push_back(j);
+    }
+    if (!g.empty()) {
+      const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+      const int n = (int)g.recs.size();
+      const uint32_t blocks = g.first.back();
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) {
+          HIP_OK(launch_grouped_packs((const PackArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
+        };
+      }, done);
+    }
+  }
+  // 4. pairwise steps by depth; persistent final steps collected for the end
+  int maxd = 0;
+  for (auto &o : ops)
+    for (auto &op : o.gemms) maxd = std::max(maxd, op.depth);
+  std::map<std::pair<int, int>, std::vector<std::pair<int, RootJob>>> roots;
+  for (int dpt = 1; dpt <= maxd; ++dpt) {
+    // float16 splits of final steps at this depth come first
+    for (int j = 0; j < njobs; ++j) {
+      const JobOps &o = ops[j];
+      if (!o.f16) continue;
+      bool here = false;
+      for (auto &op : o.gemms) here |= op.root && op.depth == dpt;
+      if (!here) continue;
+      add_launch([o](char *) {
+        return [o](hipStream_t s) {
+          HIP_OK(launch_f16_split(o.f16_src[0], o.f16_n[0], o.f16_hi[0], o.f16_lo[0], o.f16_src[1], o.f16_n[1],
+                                  o.f16_hi[1], o.f16_lo[1], o.f16_max, o.f16_rs, o.f16_rs2, s));
+        };
+      });
+    }
+    std::map<GemmClass, std::pair<Group<GemmArgs>, std::vector<int>>> classes;
+    for (int j = 0; j < njobs; ++j)
+      for (auto &op : ops[j].gemms) {
+        if (op.depth != dpt) continue;
+        if (op.persistent) {
+          roots[{op.sp, op.g.kpad}].push_back({j, make_root_job(op.sp, op.g)});
+          continue;
+        }
+        const GemmClass c = gemm_class(op.sp, op.g, op.tile);
+        if (c.ksplit) {
+          // split over k as in the job's own launch (float64 partials in its
+          // workspace), so this step runs alone
+          const GemmArgs g = op.g;
+          const int sp = op.sp, tile = op.tile;
+          add_launch([=](char *) {
+            return [=](hipStream_t s) { HIP_OK(launch_gemm(sp, g, tile, s)); };
+          }, op.root ? std::vector<int>{j} : std::vector<int>{});
+          continue;
+        }
+        GemmArgs g = op.g;
+        const int bm = tile_bm(op.tile);
+        prepare_gemm_args(g, op.sp, bm, bm);
+        g.ksplit = 0;
+        if (c.tiles > 0x7fffffffull) fail(TQC_ERR_UNSUPPORTED, "step of more than 2^31 tiles");
+        auto &slot = classes[c];
+        slot.first.push(g, (uint32_t)c.tiles);
+        if (op.root) slot.second.push_back(j);
+      }
+    for (auto &kv : classes) {
+      const GemmClass c = kv.first;
+      const Group<GemmArgs> &g = kv.second.first;
+      const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+      const int n = (int)g.recs.size();
+      const uint32_t blocks = g.first.back();
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) {
+          HIP_OK(launch_grouped_gemm(c, (const GemmArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
+        };
+      }, kv.second.second);
+    }
+  }
+  // 5. final steps on the persistent kernel: one launch per (form, kpad),
+  // jobs with the most tiles first (their workgroups start first); per job
+  // enough workgroups that the largest job's share per workgroup stays below
+  // twice the launch's share per compute unit
+  const int cus = std::max(1, root_gemm_warm());
+  for (auto &kv : roots) {
+    auto &v = kv.second;
+    std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.second.ntiles > y.second.ntiles; });
+    uint64_t total = 0, most = 0;
+    std::vector<RootJob> tab;
+    std::vector<int> jobs;
+    for (auto &x : v) {
+      total += x.second.ntiles;
+      most = std::max<uint64_t>(most, x.second.ntiles);
+      tab.push_back(x.second);
+      jobs.push_back(x.first);
+    }
+    uint64_t want = (2 * (uint64_t)cus * most + total - 1) / std::max<uint64_t>(total, 1);
+    want = std::min<uint64_t>(std::max<uint64_t>(want, 8), (uint64_t)cus);
+    const int blocks = (int)((want + 7) & ~7ull);
+    const int prec = kv.first.first, kpad = kv.first.second, n = (int)tab.size();
+    if (n > 65535) fail(TQC_ERR_UNSUPPORTED, "more than 65535 final steps in one launch");
+    const uint64_t ro = A.add_vec(tab);
+    add_launch([=](char *d) {
+      return [=](hipStream_t s) { HIP_OK(launch_root_multi(prec, kpad, (const RootJob *)(d + ro), n, blocks, s)); };
+    }, jobs);
+    b->shared_roots += 1;
+    b->shared_root_jobs += n;
+  }
+  // upload the tables, then bind the launches to them
+  if (!A.host.empty()) {
+    HIP_OK(hipMalloc(&b->gtab, A.host.size()));
+    HIP_OK(hipMemcpy(b->gtab, A.host.data(), A.host.size(), hipMemcpyHostToDevice));
+  }
+  b->done_at.assign(njobs, -1);
+  for (size_t i = 0; i < plan.size(); ++i) {
+    b->gsteps.push_back(plan[i]((char *)b->gtab));
+    for (int j : completes[i]) b->done_at[j] = (int)i;
+  }
+  for (int j = 0; j < njobs; ++j)
+    if (b->done_at[j] < 0) fail(TQC_ERR_INTERNAL, "job %d has no completing launch", j);
+}
+
 static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
-                           int use_graph, int nstreams, int timed, hipStream_t s, int batched_final = 0) {
+                           int use_graph, int nstreams, int timed, hipStream_t s, int grouped = 0) {
   if (njobs < 1 || !plans || !outs) fail(TQC_ERR_INVALID_ARG, "no jobs");
   if (nstreams < 0 || nstreams > 16) fail(TQC_ERR_INVALID_ARG, "streams %d (0..16)", nstreams);
   if (nstreams == 0) nstreams = 4;
@@ -1838,54 +2186,13 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
     b->stream_of[j] = k;
     load[k] += cost[j];
   }
-  b->class_of.assign(njobs, -1);
-  if (batched_final) {
-    // the final-step record of every job whose final step runs on the
-    // persistent kernel, exactly as run_slices would launch it
-    std::map<std::pair<int, int>, std::vector<std::pair<int, RootJob>>> groups;
-    for (int j : b->order) {
-      Plan *p = b->plans[j];
-      if (p->net->m < 2) continue;
-      const Step *root = root_step(p);
-      if (!root) continue;
-      const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
-      GemmArgs g = make_gemm_args(p, *root, b->outs[j], root_kind, scale_buffers(p).root_scale);
-      if (!root_on_persistent(p, *root, g)) continue;
-      const int sp = step_prec(p, *root);
-      groups[{sp, g.kpad}].push_back({j, make_root_job(sp, g)});
-    }
-    std::vector<RootJob> tab;
-    const int cus = std::max(1, root_gemm_warm());
-    for (auto &kv : groups) {
-      Multi::RootClass c{kv.first.first, kv.first.second, (int)kv.second.size(), 8, tab.size()};
-      // jobs in launch order (largest first: their workgroups start first);
-      // workgroups per job: enough that the largest job's share per
-      // workgroup stays below twice the class's share per compute unit
-      uint64_t total = 0, most = 0;
-      for (auto &x : kv.second) {
-        total += x.second.ntiles;
-        most = std::max<uint64_t>(most, x.second.ntiles);
-      }
-      uint64_t want = (2 * (uint64_t)cus * most + total - 1) / std::max<uint64_t>(total, 1);
-      want = std::min<uint64_t>(std::max<uint64_t>(want, 8), (uint64_t)cus);
-      c.blocks = (int)((want + 7) & ~7ull);
-      for (auto &x : kv.second) {
-        b->class_of[x.first] = (int)b->classes.size();
-        tab.push_back(x.second);
-      }
-      b->classes.push_back(c);
-    }
-    if (!tab.empty()) {
-      HIP_OK(hipMalloc((void **)&b->root_tab, tab.size() * sizeof(RootJob)));
-      HIP_OK(hipMemcpy(b->root_tab, tab.data(), tab.size() * sizeof(RootJob), hipMemcpyHostToDevice));
-    }
-  }
+  if (grouped) build_grouped(b.get());
   if (b->timed) {
     int khz = 0;
     HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
     if (khz <= 0) fail(TQC_ERR_DEVICE, "device reports no clock rate for timestamps");
     b->tick_ms = 1.0 / khz;
-    const uint64_t nst = 1 + 2 * (uint64_t)njobs + b->classes.size();
+    const uint64_t nst = 1 + 2 * (uint64_t)njobs + b->gsteps.size();
     HIP_OK(hipMalloc((void **)&b->stamps, nst * 8));
     HIP_OK(launch_zero_u64(b->stamps, nst, s));
   }
@@ -1896,31 +2203,33 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
   HIP_OK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   b->join.resize(nstreams);
   for (auto &e : b->join) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  b->mid.resize(nstreams);
+  for (auto &e : b->mid) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return b.release();
 }
 
 // fork from `origin`, every job on its stream (between its two stamps), join
 static void multi_enqueue(Multi *b, hipStream_t origin) {
   if (b->timed) HIP_OK(launch_stamp(b->stamps, origin));
+  if (b->grouped) {
+    // every job starts with the first step; step i's stamp follows it
+    for (size_t i = 0; i < b->gsteps.size(); ++i) {
+      b->gsteps[i](origin);
+      if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * b->plans.size() + i, origin));
+    }
+    return;
+  }
   HIP_OK(hipEventRecord(b->fork, origin));
   for (auto st : b->streams) HIP_OK(hipStreamWaitEvent(st, b->fork, 0));
   for (int j : b->order) {
     hipStream_t st = b->streams[b->stream_of[j]];
-    const bool deferred = b->class_of[j] >= 0;
     if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * j, st));
-    execute(b->plans[j], b->outs[j], b->out_bytes[j], st, nullptr, deferred);
-    if (b->timed && !deferred) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
+    execute(b->plans[j], b->outs[j], b->out_bytes[j], st);
+    if (b->timed) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
   }
   for (size_t k = 0; k < b->streams.size(); ++k) {
     HIP_OK(hipEventRecord(b->join[k], b->streams[k]));
     HIP_OK(hipStreamWaitEvent(origin, b->join[k], 0));
-  }
-  // the deferred final steps, one persistent launch per (form, kpad)
-  const uint64_t cls0 = 1 + 2 * (uint64_t)b->plans.size();
-  for (size_t c = 0; c < b->classes.size(); ++c) {
-    const Multi::RootClass &rc = b->classes[c];
-    HIP_OK(launch_root_multi(rc.prec, rc.kpad, b->root_tab + rc.first, rc.count, rc.blocks, origin));
-    if (b->timed) HIP_OK(launch_stamp(b->stamps + cls0 + c, origin));
   }
 }
 
@@ -1962,12 +2271,14 @@ static void multi_times(Multi *b, double *start_ms, double *end_ms) {
   check_device(b->device);
   HIP_OK(hipStreamSynchronize(b->last_stream));
   const size_t n = b->plans.size();
-  std::vector<unsigned long long> st(1 + 2 * n + b->classes.size());
+  std::vector<unsigned long long> st(1 + 2 * n + b->gsteps.size());
   HIP_OK(hipMemcpy(st.data(), b->stamps, st.size() * 8, hipMemcpyDeviceToHost));
   for (size_t j = 0; j < n; ++j) {
-    // a job whose final step ran in a shared launch ends with that launch
-    const uint64_t e = b->class_of[j] >= 0 ? 1 + 2 * n + b->class_of[j] : 2 + 2 * j;
-    if (start_ms) start_ms[j] = double((long long)(st[1 + 2 * j] - st[0])) * b->tick_ms;
+    // grouped: every job starts with the launch and ends with the shared
+    // launch that runs its final step
+    const uint64_t s0 = b->grouped ? 0 : 1 + 2 * j;
+    const uint64_t e = b->grouped ? 1 + 2 * n + b->done_at[j] : 2 + 2 * j;
+    if (start_ms) start_ms[j] = double((long long)(st[s0] - st[0])) * b->tick_ms;
     if (end_ms) end_ms[j] = double((long long)(st[e] - st[0])) * b->tick_ms;
   }
 }
@@ -2907,19 +3218,19 @@ tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *
     if (!out || !opt) fail(TQC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
     Multi *m = create_multi(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, opt->use_graph,
-                            opt->num_streams, opt->timed, (hipStream_t)stream, opt->batched_final);
+                            opt->num_streams, opt->timed, (hipStream_t)stream, opt->grouped);
     *out = reinterpret_cast<tqc_multi_t>(static_cast<tqc_multi_s *>(m));
   });
 }
 
-tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *batched_jobs, int32_t *batched_launches) {
+tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *launches, int32_t *shared_root_jobs,
+                          int32_t *shared_root_launches) {
   return guarded([&] {
     if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
     const Multi *m = static_cast<Multi *>(multi);
-    int32_t n = 0;
-    for (int c : m->class_of) n += c >= 0 ? 1 : 0;
-    if (batched_jobs) *batched_jobs = n;
-    if (batched_launches) *batched_launches = (int32_t)m->classes.size();
+    if (launches) *launches = m->grouped ? (int32_t)m->gsteps.size() : -1;
+    if (shared_root_jobs) *shared_root_jobs = m->shared_root_jobs;
+    if (shared_root_launches) *shared_root_launches = m->shared_roots;
   });
 }
 

@@ -171,12 +171,12 @@ __device__ inline void cut_map(const double *v, double *p) {
 // Consecutive threads take consecutive innermost coordinates, so every
 // load and store instruction of a wave covers consecutive addresses.
 template <int G, bool UA, bool UB>
-__device__ inline void pass_body(const TransformPassArgs &a) {
+__device__ inline void pass_body(const TransformPassArgs &a, uint64_t bid, uint64_t nblk) {
   constexpr int NA = UA ? 6 : 4;
   constexpr int NB = G == 2 ? (UB ? 6 : 4) : 1;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = nblk * blockDim.x;
   const bool small = a.nfree <= 0xffffffffull;
-  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.nfree; f += stride) {
+  for (uint64_t f = bid * blockDim.x + threadIdx.x; f < a.nfree; f += stride) {
     uint64_t ib = 0, ob = 0;
     if (small) {
       uint32_t r = (uint32_t)f;
@@ -241,18 +241,21 @@ __device__ inline void pass_body(const TransformPassArgs &a) {
 struct PassBatch {
   TransformPassArgs a[kPassBatch];
 };
-__global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
-  const TransformPassArgs &a = pb.a[blockIdx.y];
+__device__ inline void pass_dispatch(const TransformPassArgs &a, uint64_t bid, uint64_t nblk) {
   if (a.g == 1) {
-    if (a.up[0]) pass_body<1, true, false>(a);
-    else pass_body<1, false, false>(a);
+    if (a.up[0]) pass_body<1, true, false>(a, bid, nblk);
+    else pass_body<1, false, false>(a, bid, nblk);
   } else if (a.up[0]) {
-    if (a.up[1]) pass_body<2, true, true>(a);
-    else pass_body<2, true, false>(a);
+    if (a.up[1]) pass_body<2, true, true>(a, bid, nblk);
+    else pass_body<2, true, false>(a, bid, nblk);
   } else {
-    if (a.up[1]) pass_body<2, false, true>(a);
-    else pass_body<2, false, false>(a);
+    if (a.up[1]) pass_body<2, false, true>(a, bid, nblk);
+    else pass_body<2, false, false>(a, bid, nblk);
   }
+}
+
+__global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
+  pass_dispatch(pb.a[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s) {
@@ -645,6 +648,180 @@ hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s) {
     case 3: return launch_gemm_bk<3, 32>(g, tile, s);
     default: return launch_gemm_bk<4, 32>(g, tile, s);
   }
+}
+
+// =========================================================== grouped launches
+// One launch runs the same kind of work of many reconstructions.  Record r
+// owns workgroups [first[r], first[r + 1]) of the grid and runs them as the
+// workgroups 0.. of its own single-record launch would, so every entry
+// sees the same arithmetic as in that launch.
+__device__ inline int group_record(const uint32_t *first, int n, uint32_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) grouped_pass_kernel(const TransformPassArgs *recs, const uint32_t *first,
+                                                           int n) {
+  const int r = group_record(first, n, blockIdx.x);
+  pass_dispatch(recs[r], blockIdx.x - first[r], first[r + 1] - first[r]);
+}
+
+__global__ void __launch_bounds__(256) grouped_transform_kernel(const TransformArgs *recs, const uint32_t *first,
+                                                                int n) {
+  const int r = group_record(first, n, blockIdx.x);
+  const TransformArgs &a = recs[r];
+  const uint64_t total = (1ull << (2 * a.c)) << a.o;
+  const uint64_t nb = first[r + 1] - first[r];
+  for (uint64_t e = (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x)
+    transform_elem(a, e);
+}
+
+__global__ void __launch_bounds__(256) grouped_zero_kernel(const ZeroRec *recs, int n) {
+  const ZeroRec &z = recs[blockIdx.x];
+  for (uint64_t i = threadIdx.x; i < z.n; i += blockDim.x) z.p[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) grouped_absmax_kernel(const AbsMaxArgs *recs, const uint32_t *first, int n) {
+  const int r = group_record(first, n, blockIdx.x);
+  const AbsMaxArgs &a = recs[r];
+  __shared__ double red[256];
+  const uint64_t total = 1ull << a.nbits;
+  const uint64_t nb = first[r + 1] - first[r];
+  double mx = 0.0;
+  for (uint64_t e = (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x)
+    mx = fmax(mx, gathered_abs(a, e));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(a.out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void __launch_bounds__(64) grouped_scale_kernel(const ScaleRec *recs, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const ScaleRec &q = recs[r];
+  int sum = 0;
+  for (int j = 0; j < q.m; ++j) {
+    const double mx = __longlong_as_double((long long)q.maxbits[j]);
+    const int e = mx > 0.0 ? -ilogb(mx) : 0;
+    q.exps[j] = e;
+    sum += e;
+  }
+  *q.root_scale = ldexp(1.0, -q.K - sum);
+}
+
+__global__ void __launch_bounds__(256) grouped_pack_kernel(const PackArgs *recs, const uint32_t *first, int n) {
+  const int r = group_record(first, n, blockIdx.x);
+  const PackArgs &a = recs[r];
+  const uint64_t total = 1ull << a.nbits;
+  const uint64_t nb = first[r + 1] - first[r];
+  for (uint64_t e = (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x)
+    pack_elem(a, e);
+}
+
+template <int P, int BM, int BN, int BK, bool A64>
+__global__ void __launch_bounds__(256) grouped_gemm_kernel(const GemmArgs *recs, const uint32_t *first, int n) {
+  __shared__ __attribute__((aligned(16))) char smem[GemmShape<P, BM, BN, BK>::LDS_BYTES];
+  const int r = group_record(first, n, blockIdx.x);
+  gemm_tile<P, BM, BN, BK, A64>(recs[r], blockIdx.x - first[r], smem);
+}
+
+uint32_t grouped_pass_blocks(const TransformPassArgs &a) { return grid_for(a.nfree); }
+uint32_t grouped_transform_blocks(const TransformArgs &a) { return grid_for((1ull << (2 * a.c)) << a.o); }
+uint32_t grouped_absmax_blocks(const AbsMaxArgs &a) { return grid_for((1ull << a.nbits) / 8 + 1, kMaxGrid); }
+uint32_t grouped_pack_blocks(const PackArgs &a) { return grid_for(1ull << a.nbits); }
+
+hipError_t launch_grouped_passes(const TransformPassArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                 hipStream_t s) {
+  if (n < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_pass_kernel, dim3(blocks), dim3(256), 0, s, recs, first, n);
+  return hipGetLastError();
+}
+hipError_t launch_grouped_transforms(const TransformArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                     hipStream_t s) {
+  if (n < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_transform_kernel, dim3(blocks), dim3(256), 0, s, recs, first, n);
+  return hipGetLastError();
+}
+hipError_t launch_grouped_zero(const ZeroRec *recs, int n, hipStream_t s) {
+  if (n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_zero_kernel, dim3(n), dim3(256), 0, s, recs, n);
+  return hipGetLastError();
+}
+hipError_t launch_grouped_absmax(const AbsMaxArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                 hipStream_t s) {
+  if (n < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_absmax_kernel, dim3(blocks), dim3(256), 0, s, recs, first, n);
+  return hipGetLastError();
+}
+hipError_t launch_grouped_scales(const ScaleRec *recs, int n, hipStream_t s) {
+  if (n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_scale_kernel, dim3((n + 63) / 64), dim3(64), 0, s, recs, n);
+  return hipGetLastError();
+}
+hipError_t launch_grouped_packs(const PackArgs *recs, const uint32_t *first, int n, uint32_t blocks, hipStream_t s) {
+  if (n < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_pack_kernel, dim3(blocks), dim3(256), 0, s, recs, first, n);
+  return hipGetLastError();
+}
+
+GemmClass gemm_class(int prec, const GemmArgs &g, int tile) {
+  GemmClass c{};
+  c.prec = prec;
+  c.tile = tile;
+  c.bk = prec == 0 ? 16 : (prec == 1 ? (g.kpad >= 5 ? 32 : 16) : 32);
+  const int bm = tile == 0 ? 128 : (tile == 1 ? 64 : 32);
+  const uint64_t tiles = (((1ull << g.lm) + bm - 1) / bm) * (((1ull << g.ln) + bm - 1) / bm);
+  c.ksplit = splitk_log2(g, tiles, 1ull << (g.lm + g.ln));
+  c.a64 = prec != 0 && g.kpad - c.ksplit > 8;
+  c.tiles = tiles;
+  return c;
+}
+
+template <int P, int BM, int BK>
+static void launch_gg(bool a64, const GemmArgs *recs, const uint32_t *first, int n, uint32_t blocks, hipStream_t s) {
+  if constexpr (P == 0) {
+    hipLaunchKernelGGL((grouped_gemm_kernel<P, BM, BM, BK, false>), dim3(blocks), dim3(256), 0, s, recs, first, n);
+  } else {
+    if (a64)
+      hipLaunchKernelGGL((grouped_gemm_kernel<P, BM, BM, BK, true>), dim3(blocks), dim3(256), 0, s, recs, first, n);
+    else
+      hipLaunchKernelGGL((grouped_gemm_kernel<P, BM, BM, BK, false>), dim3(blocks), dim3(256), 0, s, recs, first, n);
+  }
+}
+
+template <int P, int BK>
+static void launch_gg_tile(int tile, bool a64, const GemmArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                           hipStream_t s) {
+  switch (tile) {
+    case 0: launch_gg<P, 128, BK>(a64, recs, first, n, blocks, s); break;
+    case 1: launch_gg<P, 64, BK>(a64, recs, first, n, blocks, s); break;
+    default: launch_gg<P, 32, BK>(a64, recs, first, n, blocks, s); break;
+  }
+}
+
+hipError_t launch_grouped_gemm(const GemmClass &c, const GemmArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                               hipStream_t s) {
+  if (n < 1 || blocks < 1 || c.ksplit != 0 || c.tile < 0 || c.tile > 2) return hipErrorInvalidValue;
+  switch (c.prec) {
+    case 0: launch_gg_tile<0, 16>(c.tile, false, recs, first, n, blocks, s); break;
+    case 1:
+      if (c.bk == 32) launch_gg_tile<1, 32>(c.tile, c.a64, recs, first, n, blocks, s);
+      else launch_gg_tile<1, 16>(c.tile, c.a64, recs, first, n, blocks, s);
+      break;
+    case 2: launch_gg_tile<2, 32>(c.tile, c.a64, recs, first, n, blocks, s); break;
+    case 3: launch_gg_tile<3, 32>(c.tile, c.a64, recs, first, n, blocks, s); break;
+    default: launch_gg_tile<4, 32>(c.tile, c.a64, recs, first, n, blocks, s); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace tqc

@@ -51,6 +51,53 @@ RootJob make_root_job(int prec, const GemmArgs &g);
 hipError_t launch_root_multi(int prec, int kpad, const RootJob *jobs, int njobs, int blocks_per_job,
                              hipStream_t s);
 
+// grouped launches: one launch runs the same kind of work of many
+// reconstructions.  Record r owns workgroups [first[r], first[r + 1]) of the
+// grid (first: device array of n + 1 entries, first[0] = 0, increasing; the
+// grid has first[n] workgroups) and runs them as workgroups 0.. of its own
+// launch of first[r + 1] - first[r] workgroups would.  The *_blocks helpers
+// give the workgroup count of a record's own launch.
+struct ZeroRec {
+  unsigned long long *p;
+  uint64_t n;
+};
+struct ScaleRec {
+  const unsigned long long *maxbits;
+  int m, K;
+  int *exps;
+  double *root_scale;
+};
+uint32_t grouped_pass_blocks(const TransformPassArgs &a);
+uint32_t grouped_transform_blocks(const TransformArgs &a);
+uint32_t grouped_absmax_blocks(const AbsMaxArgs &a);
+uint32_t grouped_pack_blocks(const PackArgs &a);
+hipError_t launch_grouped_passes(const TransformPassArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                 hipStream_t s);
+hipError_t launch_grouped_transforms(const TransformArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                     hipStream_t s);
+hipError_t launch_grouped_zero(const ZeroRec *recs, int n, hipStream_t s);   // one workgroup per record
+hipError_t launch_grouped_absmax(const AbsMaxArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                                 hipStream_t s);
+hipError_t launch_grouped_scales(const ScaleRec *recs, int n, hipStream_t s);  // one thread per record
+hipError_t launch_grouped_packs(const PackArgs *recs, const uint32_t *first, int n, uint32_t blocks, hipStream_t s);
+// the kernel variant launch_gemm picks for a step (tile, k step, float64
+// folding, split count); grouped GEMM records are prepared for the tile
+// (prepare_gemm_args) and must not split
+struct GemmClass {
+  int prec, tile, bk, ksplit;
+  bool a64;
+  uint64_t tiles;
+  bool operator<(const GemmClass &o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (tile != o.tile) return tile < o.tile;
+    if (bk != o.bk) return bk < o.bk;
+    return a64 < o.a64;
+  }
+};
+GemmClass gemm_class(int prec, const GemmArgs &g, int tile);
+hipError_t launch_grouped_gemm(const GemmClass &c, const GemmArgs *recs, const uint32_t *first, int n, uint32_t blocks,
+                               hipStream_t s);
+
 // output forms
 hipError_t launch_topk(const void *probs, int dtype, uint64_t len, int k, uint64_t *idx_out,
                        double *val_out, void *scratch, uint64_t scratch_bytes, hipStream_t s);
