@@ -241,6 +241,8 @@ def _pcts(x):
 BATCH_MODES = {"graph_4streams": dict(use_graph=True, streams=4),
                "graph_8streams": dict(use_graph=True, streams=8),
                "graph_grouped": dict(use_graph=True, grouped=True),
+               "graph_grouped_2waves": dict(use_graph=True, grouped=True, waves=2),
+               "graph_grouped_4waves": dict(use_graph=True, grouped=True, waves=4),
                "sequential_plain": dict(use_graph=False, streams=1)}
 
 

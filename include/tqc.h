@@ -463,6 +463,11 @@ typedef struct {
   int32_t num_streams;    /* as tqc_multi_create (0 = 4, at most 16)       */
   int32_t timed;          /* as tqc_multi_create                          */
   int32_t grouped;        /* 1: every kind of work in shared launches     */
+  int32_t waves;          /* grouped: the jobs split into this many waves
+                             of about equal predicted cost (0 = 1), each a
+                             launch list on its own stream; wave w + 1's
+                             launches start when wave w's launches before
+                             its final steps are done                    */
 } tqc_multi_options;
 tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                                const uint64_t *out_bytes, const tqc_multi_options *opt, void *stream,

@@ -84,7 +84,7 @@ class BatchOptions(ctypes.Structure):
 
 class MultiOptions(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("timed", ctypes.c_int32),
-                ("grouped", ctypes.c_int32)]
+                ("grouped", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
 class TrainOptions(ctypes.Structure):
@@ -619,7 +619,7 @@ class Multi:
     Outputs equal each plan's own ``execute`` bit for bit."""
 
     def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None,
-                 grouped=False):
+                 grouped=False, waves=1):
         L = lib()
         if outs is None:
             outs = [p.output_tensor() for p in plans]
@@ -633,7 +633,7 @@ class Multi:
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
         ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
         h = ctypes.c_void_p()
-        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(grouped)))
+        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(grouped)), int(waves))
         _check(L.tqc_multi_create_ex(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 

@@ -1795,8 +1795,14 @@ struct Multi {
   // (built at creation, replayed by each execute); stamp slot of each step
   // and, per job, the step that completes it
   bool grouped = false;
-  std::vector<std::function<void(hipStream_t)>> gsteps;
-  std::vector<int> done_at;       // job -> index of its completing step
+  struct Wave {
+    std::vector<std::function<void(hipStream_t)>> steps;  // up to the final steps
+    std::vector<std::function<void(hipStream_t)>> roots;  // shared persistent final steps
+  };
+  std::vector<Wave> waves;
+  std::vector<hipEvent_t> head_done;  // per wave: its steps are done
+  std::vector<int> done_at;       // job -> stamp slot of the launch that completes it
+  int nslots = 0;                 // stamp slots in use
   int shared_roots = 0;           // persistent final-step launches
   int shared_root_jobs = 0;       // jobs whose final step runs in one of them
   void *gtab = nullptr;           // device tables of the grouped launches
@@ -1806,6 +1812,7 @@ struct Multi {
     if (graph) (void)hipGraphDestroy(graph);
     for (auto e : join) (void)hipEventDestroy(e);
     for (auto e : mid) (void)hipEventDestroy(e);
+    for (auto e : head_done) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     for (auto st : streams) (void)hipStreamDestroy(st);
     if (cap) (void)hipStreamDestroy(cap);
@@ -1938,25 +1945,23 @@ struct Group {
 // float16 splits before their final step), and last the final steps that run
 // on the persistent kernel, one launch per (form, K).  Every record is the
 // one the job's own execute would launch, so outputs match bit for bit.
-static void build_grouped(Multi *b) {
-  b->grouped = true;
-  const int njobs = (int)b->plans.size();
+using LaunchFactory = std::function<std::function<void(hipStream_t)>(char *)>;
+
+struct WavePlan {
+  std::vector<LaunchFactory> steps, roots;
+  std::vector<std::vector<int>> step_jobs, root_jobs;  // jobs each launch completes
+};
+
+// The launches of one wave (a subset of the jobs, `sel`), their tables in A.
+static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<JobOps> &all_ops, TableArena &A) {
+  WavePlan W;
+  const int njobs = (int)sel.size();
   std::vector<JobOps> ops(njobs);
-  for (int j = 0; j < njobs; ++j) {
-    if (b->plans[j]->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not grouped", j);
-    // points the network's Pauli tensors into this plan's workspace (jobs
-    // may share a network); the workspace itself exists already
-    ensure_workspace(b->plans[j], nullptr);
-    ops[j] = job_ops(b->plans[j], b->outs[j]);
-  }
-  TableArena A;
-  // each planned launch: a closure over device pointers resolved after the
-  // tables are uploaded
-  std::vector<std::function<std::function<void(hipStream_t)>(char *)>> plan;
-  std::vector<std::vector<int>> completes;  // jobs each launch completes
-  auto add_launch = [&](std::function<std::function<void(hipStream_t)>(char *)> f, std::vector<int> jobs = {}) {
-    plan.push_back(std::move(f));
-    completes.push_back(std::move(jobs));
+  for (int q = 0; q < njobs; ++q) ops[q] = all_ops[sel[q]];
+  auto add_launch = [&](LaunchFactory f, std::vector<int> jobs = {}) {
+    for (int &x : jobs) x = sel[x];
+    W.steps.push_back(std::move(f));
+    W.step_jobs.push_back(std::move(jobs));
   };
   // 1. transform passes, level by level, then per-entry transforms
   size_t nlev = 0;
@@ -2028,7 +2033,7 @@ static void build_grouped(Multi *b) {
     std::vector<int> done;
     for (int j = 0; j < njobs; ++j) {
       for (auto &a : ops[j].packs) g.push(a, grouped_pack_blocks(a));
-      if (b->plans[j]->net->m == 1) done.push_back(j);
+      if (b->plans[sel[j]]->net->m == 1) done.push_back(j);
     }
     if (!g.empty()) {
       const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
@@ -2125,28 +2130,72 @@ static void build_grouped(Multi *b) {
     const int prec = kv.first.first, kpad = kv.first.second, n = (int)tab.size();
     if (n > 65535) fail(TQC_ERR_UNSUPPORTED, "more than 65535 final steps in one launch");
     const uint64_t ro = A.add_vec(tab);
-    add_launch([=](char *d) {
+    W.roots.push_back([=](char *d) {
       return [=](hipStream_t s) { HIP_OK(launch_root_multi(prec, kpad, (const RootJob *)(d + ro), n, blocks, s)); };
-    }, jobs);
+    });
+    for (int &x : jobs) x = sel[x];
+    W.root_jobs.push_back(jobs);
     b->shared_roots += 1;
     b->shared_root_jobs += n;
   }
+  return W;
+}
+
+// The whole batch as a few waves of jobs (about equal predicted cost each,
+// largest jobs first); each wave is a short list of shared launches on its
+// own stream, and wave w + 1 starts once wave w's launches before its final
+// steps are done, so one wave's final steps (store bound) run beside the
+// next wave's earlier launches.
+static void build_grouped(Multi *b, int nwaves) {
+  b->grouped = true;
+  const int njobs = (int)b->plans.size();
+  std::vector<JobOps> ops(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    if (b->plans[j]->num_slices != 1) fail(TQC_ERR_UNSUPPORTED, "job %d: sliced plans are not grouped", j);
+    // points the network's Pauli tensors into this plan's workspace (jobs
+    // may share a network); the workspace itself exists already
+    ensure_workspace(b->plans[j], nullptr);
+    ops[j] = job_ops(b->plans[j], b->outs[j]);
+  }
+  nwaves = std::max(1, std::min(nwaves, njobs));
+  std::vector<std::vector<int>> sel(nwaves);
+  std::vector<double> load(nwaves, 0.0);
+  for (int j : b->order) {
+    const int w = int(std::min_element(load.begin(), load.end()) - load.begin());
+    sel[w].push_back(j);
+    load[w] += std::max(1e-9, b->plans[j]->stats.predicted_seconds);
+  }
+  TableArena A;
+  std::vector<WavePlan> plans;
+  for (int w = 0; w < nwaves; ++w)
+    if (!sel[w].empty()) plans.push_back(plan_wave(b, sel[w], ops, A));
   // upload the tables, then bind the launches to them
   if (!A.host.empty()) {
     HIP_OK(hipMalloc(&b->gtab, A.host.size()));
     HIP_OK(hipMemcpy(b->gtab, A.host.data(), A.host.size(), hipMemcpyHostToDevice));
   }
   b->done_at.assign(njobs, -1);
-  for (size_t i = 0; i < plan.size(); ++i) {
-    b->gsteps.push_back(plan[i]((char *)b->gtab));
-    for (int j : completes[i]) b->done_at[j] = (int)i;
+  int slot = 1 + 2 * njobs;
+  for (WavePlan &P : plans) {
+    Multi::Wave W;
+    for (size_t i = 0; i < P.steps.size(); ++i, ++slot) {
+      W.steps.push_back(P.steps[i]((char *)b->gtab));
+      for (int j : P.step_jobs[i]) b->done_at[j] = slot;
+    }
+    for (size_t i = 0; i < P.roots.size(); ++i, ++slot) {
+      W.roots.push_back(P.roots[i]((char *)b->gtab));
+      for (int j : P.root_jobs[i]) b->done_at[j] = slot;
+    }
+    b->waves.push_back(std::move(W));
   }
+  b->nslots = slot;
   for (int j = 0; j < njobs; ++j)
     if (b->done_at[j] < 0) fail(TQC_ERR_INTERNAL, "job %d has no completing launch", j);
 }
 
 static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
-                           int use_graph, int nstreams, int timed, hipStream_t s, int grouped = 0) {
+                           int use_graph, int nstreams, int timed, hipStream_t s, int grouped = 0,
+                           int waves = 1) {
   if (njobs < 1 || !plans || !outs) fail(TQC_ERR_INVALID_ARG, "no jobs");
   if (nstreams < 0 || nstreams > 16) fail(TQC_ERR_INVALID_ARG, "streams %d (0..16)", nstreams);
   if (nstreams == 0) nstreams = 4;
@@ -2186,13 +2235,16 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
     b->stream_of[j] = k;
     load[k] += cost[j];
   }
-  if (grouped) build_grouped(b.get());
+  if (grouped) {
+    build_grouped(b.get(), waves);
+    nstreams = std::max<int>(nstreams, (int)b->waves.size());
+  }
   if (b->timed) {
     int khz = 0;
     HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
     if (khz <= 0) fail(TQC_ERR_DEVICE, "device reports no clock rate for timestamps");
     b->tick_ms = 1.0 / khz;
-    const uint64_t nst = 1 + 2 * (uint64_t)njobs + b->gsteps.size();
+    const uint64_t nst = std::max<uint64_t>(1 + 2 * (uint64_t)njobs, (uint64_t)b->nslots);
     HIP_OK(hipMalloc((void **)&b->stamps, nst * 8));
     HIP_OK(launch_zero_u64(b->stamps, nst, s));
   }
@@ -2205,6 +2257,8 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
   for (auto &e : b->join) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   b->mid.resize(nstreams);
   for (auto &e : b->mid) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  b->head_done.resize(b->waves.size());
+  for (auto &e : b->head_done) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return b.release();
 }
 
@@ -2212,11 +2266,28 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
 static void multi_enqueue(Multi *b, hipStream_t origin) {
   if (b->timed) HIP_OK(launch_stamp(b->stamps, origin));
   if (b->grouped) {
-    // every job starts with the first step; step i's stamp follows it
-    for (size_t i = 0; i < b->gsteps.size(); ++i) {
-      b->gsteps[i](origin);
-      if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * b->plans.size() + i, origin));
+    // wave w on worker stream w: its launches up to the final steps start
+    // once wave w - 1's are done, then its shared final-step launches; every
+    // launch is followed by its stamp
+    HIP_OK(hipEventRecord(b->fork, origin));
+    int slot = 1 + 2 * (int)b->plans.size();
+    for (size_t w = 0; w < b->waves.size(); ++w) {
+      hipStream_t st = b->streams[w];
+      HIP_OK(hipStreamWaitEvent(st, w == 0 ? b->fork : b->head_done[w - 1], 0));
+      for (auto &f : b->waves[w].steps) {
+        f(st);
+        if (b->timed) HIP_OK(launch_stamp(b->stamps + slot, st));
+        ++slot;
+      }
+      HIP_OK(hipEventRecord(b->head_done[w], st));
+      for (auto &f : b->waves[w].roots) {
+        f(st);
+        if (b->timed) HIP_OK(launch_stamp(b->stamps + slot, st));
+        ++slot;
+      }
+      HIP_OK(hipEventRecord(b->join[w], st));
     }
+    for (size_t w = 0; w < b->waves.size(); ++w) HIP_OK(hipStreamWaitEvent(origin, b->join[w], 0));
     return;
   }
   HIP_OK(hipEventRecord(b->fork, origin));
@@ -2271,13 +2342,13 @@ static void multi_times(Multi *b, double *start_ms, double *end_ms) {
   check_device(b->device);
   HIP_OK(hipStreamSynchronize(b->last_stream));
   const size_t n = b->plans.size();
-  std::vector<unsigned long long> st(1 + 2 * n + b->gsteps.size());
+  std::vector<unsigned long long> st(std::max<size_t>(1 + 2 * n, (size_t)b->nslots));
   HIP_OK(hipMemcpy(st.data(), b->stamps, st.size() * 8, hipMemcpyDeviceToHost));
   for (size_t j = 0; j < n; ++j) {
     // grouped: every job starts with the launch and ends with the shared
     // launch that runs its final step
     const uint64_t s0 = b->grouped ? 0 : 1 + 2 * j;
-    const uint64_t e = b->grouped ? 1 + 2 * n + b->done_at[j] : 2 + 2 * j;
+    const uint64_t e = b->grouped ? (uint64_t)b->done_at[j] : 2 + 2 * j;
     if (start_ms) start_ms[j] = double((long long)(st[s0] - st[0])) * b->tick_ms;
     if (end_ms) end_ms[j] = double((long long)(st[e] - st[0])) * b->tick_ms;
   }
@@ -3218,7 +3289,8 @@ tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *
     if (!out || !opt) fail(TQC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
     Multi *m = create_multi(num_jobs, reinterpret_cast<Plan *const *>(plans), outs, out_bytes, opt->use_graph,
-                            opt->num_streams, opt->timed, (hipStream_t)stream, opt->grouped);
+                            opt->num_streams, opt->timed, (hipStream_t)stream, opt->grouped,
+                            opt->waves > 0 ? opt->waves : 1);
     *out = reinterpret_cast<tqc_multi_t>(static_cast<tqc_multi_s *>(m));
   });
 }
@@ -3228,7 +3300,9 @@ tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *launches, int32_t *shared_
   return guarded([&] {
     if (!multi) fail(TQC_ERR_INVALID_ARG, "null argument");
     const Multi *m = static_cast<Multi *>(multi);
-    if (launches) *launches = m->grouped ? (int32_t)m->gsteps.size() : -1;
+    int32_t nl = 0;
+    for (auto &w : m->waves) nl += (int32_t)(w.steps.size() + w.roots.size());
+    if (launches) *launches = m->grouped ? nl : -1;
     if (shared_root_jobs) *shared_root_jobs = m->shared_root_jobs;
     if (shared_root_launches) *shared_root_launches = m->shared_roots;
   });

@@ -129,16 +129,16 @@ def test_generated_batch_jobs_match_oracle(form, rtol):
 
 
 # ------------------------------------------------------------ grouped mode
-@pytest.mark.parametrize("form,use_graph", [("fp32", True), ("fp32", False), ("bf16x3", True),
-                                            ("bf16x6", True), ("fp16x3", False), ("fp64", True)])
-def test_grouped_equals_plain_execution(form, use_graph):
+@pytest.mark.parametrize("form,use_graph,waves", [("fp32", True, 1), ("fp32", False, 3), ("bf16x3", True, 2),
+                                                  ("bf16x6", True, 1), ("fp16x3", False, 2), ("fp64", True, 4)])
+def test_grouped_equals_plain_execution(form, use_graph, waves):
     """Every kind of work of all jobs in shared launches (transform passes,
     scales, packs, steps by depth, final steps on the persistent kernel in one
     launch per (form, K)); every output still equals the plan's own
     execution bit for bit, also over graph replays."""
     specs, nets, plans = jobs(form)
     plain = [p.execute().clone() for p in plans]
-    mj = tqc.Multi(plans, use_graph=use_graph, timed=True, grouped=True)
+    mj = tqc.Multi(plans, use_graph=use_graph, timed=True, grouped=True, waves=waves)
     nl, nb, nr = mj.info()
     assert 0 < nl < 4 * len(plans), nl
     if form != "fp64":
@@ -188,7 +188,7 @@ def test_grouped_large_jobs_against_oracle():
     plans = [tqc.Plan(tqc.Network.from_spec(s), precision="fp32") for s in specs]
     plain = [p.execute().clone() for p in plans]
     torch.cuda.synchronize()
-    mj = tqc.Multi(plans, use_graph=True, grouped=True)
+    mj = tqc.Multi(plans, use_graph=True, grouped=True, waves=3)
     mj.execute()
     torch.cuda.synchronize()
     for i, (o, r) in enumerate(zip(mj.outs, plain)):
