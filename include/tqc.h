@@ -175,8 +175,9 @@ typedef struct {
   int32_t num_candidates;      /* randomised-greedy candidates (0 = default) */
   uint64_t seed;
   int32_t tile_policy;         /* 0 fixed default tiles, 1 autotuned table,
-                                  2 fixed tiles and no persistent final-step
-                                  kernel (the general GEMM for every step)  */
+                                  2 fixed tiles and the general GEMM for
+                                  every step (neither the persistent
+                                  final-step kernel nor the long-k kernel) */
   int32_t num_measured;        /* TQC_COST_MEASURED: shortlisted orders timed
                                   besides the roofline plan (0 = 4)          */
   double max_rel_error;        /* TQC_COST_MEASURED: largest accepted

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtqc.so")
 ARCH = os.environ.get("TQC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "kernels.hip", "root.hip", "outputs.hip", "batch.hip", "costmodel.hip",
+SOURCES = ["api.hip", "kernels.hip", "root.hip", "longk.hip", "outputs.hip", "batch.hip", "costmodel.hip",
            "planner.cpp", "cutfind.cpp"]
 
 

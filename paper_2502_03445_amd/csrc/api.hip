@@ -647,7 +647,7 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
         // deferred: the caller runs it in a launch shared with other jobs
         if (!defer_root) HIP_OK(launch_root_gemm(sp, g, s));
       } else {
-        HIP_OK(launch_gemm(sp, g, st.tile, s));
+        HIP_OK(launch_gemm(sp, g, st.tile, s, p->tile_policy == 2));
       }
       if (tm) tm->end();
     }
@@ -1603,7 +1603,7 @@ static void autotune_plan(Plan *p, void *out, uint64_t out_bytes, int reps, hipS
       const bool persistent = root_on_persistent(p, trial, g);
       auto run = [&]() {
         if (persistent) HIP_OK(launch_root_gemm(sp, g, s));
-        else HIP_OK(launch_gemm(sp, g, tile, s));
+        else HIP_OK(launch_gemm(sp, g, tile, s, p->tile_policy == 2));
       };
       run();  // warm
       HIP_OK(hipEventRecord(e0, s));

@@ -281,10 +281,205 @@ __device__ inline uint64_t out_key_f64(double v) {
   return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// Epilogue of one output tile (shared by the GEMM kernels): result(i, j, r)
+// is item r of 16x16 block (i, j) of the calling wave as a double.  Stores
+// the scaled tile in the consumer's layout (staged through LDS in output
+// order when `staged`), the split-k partials, or scatters directly; writes
+// the tile statistics when the step asks for them.  `smem` holds at least
+// the staged float tile, and `stat_off` 64 bytes for the statistics.
+template <int P, int BM, int BN, typename R>
+__device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmArgs &g, char *smem, int stat_off,
+                                                                     uint64_t tm, uint64_t tn, uint64_t split,
+                                                                     bool staged, R result) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  const uint64_t tilesN = (N + BN - 1) / BN;
+  const uint64_t m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  const double scale = g.dscale ? *g.dscale : g.scale;
+  // tile statistics of the stored values (float32 / float64 outputs only)
+  const bool want_stats = g.tkey != nullptr;
+  double st_sum = 0.0;
+  uint64_t st_key = 0;
+  uint32_t st_k32 = 0;
+  auto note = [&](double y) {  // y = accumulator * scale, before the store's rounding
+    if (g.out_kind == OUT_F32) {
+      const float f = (float)y;
+      st_sum += (double)f;
+      const uint32_t u = __float_as_uint(f);
+      const uint32_t k = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);  // out_key_f32
+      st_k32 = k > st_k32 ? k : st_k32;
+    } else {
+      st_sum += y;
+      const uint64_t k = out_key_f64(y);
+      st_key = k > st_key ? k : st_key;
+    }
+  };
+  auto finish_stats = [&]() {
+    if (g.out_kind == OUT_F32) st_key = st_k32;
+    // fixed-order reduction: lanes by xor butterfly, then waves 0..3
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      st_sum += __shfl_xor(st_sum, off);
+      const uint64_t o = __shfl_xor(st_key, off);
+      st_key = o > st_key ? o : st_key;
+    }
+    double *rs = (double *)(smem + stat_off);
+    uint64_t *rk = (uint64_t *)(smem + stat_off + 32);
+    if (lane == 0) {
+      rs[wave] = st_sum;
+      rk[wave] = st_key;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
+      uint64_t k = rk[0];
+      for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
+      g.tsum[tm * tilesN + tn] = t;
+      g.tkey[tm * tilesN + tn] = k;
+    }
+  };
+  // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
+  // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
+  // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
+  if (staged) {
+    // 1) accumulators -> LDS at their compact (output-order) tile index
+    float *ct = (float *)smem;
+    __syncthreads();  // operand tiles no longer needed
+    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
+    uint32_t tcol[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) tcol[j] = (uint32_t)deposit_c<LBN>(wn * WN + j * 16 + lr, g.rankN, LBN);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t trow = (uint32_t)deposit_c<LBM>(wm * WM + i * 16 + 4 * lg + r, g.rankM, LBM);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)result(i, j, r);
+      }
+    __syncthreads();
+    // 2) stream the tile out in output order: compact index x maps to the
+    //    output offset sum_b bit_b(x) << lpos[b]; the bits below the stride
+    //    of the loop are fixed per thread
+    const uint64_t base = deposit_c<kMaxBits>(m0, g.posM, g.lm) + deposit_c<kMaxBits>(n0, g.posN, g.ln);
+    constexpr int TT = BM * BN;
+    constexpr int NCB = LBM + LBN;
+    if (g.vec4) {
+      constexpr int LB = 10;  // log2(256 threads * 4)
+      const uint64_t lo = deposit_c<LB>((uint64_t)tid * 4, g.lpos, LB);
+#pragma unroll 4
+      for (int it = 0; it * 1024 < TT; ++it) {
+        const int x = it * 1024 + tid * 4;
+        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
+        const floatx4 v = *(const floatx4 *)(ct + x);
+        switch (g.out_kind) {
+          case OUT_F32: {
+            floatx4 w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[e] = (float)((double)v[e] * scale);
+            *(floatx4 *)((float *)g.c0 + addr) = w;
+            if (want_stats)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
+            break;
+          }
+          case OUT_F64_ACC: {
+            double *o = (double *)g.c0 + addr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] += (double)v[e] * scale;
+            break;
+          }
+          case OUT_F64: {
+            double *o = (double *)g.c0 + addr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * scale;
+            if (want_stats)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
+            break;
+          }
+          default: {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) store_out(g, scale, addr + e, v[e]);
+            break;
+          }
+        }
+      }
+    } else {
+      constexpr int LB = 8;  // log2(256 threads)
+      const uint64_t lo = deposit_c<LB>((uint64_t)tid, g.lpos, LB);
+      for (int it = 0; it * 256 < TT; ++it) {
+        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
+        const float v = ct[it * 256 + tid];
+        store_out(g, scale, addr, v);
+        if (want_stats) note((double)v * scale);
+      }
+    }
+    if (want_stats) finish_stats();
+    return;
+  }
+  // split-K partial results: unscaled float64, dense [split][m][n]
+  if (g.ksplit) {
+    double *part = g.partial + split * M * N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
+        const uint64_t row = m0 + wm * WM + i * 16 + rr;
+        if (row >= M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const uint64_t col = n0 + wn * WN + j * 16 + lr;
+          if (col < N) part[row * N + col] = result(i, j, r);
+        }
+      }
+    return;
+  }
+  // direct scatter (partial tiles, float64 form): row = m0 | local row, the
+  // tile base and the tile-local bits deposit separately
+  {
+    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
+    const int lbm = g.lm < LBM ? g.lm : LBM, lbn = g.ln < LBN ? g.ln : LBN;
+    const uint64_t basem = deposit_c<kMaxBits>(m0, g.posM, g.lm);
+    const uint64_t basen = deposit_c<kMaxBits>(n0, g.posN, g.ln);
+    uint64_t offn[FN];
+    bool okn[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int cl = wn * WN + j * 16 + lr;
+      okn[j] = n0 + cl < N;
+      offn[j] = basen + deposit_c<LBN>((uint64_t)cl, g.posN, lbn);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
+        const int rl = wm * WM + i * 16 + rr;
+        if (m0 + rl >= M) continue;
+        const uint64_t offm = basem + deposit_c<LBM>((uint64_t)rl, g.posM, lbm);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          if (okn[j]) {
+            const double v = result(i, j, r);
+            store_out(g, scale, offm + offn[j], v);
+            if (want_stats) note(v * scale);
+          }
+      }
+    }
+  }
+  if (want_stats) finish_stats();
+}
+
 // A64: float32 MFMA sums over 256-long k chunks are folded into float64
 // accumulators (long float32 chains would exceed 1e-6 relative error).
 template <int P, int BM, int BN, int BK, bool A64 = false>
-__device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
+__device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
   using T = PrecTraits<P>;
   using E = typename T::E;
   using Acc = typename T::Acc;
@@ -467,181 +662,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, uint64_t bid, char *smem) {
     else return (double)acc[i][j][r];
   };
 
-  const double scale = g.dscale ? *g.dscale : g.scale;
-  // tile statistics of the stored values (float32 / float64 outputs only)
-  const bool want_stats = g.tkey != nullptr;
-  double st_sum = 0.0;
-  uint64_t st_key = 0;
-  uint32_t st_k32 = 0;
-  auto note = [&](double y) {  // y = accumulator * scale, before the store's rounding
-    if (g.out_kind == OUT_F32) {
-      const float f = (float)y;
-      st_sum += (double)f;
-      const uint32_t u = __float_as_uint(f);
-      const uint32_t k = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);  // out_key_f32
-      st_k32 = k > st_k32 ? k : st_k32;
-    } else {
-      st_sum += y;
-      const uint64_t k = out_key_f64(y);
-      st_key = k > st_key ? k : st_key;
-    }
-  };
-  auto finish_stats = [&]() {
-    if (g.out_kind == OUT_F32) st_key = st_k32;
-    // fixed-order reduction: lanes by xor butterfly, then waves 0..3
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      st_sum += __shfl_xor(st_sum, off);
-      const uint64_t o = __shfl_xor(st_key, off);
-      st_key = o > st_key ? o : st_key;
-    }
-    double *rs = (double *)(smem + S::STAT_OFF);
-    uint64_t *rk = (uint64_t *)(smem + S::STAT_OFF + 32);
-    if (lane == 0) {
-      rs[wave] = st_sum;
-      rk[wave] = st_key;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const double t = ((rs[0] + rs[1]) + rs[2]) + rs[3];
-      uint64_t k = rk[0];
-      for (int w = 1; w < 4; ++w) k = rk[w] > k ? rk[w] : k;
-      g.tsum[tm * tilesN + tn] = t;
-      g.tkey[tm * tilesN + tn] = k;
-    }
-  };
-  // Epilogue.  16x16 block output layout: lane holds column lr; item r is row
-  // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
-  // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
-  if (staged) {
-    // 1) accumulators -> LDS at their compact (output-order) tile index
-    float *ct = (float *)smem;
-    __syncthreads();  // operand tiles no longer needed
-    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
-    uint32_t tcol[FN];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) tcol[j] = (uint32_t)deposit_c<LBN>(wn * WN + j * 16 + lr, g.rankN, LBN);
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t trow = (uint32_t)deposit_c<LBM>(wm * WM + i * 16 + 4 * lg + r, g.rankM, LBM);
-#pragma unroll
-        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)result(i, j, r);
-      }
-    __syncthreads();
-    // 2) stream the tile out in output order: compact index x maps to the
-    //    output offset sum_b bit_b(x) << lpos[b]; the bits below the stride
-    //    of the loop are fixed per thread
-    const uint64_t base = deposit_c<kMaxBits>(m0, g.posM, g.lm) + deposit_c<kMaxBits>(n0, g.posN, g.ln);
-    constexpr int TT = BM * BN;
-    constexpr int NCB = LBM + LBN;
-    if (g.vec4) {
-      constexpr int LB = 10;  // log2(256 threads * 4)
-      const uint64_t lo = deposit_c<LB>((uint64_t)tid * 4, g.lpos, LB);
-#pragma unroll 4
-      for (int it = 0; it * 1024 < TT; ++it) {
-        const int x = it * 1024 + tid * 4;
-        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
-        const floatx4 v = *(const floatx4 *)(ct + x);
-        switch (g.out_kind) {
-          case OUT_F32: {
-            floatx4 w;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) w[e] = (float)((double)v[e] * scale);
-            *(floatx4 *)((float *)g.c0 + addr) = w;
-            if (want_stats)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
-            break;
-          }
-          case OUT_F64_ACC: {
-            double *o = (double *)g.c0 + addr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] += (double)v[e] * scale;
-            break;
-          }
-          case OUT_F64: {
-            double *o = (double *)g.c0 + addr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = (double)v[e] * scale;
-            if (want_stats)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
-            break;
-          }
-          default: {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) store_out(g, scale, addr + e, v[e]);
-            break;
-          }
-        }
-      }
-    } else {
-      constexpr int LB = 8;  // log2(256 threads)
-      const uint64_t lo = deposit_c<LB>((uint64_t)tid, g.lpos, LB);
-      for (int it = 0; it * 256 < TT; ++it) {
-        const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
-        const float v = ct[it * 256 + tid];
-        store_out(g, scale, addr, v);
-        if (want_stats) note((double)v * scale);
-      }
-    }
-    if (want_stats) finish_stats();
-    return;
-  }
-  // split-K partial results: unscaled float64, dense [split][m][n]
-  if (g.ksplit) {
-    double *part = g.partial + split * M * N;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
-        const uint64_t row = m0 + wm * WM + i * 16 + rr;
-        if (row >= M) continue;
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const uint64_t col = n0 + wn * WN + j * 16 + lr;
-          if (col < N) part[row * N + col] = result(i, j, r);
-        }
-      }
-    return;
-  }
-  // direct scatter (partial tiles, float64 form): row = m0 | local row, the
-  // tile base and the tile-local bits deposit separately
-  {
-    constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
-    const int lbm = g.lm < LBM ? g.lm : LBM, lbn = g.ln < LBN ? g.ln : LBN;
-    const uint64_t basem = deposit_c<kMaxBits>(m0, g.posM, g.lm);
-    const uint64_t basen = deposit_c<kMaxBits>(n0, g.posN, g.ln);
-    uint64_t offn[FN];
-    bool okn[FN];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int cl = wn * WN + j * 16 + lr;
-      okn[j] = n0 + cl < N;
-      offn[j] = basen + deposit_c<LBN>((uint64_t)cl, g.posN, lbn);
-    }
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = (P == 0) ? (lg + 4 * r) : (4 * lg + r);
-        const int rl = wm * WM + i * 16 + rr;
-        if (m0 + rl >= M) continue;
-        const uint64_t offm = basem + deposit_c<LBM>((uint64_t)rl, g.posM, lbm);
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          if (okn[j]) {
-            const double v = result(i, j, r);
-            store_out(g, scale, offm + offn[j], v);
-            if (want_stats) note(v * scale);
-          }
-      }
-    }
-  }
-  if (want_stats) finish_stats();
+  gemm_epilogue<P, BM, BN>(g, smem, S::STAT_OFF, tm, tn, split, staged, result);
 }
 
 // Tile-dependent epilogue parameters (host side): the tile's output bits in

@@ -610,12 +610,15 @@ static int splitk_log2(const GemmArgs &g, uint64_t tiles, uint64_t mn) {
 }
 
 template <int P, int BM, int BN, int BK>
-static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
+static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s, bool general) {
   using S = GemmShape<P, BM, BN, BK>;
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
   const uint64_t tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
   const uint64_t tiles = tilesM * tilesN;
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+  // long k on whole 128 x 128 tiles that fill the device: the deep-ring kernel
+  if (!general && P != 0 && BM == 128 && BN == 128 && gemm_long_eligible(P, g, (uint64_t)device_cus()))
+    return launch_gemm_long(P, g, s);
   prepare_gemm_args(g, P, BM, BN);
   static_assert(S::LDS_BYTES <= 81920, "two workgroups per CU need at most 80 KiB of LDS each");
   g.ksplit = splitk_log2(g, tiles, M * N);
@@ -631,22 +634,22 @@ static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s) {
 
 // tile ids: 0 = 128x128, 1 = 64x64, 2 = 32x32
 template <int P, int BK>
-static hipError_t launch_gemm_bk(const GemmArgs &g, int tile, hipStream_t s) {
+static hipError_t launch_gemm_bk(const GemmArgs &g, int tile, hipStream_t s, bool general) {
   switch (tile) {
-    case 0: return launch_gemm_t<P, 128, 128, BK>(g, s);
-    case 1: return launch_gemm_t<P, 64, 64, BK>(g, s);
-    default: return launch_gemm_t<P, 32, 32, BK>(g, s);
+    case 0: return launch_gemm_t<P, 128, 128, BK>(g, s, general);
+    case 1: return launch_gemm_t<P, 64, 64, BK>(g, s, general);
+    default: return launch_gemm_t<P, 32, 32, BK>(g, s, general);
   }
 }
 
-hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s) {
+hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s, bool general) {
   const int kp = g.kpad;
   switch (prec) {
-    case 0: return launch_gemm_bk<0, 16>(g, tile, s);
-    case 1: return kp >= 5 ? launch_gemm_bk<1, 32>(g, tile, s) : launch_gemm_bk<1, 16>(g, tile, s);
-    case 2: return launch_gemm_bk<2, 32>(g, tile, s);
-    case 3: return launch_gemm_bk<3, 32>(g, tile, s);
-    default: return launch_gemm_bk<4, 32>(g, tile, s);
+    case 0: return launch_gemm_bk<0, 16>(g, tile, s, general);
+    case 1: return kp >= 5 ? launch_gemm_bk<1, 32>(g, tile, s, general) : launch_gemm_bk<1, 16>(g, tile, s, general);
+    case 2: return launch_gemm_bk<2, 32>(g, tile, s, general);
+    case 3: return launch_gemm_bk<3, 32>(g, tile, s, general);
+    default: return launch_gemm_bk<4, 32>(g, tile, s, general);
   }
 }
 

@@ -32,7 +32,13 @@ hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s);         
 hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
                                   double *root_scale, hipStream_t s);
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
-hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s);
+// general = true: the general kernel even where the long-k kernel applies
+hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s, bool general = false);
+// long-k steps (k >= 512) on 128 x 128 tiles, at least min_tiles of them:
+// the kernel with a deep LDS ring of operand slices (same results as
+// launch_gemm's general kernel)
+bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles);
+hipError_t launch_gemm_long(int prec, const GemmArgs &g, hipStream_t s);
 // persistent final-step GEMM (128 x 128 tiles, K <= 256, float32 output in a
 // layout whose two lowest output bits fall in every tile); hipErrorNotSupported
 // when the step does not qualify

@@ -1,0 +1,302 @@
+// Long-k pairwise contractions (Sec. III-B, Eq. (3): a step that closes
+// many cuts at once sums over 4^c cut assignments, k >= 512).
+//
+// Such a step is bound by the matrix cores, and what keeps the MFMA pipes
+// idle is memory latency: every workgroup needs a new k slice of both
+// operand tiles per MFMA group.  This kernel keeps NS slices in flight:
+//   * the operand tiles go from global memory straight into an NS-stage LDS
+//     ring (global_load_lds_dwordx4: each lane moves 16 bytes, one
+//     instruction fills 1 KiB of LDS), so no registers hold staged data and
+//     the ring can be deep;
+//   * the slice for stage s + NS is requested while stage s is computed, and
+//     one barrier per stage both publishes stage s + 1 and frees the slot of
+//     stage s (its fragments are already in registers);
+//   * the MFMA fragments of stage s + 1 are read from LDS while the MFMAs of
+//     stage s run (two register sets);
+//   * rows are stored with their 16-byte chunks XOR-permuted by row, so that
+//     the fragment reads of 8 (or 16) lanes at a time touch distinct LDS
+//     banks.
+// A 128 x 128 output tile per workgroup of four waves (64 x 64 each, as in
+// the general kernel); the MFMA sequence per accumulator, the float64 fold of
+// every 256-long k chunk and the epilogue are those of the general kernel,
+// so both give the same bits.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_ops.hpp"
+#include "kernels.hpp"
+
+namespace tqc {
+
+namespace {
+
+constexpr int kLBM = 128, kLBN = 128;
+
+// Stage depth by form: float32 and the two-plane 16-bit forms move 128-byte
+// row slices (32 k of float32 in four 32 KiB stages, 64 k of 16-bit values
+// in two 64 KiB stages: every request is one whole cache line); the
+// three-plane form moves 64-byte slices (32 k) in three 48 KiB stages.
+template <int P>
+struct LongShape {
+  using T = PrecTraits<P>;
+  static constexpr int NP = T::planes;
+  static constexpr int ES = sizeof(typename T::E);
+  static constexpr int BK = (P == 1 || NP == 3) ? 32 : 64;  // k per stage
+  static constexpr int KG = T::kgroup;            // k per MFMA group (register set)
+  static constexpr int KH = BK / KG;              // MFMA groups per stage
+  static constexpr int ROWB = BK * ES;            // bytes of one row's k slice per plane
+  static constexpr int CPR = ROWB / 16;           // 16-byte chunks per row slice
+  static constexpr int PLANE_B = kLBM * ROWB;     // one operand plane of a stage
+  static constexpr int IPP = PLANE_B / 1024;      // 1 KiB load instructions per plane
+  static constexpr int STAGE_B = 2 * NP * PLANE_B;
+  static constexpr int IPW = STAGE_B / 1024 / 4;  // load instructions per wave per stage
+  static constexpr int NS = (P == 1) ? 4 : (NP == 3 ? 3 : 2);
+  static constexpr int RING_B = NS * STAGE_B;
+  static constexpr int CT_B = kLBM * kLBN * 4;    // staged float tile of the epilogue
+  static constexpr int MAIN_B = RING_B > CT_B ? RING_B : CT_B;
+  static constexpr int LDS_B = MAIN_B + 64;       // + tile statistics
+  static_assert(LDS_B <= 160 * 1024, "LDS");
+  static_assert(IPW * 4 * 1024 == STAGE_B && 64 % CPR == 0, "whole instructions");
+  static_assert(KH * KG == BK && KG * ES == 64, "an MFMA group reads 64 bytes of a row");
+};
+
+// XOR permutation of the 16-byte chunks of row r (by its low four bits).
+// A fragment read (ds_read_b128) has lane (lr, lg) read row lr of a 16-row
+// block at logical chunk lg (+ 4 for the second MFMA group of a 128-byte
+// row).  The permutations keep the 64 lanes of such a read on distinct
+// banks whichever lanes the LDS serves together: 16 consecutive lanes, lanes
+// 0-7 with 32-39, lanes 0-3 with 16-19, 32-35 and 48-51 (64 banks), or 8
+// consecutive lanes, lanes 0-3 with 32-35 (32 banks) -- checked by
+// enumeration for both row sizes.
+template <int CPR>
+__device__ __host__ inline uint32_t chunk_swz(uint32_t r) {
+  if constexpr (CPR == 8)
+    return ((r & 1u) ? 1u : 0u) ^ ((r & 2u) ? 4u : 0u) ^ ((r & 4u) ? 3u : 0u) ^ ((r & 8u) ? 1u : 0u);
+  else
+    return ((r >> 1) ^ (r >> 2)) & 3u;
+}
+
+// s_waitcnt immediate (gfx9 layout): vector-memory count v, LDS/scalar count
+// l, export count not waited for
+constexpr int waitcnt_imm(int v, int l) { return (v & 15) | (7 << 4) | ((l & 15) << 8) | ((v >> 4) << 14); }
+
+// workgroup barrier that does not wait for outstanding vector-memory
+// operations (the ring's loads stay in flight across it); the empty asm
+// statements keep the compiler from moving memory accesses across it
+__device__ inline void ring_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// one workgroup per CU by design (LDS): let the register allocator use the
+// whole register file instead of trading latency hiding for occupancy
+template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) gemm_long_kernel(GemmArgs g) {
+  using L = LongShape<P>;
+  constexpr int NP = L::NP, NS = L::NS, CPR = L::CPR, IPW = L::IPW, IPP = L::IPP, KH = L::KH;
+  constexpr int FM = 4, FN = 4;
+  __shared__ __attribute__((aligned(1024))) char smem[L::LDS_B];
+
+  const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
+  const uint64_t KP = 1ull << g.kpad;
+  const uint32_t rowstride = (uint32_t)(KP * L::ES);  // bytes per operand row
+  const uint64_t tilesM = M / kLBM, tilesN = N / kLBN;
+  uint64_t tm, tn;
+  tile_of(blockIdx.x, tilesM, tilesN, g.swz, tm, tn);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  // ---- ring fill: instruction n = j * 4 + wave of a stage writes LDS bytes
+  // [n KiB, n + 1 KiB) of the stage: plane region n / IPP = j / (IPP / 4)
+  // (A planes, then B planes), rows (n % IPP) * 64 / CPR ..; lane l moves
+  // chunk position l % CPR of its row, which holds logical chunk
+  // position ^ swz(row)
+  static_assert(IPP % 4 == 0, "a plane region is filled by whole rounds of the four waves");
+  const char *src[IPW];
+  uint32_t soff[IPW];
+#pragma unroll
+  for (int j = 0; j < IPW; ++j) {
+    const int region = j / (IPP / 4), ni = (j % (IPP / 4)) * 4 + wave;
+    const uint32_t r = (uint32_t)(ni * (64 / CPR) + lane / CPR);
+    const uint32_t c = (uint32_t)(lane % CPR) ^ chunk_swz<CPR>(r);
+    const bool isA = region < NP;
+    const int p = isA ? region : region - NP;
+    const void *base = isA ? (p == 0 ? g.a0 : (p == 1 ? g.a1 : g.a2)) : (p == 0 ? g.b0 : (p == 1 ? g.b1 : g.b2));
+    const uint64_t row0 = isA ? tm * kLBM : tn * kLBN;
+    src[j] = (const char *)base + row0 * rowstride;
+    soff[j] = r * rowstride + c * 16u;
+  }
+  const uint32_t nstages = (uint32_t)(KP / L::BK);
+  auto issue = [&](uint32_t s) {
+    char *slot = smem + (s % NS) * L::STAGE_B;
+    const uint32_t kb = s * (uint32_t)L::ROWB;
+#pragma unroll
+    for (int j = 0; j < IPW; ++j)
+      __builtin_amdgcn_global_load_lds((const void *)(src[j] + kb + soff[j]),
+                                       (lds_ptr)(slot + (j * 4 + wave) * 1024), 16, 0, 0);
+  };
+
+  // ---- fragment reads: lane (lr, lg) of block i reads row wm*64 + i*16 + lr,
+  // logical chunk 4h + lg for MFMA group h of the stage
+  uint32_t aoff[FM], boff[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const uint32_t r = (uint32_t)(wm * 64 + i * 16 + lr);
+    aoff[i] = r * L::ROWB + (((uint32_t)lg ^ chunk_swz<CPR>(r)) * 16u);
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const uint32_t r = (uint32_t)(wn * 64 + j * 16 + lr);
+    boff[j] = NP * L::PLANE_B + r * L::ROWB + (((uint32_t)lg ^ chunk_swz<CPR>(r)) * 16u);
+  }
+
+  floatx4 acc[FM][FN];
+  doublex4 acc2[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc[i][j] = floatx4{0, 0, 0, 0};
+      acc2[i][j] = doublex4{0, 0, 0, 0};
+    }
+
+  // two register sets, one MFMA group (16 k of float32, 32 k of 16-bit
+  // values) each; group x = stage x / KH, part x % KH
+  using Frag = typename std::conditional<P == 1, floatx4, bf16x8>::type;
+  Frag fa[2][NP][FM], fb[2][NP][FN];
+  auto read_frags = [&](auto SET, uint32_t x) {
+    constexpr int q = decltype(SET)::value;
+    const char *st = smem + ((x / KH) % NS) * L::STAGE_B;
+    const uint32_t hx = (x % KH) * 64u;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[q][p][i] = *(const Frag *)(st + p * L::PLANE_B + (aoff[i] ^ hx));
+#pragma unroll
+      for (int j = 0; j < FN; ++j) fb[q][p][j] = *(const Frag *)(st + p * L::PLANE_B + (boff[j] ^ hx));
+    }
+  };
+  auto mfmas = [&](auto SET) {
+    constexpr int q = decltype(SET)::value;
+    if constexpr (P == 1) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
+    } else {
+      // per accumulator: the small products first, then the leading one
+      constexpr int NPR = (NP == 3) ? 6 : 3;
+      constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
+      constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
+#pragma unroll
+      for (int pr = 0; pr < NPR; ++pr) {
+        const int x = (NP == 3) ? pa3[pr] : pa2[pr];
+        const int y = (NP == 3) ? pb3[pr] : pb2[pr];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = mfma_split<P>(fa[q][x][i], fb[q][y][j], acc[i][j]);
+      }
+    }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc2[i][j][r] += (double)acc[i][j][r];
+        acc[i][j] = floatx4{0, 0, 0, 0};
+      }
+  };
+
+  // prologue: stages 0 .. NS - 1 requested, group 0 in registers
+#pragma unroll
+  for (int s = 0; s < NS; ++s) issue((uint32_t)s);
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm((NS - 1) * IPW, 15));
+  ring_barrier();
+  read_frags(std::integral_constant<int, 0>{}, 0);
+
+  // group x = c * GPC + u of fold chunk c (256 k): read group x + 1 while
+  // the MFMAs of group x run.  When x + 1 starts stage s + 1: wait for stage
+  // s + 1 (and for this wave's reads of stage s), barrier, request stage
+  // s + NS into the slot of stage s.  After the last group the read of
+  // "group x + 1" touches a stale slot whose values are never used.
+  constexpr int GPC = 256 / L::KG;  // MFMA groups per float64 fold
+  static_assert(GPC % 2 == 0 && GPC % KH == 0, "chunks hold whole stages and register-set pairs");
+  const uint32_t nchunks = (uint32_t)(KP / 256);
+  for (uint32_t c = 0; c < nchunks; ++c) {
+#pragma unroll
+    for (int u = 0; u < GPC; ++u) {
+      const uint32_t x = c * GPC + (uint32_t)u;
+      // the reads of group x have had a whole MFMA group to land: wait for
+      // them before the reads of group x + 1 are issued (the LDS counter
+      // cannot express "all but the last 16")
+      __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
+      if ((u + 1) % KH == 0) {
+        const uint32_t s = x / KH;
+        if (s + NS - 1 < nstages) __builtin_amdgcn_s_waitcnt(waitcnt_imm((NS - 2) * IPW, 0));
+        else __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+        ring_barrier();
+        if (s + NS < nstages) issue(s + NS);
+      }
+      // the scheduler would otherwise sink the reads next to their use and
+      // expose their latency
+      if (u & 1) {
+        read_frags(std::integral_constant<int, 0>{}, x + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(std::integral_constant<int, 1>{});
+      } else {
+        read_frags(std::integral_constant<int, 1>{}, x + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(std::integral_constant<int, 0>{});
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    fold();
+  }
+
+  const bool staged = g.staged && g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC;
+  auto result = [&](int i, int j, int r) -> double { return acc2[i][j][r]; };
+  gemm_epilogue<P, kLBM, kLBN>(g, smem, L::MAIN_B, tm, tn, 0, staged, result);
+}
+
+template <int P>
+hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
+  const uint64_t tiles = (1ull << g.lm) / kLBM * ((1ull << g.ln) / kLBN);
+  if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+  prepare_gemm_args(g, P, kLBM, kLBN);
+  g.ksplit = 0;
+  hipLaunchKernelGGL(gemm_long_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
+  if (prec < 1 || prec > 4) return false;
+  if (g.kpad < 9 || g.lm < 7 || g.ln < 7) return false;  // long k, whole 128 x 128 tiles
+  if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;   // 32-bit row offsets within a tile
+  const uint64_t tiles = (1ull << (g.lm - 7)) << (g.ln - 7);
+  return tiles >= min_tiles;
+}
+
+hipError_t launch_gemm_long(int prec, const GemmArgs &g, hipStream_t s) {
+  switch (prec) {
+    case 1: return launch_long_t<1>(g, s);
+    case 2: return launch_long_t<2>(g, s);
+    case 3: return launch_long_t<3>(g, s);
+    case 4: return launch_long_t<4>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tqc

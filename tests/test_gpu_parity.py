@@ -540,6 +540,55 @@ def test_final_step_kernel(case, form):
     assert ok, (case, form, e)
 
 
+# ----------------------------------------------------- long-k ring kernel
+# steps with k >= 512 on whole 128 x 128 tiles, at least one per CU, run on
+# the kernel with the deep LDS ring; tile_policy = 2 forces the general
+# kernel, whose arithmetic per accumulator is the same
+LONG_CASES = [
+    ([(0, 1)] * 5, [11, 11], "f32"),              # final step, K = 1024, 256 tiles
+    ([(0, 1)] * 6, [12, 10], "f32"),              # final step, K = 4096
+    ([(0, 1)] * 5, [11, 12], "f64"),              # float64 output: the float64 sums scattered
+    ([(0, 1)] * 5 + [(1, 2)], [11, 9, 4], "f32"),  # a long step inside a chain
+]
+
+
+def _long_spec(case):
+    edges, outs, out_dtype = LONG_CASES[case]
+    rng = np.random.default_rng(7100 + case)
+    return synthetic.network_from_edges(int(sum(outs)), len(outs), edges, outs, rng), out_dtype
+
+
+def _long_eligible(st):
+    return (st["log2_k"] >= 9 and st["log2_m"] >= 7 and st["log2_n"] >= 7
+            and st["log2_m"] + st["log2_n"] - 14 >= 8)
+
+
+@pytest.mark.parametrize("case", range(len(LONG_CASES)))
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
+def test_long_k_kernel(case, form):
+    spec, out_dtype = _long_spec(case)
+    N = tqc.Network.from_spec(spec)
+    P0 = tqc.Plan(N, precision=form, out_dtype=out_dtype)
+    assert any(_long_eligible(st) for st in P0.steps), P0.steps
+    P2 = tqc.Plan(N, precision=form, out_dtype=out_dtype, tile_policy=2)
+    a = P0.execute().clone()
+    b = P2.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b), (case, form)
+    # sampled and top entries against the oracle, per-entry rounding bound
+    rng = np.random.default_rng(7200 + case)
+    top = torch.topk(a.abs(), 50).indices.cpu().numpy().astype(np.uint64)
+    xs = np.concatenate([rng.integers(0, 1 << spec.n, size=1500, dtype=np.uint64), top])
+    tens = network_pauli_tensors(spec)
+    ref = entries_variable_elimination(spec, xs, tensors=tens)
+    A = entries_variable_elimination(spec, xs, tensors=[(c, o, np.abs(t)) for c, o, t in tens])
+    got = a[torch.from_numpy(xs.astype(np.int64)).cuda()].double().cpu().numpy()
+    gamma = {"fp32": 2.0 ** -16, "bf16x6": 2.0 ** -16, "bf16x3": 2.0 ** -12, "fp16x3": 2.0 ** -16}[form]
+    floor = 1e-6 * np.abs(ref).max() if form == "fp16x3" else 2.0 ** -149
+    err = np.abs(got - ref)
+    assert np.all(err <= gamma * A + floor), (case, form, (err / A).max())
+
+
 # --------------------------------------------- precision study (2^30 slice)
 def test_precision_network_slice_full_size():
     """6 synthetic tensors, 18 cuts, 34 qubits, 4 fixed: the 2^30 slice in
