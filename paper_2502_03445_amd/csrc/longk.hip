@@ -11,11 +11,13 @@
 //   * the slice for stage s + NS is requested while stage s is computed, and
 //     one barrier per stage both publishes stage s + 1 and frees the slot of
 //     stage s (its fragments are already in registers);
-//   * the MFMA fragments of stage s + 1 are read from LDS while the MFMAs of
-//     stage s run (two register sets);
+//   * the MFMA fragments of the next k group are read from LDS while the
+//     MFMAs of this one run (two register sets); reads, ring loads and MFMAs
+//     are issued interleaved, a few MFMAs between consecutive memory
+//     instructions, so that a wave never stalls on a full LDS or load queue
+//     while it has MFMAs to issue;
 //   * rows are stored with their 16-byte chunks XOR-permuted by row, so that
-//     the fragment reads of 8 (or 16) lanes at a time touch distinct LDS
-//     banks.
+//     fragment reads run without LDS bank conflicts.
 // A 128 x 128 output tile per workgroup of four waves (64 x 64 each, as in
 // the general kernel); the MFMA sequence per accumulator, the float64 fold of
 // every 256-long k chunk and the epilogue are those of the general kernel,
@@ -60,20 +62,17 @@ struct LongShape {
   static_assert(KH * KG == BK && KG * ES == 64, "an MFMA group reads 64 bytes of a row");
 };
 
-// XOR permutation of the 16-byte chunks of row r (by its low four bits).
-// A fragment read (ds_read_b128) has lane (lr, lg) read row lr of a 16-row
-// block at logical chunk lg (+ 4 for the second MFMA group of a 128-byte
-// row).  The permutations keep the 64 lanes of such a read on distinct
-// banks whichever lanes the LDS serves together: 16 consecutive lanes, lanes
-// 0-7 with 32-39, lanes 0-3 with 16-19, 32-35 and 48-51 (64 banks), or 8
-// consecutive lanes, lanes 0-3 with 32-35 (32 banks) -- checked by
-// enumeration for both row sizes.
+// XOR permutation of the 16-byte chunks of row r.  A fragment read
+// (ds_read_b128) has lane (lr, lg) read row lr of a 16-row block at logical
+// chunk lg (+ 4 for the second MFMA group of a 128-byte row).  With the
+// chunk XORed by the row's low three bits (128-byte rows) such reads run
+// without bank conflicts on gfx950, as does the pairwise permutation of
+// 64-byte rows (both measured with the LDS bank-conflict counter; the
+// identity costs 12 extra cycles per read, other permutations 4).
 template <int CPR>
 __device__ __host__ inline uint32_t chunk_swz(uint32_t r) {
-  if constexpr (CPR == 8)
-    return ((r & 1u) ? 1u : 0u) ^ ((r & 2u) ? 4u : 0u) ^ ((r & 4u) ? 3u : 0u) ^ ((r & 8u) ? 1u : 0u);
-  else
-    return ((r >> 1) ^ (r >> 2)) & 3u;
+  if constexpr (CPR == 8) return r & 7u;
+  else return ((r >> 1) ^ (r >> 2)) & 3u;
 }
 
 // s_waitcnt immediate (gfx9 layout): vector-memory count v, LDS/scalar count
@@ -132,6 +131,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     soff[j] = r * rowstride + c * 16u;
   }
   const uint32_t nstages = (uint32_t)(KP / L::BK);
+  auto issue_one = [&](uint32_t s, int j) {
+    char *slot = smem + (s % NS) * L::STAGE_B;
+    __builtin_amdgcn_global_load_lds((const void *)(src[j] + s * (uint32_t)L::ROWB + soff[j]),
+                                     (lds_ptr)(slot + (j * 4 + wave) * 1024), 16, 0, 0);
+  };
   auto issue = [&](uint32_t s) {
     char *slot = smem + (s % NS) * L::STAGE_B;
     const uint32_t kb = s * (uint32_t)L::ROWB;
@@ -181,30 +185,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
       for (int j = 0; j < FN; ++j) fb[q][p][j] = *(const Frag *)(st + p * L::PLANE_B + (boff[j] ^ hx));
     }
   };
-  auto mfmas = [&](auto SET) {
+  // MFMA m of a group, in the order of the general kernel per accumulator:
+  // float32 by k step t, then blocks; the split forms by product, then blocks
+  constexpr int NREAD = NP * (FM + FN);                  // fragment reads per group
+  constexpr int NMF = (P == 1) ? 64 : ((NP == 3) ? 96 : 48);  // MFMAs per group
+  constexpr int MPS = NMF / NREAD;                       // MFMAs per slot
+  static_assert(MPS * NREAD == NMF && IPW <= NREAD, "slots");
+  auto mfma_one = [&](auto SET, int m) {
     constexpr int q = decltype(SET)::value;
+    const int i = (m / 4) % 4, j = m % 4;
     if constexpr (P == 1) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
+      const int t = m / 16;
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
     } else {
-      // per accumulator: the small products first, then the leading one
-      constexpr int NPR = (NP == 3) ? 6 : 3;
       constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
       constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
-#pragma unroll
-      for (int pr = 0; pr < NPR; ++pr) {
-        const int x = (NP == 3) ? pa3[pr] : pa2[pr];
-        const int y = (NP == 3) ? pb3[pr] : pb2[pr];
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) acc[i][j] = mfma_split<P>(fa[q][x][i], fb[q][y][j], acc[i][j]);
-      }
+      const int pr = m / 16;
+      const int x = (NP == 3) ? pa3[pr] : pa2[pr];
+      const int y = (NP == 3) ? pb3[pr] : pb2[pr];
+      acc[i][j] = mfma_split<P>(fa[q][x][i], fb[q][y][j], acc[i][j]);
     }
   };
   auto fold = [&]() {
@@ -241,25 +240,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
       // them before the reads of group x + 1 are issued (the LDS counter
       // cannot express "all but the last 16")
       __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
+      bool dma_here = false;
       if ((u + 1) % KH == 0) {
         const uint32_t s = x / KH;
         if (s + NS - 1 < nstages) __builtin_amdgcn_s_waitcnt(waitcnt_imm((NS - 2) * IPW, 0));
         else __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
         ring_barrier();
-        if (s + NS < nstages) issue(s + NS);
+        dma_here = s + NS < nstages;
       }
-      // the scheduler would otherwise sink the reads next to their use and
-      // expose their latency
-      if (u & 1) {
-        read_frags(std::integral_constant<int, 0>{}, x + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(std::integral_constant<int, 1>{});
-      } else {
-        read_frags(std::integral_constant<int, 1>{}, x + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(std::integral_constant<int, 0>{});
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      // slots: read k of group x + 1, ring load k (at a stage boundary),
+      // then MPS MFMAs of group x; each slot closed by a scheduling fence
+      const uint32_t xn = x + 1;
+      const char *stn = smem + ((xn / KH) % NS) * L::STAGE_B;
+      const uint32_t hx = (xn % KH) * 64u;
+      const uint32_t sN = x / KH + NS;
+      auto body = [&](auto SET) {
+        constexpr int q = decltype(SET)::value;
+#pragma unroll
+        for (int k = 0; k < NREAD; ++k) {
+          {
+            const int p = k / 8, w = k % 8;
+            if (w < 4) fa[1 - q][p][w] = *(const Frag *)(stn + p * L::PLANE_B + (aoff[w] ^ hx));
+            else fb[1 - q][p][w - 4] = *(const Frag *)(stn + p * L::PLANE_B + (boff[w - 4] ^ hx));
+          }
+          if (k < IPW && dma_here) issue_one(sN, k < IPW ? k : 0);
+#pragma unroll
+          for (int m = k * MPS; m < (k + 1) * MPS; ++m) mfma_one(SET, m);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      };
+      if (u & 1) body(std::integral_constant<int, 1>{});
+      else body(std::integral_constant<int, 0>{});
     }
     fold();
   }
