@@ -617,7 +617,7 @@ static hipError_t launch_gemm_t(GemmArgs g, hipStream_t s, bool general) {
   const uint64_t tiles = tilesM * tilesN;
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
   // long k on whole 128 x 128 tiles that fill the device: the deep-ring kernel
-  if (!general && P != 0 && BM == 128 && BN == 128 && gemm_long_eligible(P, g, (uint64_t)device_cus()))
+  if (!general && BM == 128 && BN == 128 && gemm_long_eligible(P, g, (uint64_t)device_cus()))
     return launch_gemm_long(P, g, s);
   prepare_gemm_args(g, P, BM, BN);
   static_assert(S::LDS_BYTES <= 81920, "two workgroups per CU need at most 80 KiB of LDS each");

@@ -34,16 +34,17 @@ namespace {
 
 constexpr int kLBM = 128, kLBN = 128;
 
-// Stage depth by form: float32 and the two-plane 16-bit forms move 128-byte
-// row slices (32 k of float32 in four 32 KiB stages, 64 k of 16-bit values
-// in two 64 KiB stages: every request is one whole cache line); the
-// three-plane form moves 64-byte slices (32 k) in three 48 KiB stages.
+// Stage depth by form: float64, float32 and the two-plane 16-bit forms move
+// 128-byte row slices (16 k of float64 or 32 k of float32 in four 32 KiB
+// stages, 64 k of 16-bit values in two 64 KiB stages: every request is one
+// whole cache line); the three-plane form moves 64-byte slices (32 k) in
+// three 48 KiB stages.
 template <int P>
 struct LongShape {
   using T = PrecTraits<P>;
   static constexpr int NP = T::planes;
   static constexpr int ES = sizeof(typename T::E);
-  static constexpr int BK = (P == 1 || NP == 3) ? 32 : 64;  // k per stage
+  static constexpr int BK = (P == 0) ? 16 : ((P == 1 || NP == 3) ? 32 : 64);  // k per stage
   static constexpr int KG = T::kgroup;            // k per MFMA group (register set)
   static constexpr int KH = BK / KG;              // MFMA groups per stage
   static constexpr int ROWB = BK * ES;            // bytes of one row's k slice per plane
@@ -52,14 +53,14 @@ struct LongShape {
   static constexpr int IPP = PLANE_B / 1024;      // 1 KiB load instructions per plane
   static constexpr int STAGE_B = 2 * NP * PLANE_B;
   static constexpr int IPW = STAGE_B / 1024 / 4;  // load instructions per wave per stage
-  static constexpr int NS = (P == 1) ? 4 : (NP == 3 ? 3 : 2);
+  static constexpr int NS = (P <= 1) ? 4 : (NP == 3 ? 3 : 2);
   static constexpr int RING_B = NS * STAGE_B;
   static constexpr int CT_B = kLBM * kLBN * 4;    // staged float tile of the epilogue
   static constexpr int MAIN_B = RING_B > CT_B ? RING_B : CT_B;
   static constexpr int LDS_B = MAIN_B + 64;       // + tile statistics
   static_assert(LDS_B <= 160 * 1024, "LDS");
   static_assert(IPW * 4 * 1024 == STAGE_B && 64 % CPR == 0, "whole instructions");
-  static_assert(KH * KG == BK && KG * ES == 64, "an MFMA group reads 64 bytes of a row");
+  static_assert(KH * KG == BK && (KH == 1 || KG * ES == 64), "MFMA groups split a row slice in halves");
 };
 
 // XOR permutation of the 16-byte chunks of row r.  A fragment read
@@ -147,73 +148,84 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 
   // ---- fragment reads: lane (lr, lg) of block i reads row wm*64 + i*16 + lr,
   // logical chunk 4h + lg for MFMA group h of the stage
+  constexpr int FH0 = (P == 0) ? 2 : 1;  // 16-byte chunks per fragment of one lane
   uint32_t aoff[FM], boff[FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     const uint32_t r = (uint32_t)(wm * 64 + i * 16 + lr);
-    aoff[i] = r * L::ROWB + (((uint32_t)lg ^ chunk_swz<CPR>(r)) * 16u);
+    aoff[i] = r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<CPR>(r)) * 16u);
   }
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
     const uint32_t r = (uint32_t)(wn * 64 + j * 16 + lr);
-    boff[j] = NP * L::PLANE_B + r * L::ROWB + (((uint32_t)lg ^ chunk_swz<CPR>(r)) * 16u);
+    boff[j] = NP * L::PLANE_B + r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<CPR>(r)) * 16u);
   }
 
-  floatx4 acc[FM][FN];
+  using Acc = typename PrecTraits<P>::Acc;  // float64 accumulates in place, no fold
+  Acc acc[FM][FN];
   doublex4 acc2[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      acc[i][j] = floatx4{0, 0, 0, 0};
+      acc[i][j] = Acc{0, 0, 0, 0};
       acc2[i][j] = doublex4{0, 0, 0, 0};
     }
 
-  // two register sets, one MFMA group (16 k of float32, 32 k of 16-bit
-  // values) each; group x = stage x / KH, part x % KH
-  using Frag = typename std::conditional<P == 1, floatx4, bf16x8>::type;
-  Frag fa[2][NP][FM], fb[2][NP][FN];
-  auto read_frags = [&](auto SET, uint32_t x) {
+  // two register sets, one MFMA group (16 k of float64 or float32, 32 k of
+  // 16-bit values) each; group x = stage x / KH, part x % KH.  A float64
+  // fragment (four k of one row, 32 bytes) is two 16-byte reads: logical
+  // chunks 2 lg and 2 lg + 1, i.e. positions p and p ^ 1.
+  using Frag = typename std::conditional<P == 1, floatx4, typename std::conditional<P == 0, double2v, bf16x8>::type>::type;
+  constexpr int FH = (P == 0) ? 2 : 1;  // 16-byte reads per fragment
+  Frag fa[2][NP][FM][FH], fb[2][NP][FN][FH];
+  auto read_one = [&](auto SET, const char *st, uint32_t hx, int k) {
     constexpr int q = decltype(SET)::value;
+    const int h = k % FH, f = k / FH, p = f / 8, w = f % 8;
+    const uint32_t hb = (uint32_t)h * 16u;
+    if (w < 4) fa[q][p][w][h] = *(const Frag *)(st + p * L::PLANE_B + ((aoff[w] ^ hx) ^ hb));
+    else fb[q][p][w - 4][h] = *(const Frag *)(st + p * L::PLANE_B + ((boff[w - 4] ^ hx) ^ hb));
+  };
+  auto read_frags = [&](auto SET, uint32_t x) {
     const char *st = smem + ((x / KH) % NS) * L::STAGE_B;
     const uint32_t hx = (x % KH) * 64u;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i) fa[q][p][i] = *(const Frag *)(st + p * L::PLANE_B + (aoff[i] ^ hx));
-#pragma unroll
-      for (int j = 0; j < FN; ++j) fb[q][p][j] = *(const Frag *)(st + p * L::PLANE_B + (boff[j] ^ hx));
-    }
+    for (int k = 0; k < NP * 8 * FH; ++k) read_one(SET, st, hx, k);
   };
   // MFMA m of a group, in the order of the general kernel per accumulator:
   // float32 by k step t, then blocks; the split forms by product, then blocks
-  constexpr int NREAD = NP * (FM + FN);                  // fragment reads per group
-  constexpr int NMF = (P == 1) ? 64 : ((NP == 3) ? 96 : 48);  // MFMAs per group
+  constexpr int NREAD = NP * (FM + FN) * FH;             // 16-byte reads per group
+  constexpr int NMF = (P <= 1) ? 64 : ((NP == 3) ? 96 : 48);  // MFMAs per group
   constexpr int MPS = NMF / NREAD;                       // MFMAs per slot
   static_assert(MPS * NREAD == NMF && IPW <= NREAD, "slots");
   auto mfma_one = [&](auto SET, int m) {
     constexpr int q = decltype(SET)::value;
     const int i = (m / 4) % 4, j = m % 4;
-    if constexpr (P == 1) {
+    if constexpr (P == 0) {
       const int t = m / 16;
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][t], fb[q][0][j][t], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[q][0][i][t / 2][t % 2], fb[q][0][j][t / 2][t % 2], acc[i][j], 0,
+                                                      0, 0);
+    } else if constexpr (P == 1) {
+      const int t = m / 16;
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][0][i][0][t], fb[q][0][j][0][t], acc[i][j], 0, 0, 0);
     } else {
       constexpr int pa3[6] = {2, 1, 0, 1, 0, 0}, pb3[6] = {0, 1, 2, 0, 1, 0};
       constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
       const int pr = m / 16;
       const int x = (NP == 3) ? pa3[pr] : pa2[pr];
       const int y = (NP == 3) ? pb3[pr] : pb2[pr];
-      acc[i][j] = mfma_split<P>(fa[q][x][i], fb[q][y][j], acc[i][j]);
+      acc[i][j] = mfma_split<P>(fa[q][x][i][0], fb[q][y][j][0], acc[i][j]);
     }
   };
   auto fold = [&]() {
+    if constexpr (P == 0) return;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc2[i][j][r] += (double)acc[i][j][r];
-        acc[i][j] = floatx4{0, 0, 0, 0};
+        acc[i][j] = Acc{0, 0, 0, 0};
       }
   };
 
@@ -258,11 +270,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
         constexpr int q = decltype(SET)::value;
 #pragma unroll
         for (int k = 0; k < NREAD; ++k) {
-          {
-            const int p = k / 8, w = k % 8;
-            if (w < 4) fa[1 - q][p][w] = *(const Frag *)(stn + p * L::PLANE_B + (aoff[w] ^ hx));
-            else fb[1 - q][p][w - 4] = *(const Frag *)(stn + p * L::PLANE_B + (boff[w - 4] ^ hx));
-          }
+          read_one(std::integral_constant<int, 1 - q>{}, stn, hx, k);
           if (k < IPW && dma_here) issue_one(sN, k < IPW ? k : 0);
 #pragma unroll
           for (int m = k * MPS; m < (k + 1) * MPS; ++m) mfma_one(SET, m);
@@ -275,8 +283,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     fold();
   }
 
-  const bool staged = g.staged && g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC;
-  auto result = [&](int i, int j, int r) -> double { return acc2[i][j][r]; };
+  const bool staged = P != 0 && g.staged && g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC;
+  auto result = [&](int i, int j, int r) -> double {
+    if constexpr (P == 0) return acc[i][j][r];
+    else return acc2[i][j][r];
+  };
   gemm_epilogue<P, kLBM, kLBN>(g, smem, L::MAIN_B, tm, tn, 0, staged, result);
 }
 
@@ -293,7 +304,7 @@ hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
 }  // namespace
 
 bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
-  if (prec < 1 || prec > 4) return false;
+  if (prec < 0 || prec > 4) return false;
   if (g.kpad < 9 || g.lm < 7 || g.ln < 7) return false;  // long k, whole 128 x 128 tiles
   if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;   // 32-bit row offsets within a tile
   const uint64_t tiles = (1ull << (g.lm - 7)) << (g.ln - 7);
@@ -302,6 +313,7 @@ bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
 
 hipError_t launch_gemm_long(int prec, const GemmArgs &g, hipStream_t s) {
   switch (prec) {
+    case 0: return launch_long_t<0>(g, s);
     case 1: return launch_long_t<1>(g, s);
     case 2: return launch_long_t<2>(g, s);
     case 3: return launch_long_t<3>(g, s);

@@ -564,7 +564,7 @@ def _long_eligible(st):
 
 
 @pytest.mark.parametrize("case", range(len(LONG_CASES)))
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3", "bf16x6", "fp16x3"])
 def test_long_k_kernel(case, form):
     spec, out_dtype = _long_spec(case)
     N = tqc.Network.from_spec(spec)
@@ -583,8 +583,15 @@ def test_long_k_kernel(case, form):
     ref = entries_variable_elimination(spec, xs, tensors=tens)
     A = entries_variable_elimination(spec, xs, tensors=[(c, o, np.abs(t)) for c, o, t in tens])
     got = a[torch.from_numpy(xs.astype(np.int64)).cuda()].double().cpu().numpy()
-    gamma = {"fp32": 2.0 ** -16, "bf16x6": 2.0 ** -16, "bf16x3": 2.0 ** -12, "fp16x3": 2.0 ** -16}[form]
+    # float64: K float64 products and sums (K * 2^-53 of A, K <= 4096), plus
+    # the float32 output's own rounding where the output is float32
+    gamma = {"fp64": 2.0 ** -40, "fp32": 2.0 ** -16, "bf16x6": 2.0 ** -16, "bf16x3": 2.0 ** -12,
+             "fp16x3": 2.0 ** -16}[form]
+    # the float32 MFMA accumulators of the other forms keep float32's
+    # subnormal spacing 2^-149 whatever the output type
     floor = 1e-6 * np.abs(ref).max() if form == "fp16x3" else 2.0 ** -149
+    if form == "fp64":
+        floor = 0.0 if out_dtype == "f64" else 2.0 ** -149 + 2.0 ** -24 * np.abs(ref)
     err = np.abs(got - ref)
     assert np.all(err <= gamma * A + floor), (case, form, (err / A).max())
 
