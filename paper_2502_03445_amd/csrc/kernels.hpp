@@ -34,7 +34,7 @@ hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int 
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
 // general = true: the general kernel even where the long-k kernel applies
 hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s, bool general = false);
-// long-k steps (k >= 512) on 128 x 128 tiles, at least min_tiles of them:
+// long-k steps (k >= 512; k >= 256 in float64) on 128 x 128 tiles, at least min_tiles of them:
 // the kernel with a deep LDS ring of operand slices (same results as
 // launch_gemm's general kernel)
 bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles);

@@ -1,5 +1,6 @@
 // Long-k pairwise contractions (Sec. III-B, Eq. (3): a step that closes
-// many cuts at once sums over 4^c cut assignments, k >= 512).
+// many cuts at once sums over 4^c cut assignments, k >= 512; k >= 256 in
+// float64).
 //
 // Such a step is bound by the matrix cores, and what keeps the MFMA pipes
 // idle is memory latency: every workgroup needs a new k slice of both
@@ -305,7 +306,13 @@ hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
 
 bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
   if (prec < 0 || prec > 4) return false;
-  if (g.kpad < 9 || g.lm < 7 || g.ln < 7) return false;  // long k, whole 128 x 128 tiles
+  // k >= 512, or k >= 256 for float64: with 8 or fewer stages per tile the
+  // general kernel's two workgroups per CU hide their prologue and epilogue
+  // behind each other's MFMAs and win (measured), except in float64, where
+  // the general kernel runs one workgroup per CU as well.  (At k = 256 the
+  // single fold chunk equals the general kernel's plain conversion, so the
+  // results stay equal.)  Whole 128 x 128 tiles only.
+  if (g.kpad < (prec == 0 ? 8 : 9) || g.lm < 7 || g.ln < 7) return false;
   if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;   // 32-bit row offsets within a tile
   const uint64_t tiles = (1ull << (g.lm - 7)) << (g.ln - 7);
   return tiles >= min_tiles;
