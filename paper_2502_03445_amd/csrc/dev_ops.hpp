@@ -346,8 +346,12 @@ __device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmAr
   // 4*lg + r for the float32-accumulating MFMAs and row lg + 4*r for the
   // float64 MFMA (measured lane layout of v_mfma_f64_16x16x4f64).
   if (staged) {
-    // 1) accumulators -> LDS at their compact (output-order) tile index
+    // 1) accumulators -> LDS at their compact (output-order) tile index,
+    //    16-byte chunks XOR-swizzled by higher index bits so that the
+    //    scattered single-float writes spread over the LDS banks; float4
+    //    reads at multiples of 4 stay contiguous
     float *ct = (float *)smem;
+    auto swz = [](uint32_t c) { return c ^ ((((c >> 5) ^ (c >> 8) ^ (c >> 11)) & 7u) << 2); };
     __syncthreads();  // operand tiles no longer needed
     constexpr int LBM = __builtin_ctz(BM), LBN = __builtin_ctz(BN);
     uint32_t tcol[FN];
@@ -359,7 +363,7 @@ __device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmAr
       for (int r = 0; r < 4; ++r) {
         const uint32_t trow = (uint32_t)deposit_c<LBM>(wm * WM + i * 16 + 4 * lg + r, g.rankM, LBM);
 #pragma unroll
-        for (int j = 0; j < FN; ++j) ct[trow | tcol[j]] = (float)result(i, j, r);
+        for (int j = 0; j < FN; ++j) ct[swz(trow | tcol[j])] = (float)result(i, j, r);
       }
     __syncthreads();
     // 2) stream the tile out in output order: compact index x maps to the
@@ -375,7 +379,7 @@ __device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmAr
       for (int it = 0; it * 1024 < TT; ++it) {
         const int x = it * 1024 + tid * 4;
         const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
-        const floatx4 v = *(const floatx4 *)(ct + x);
+        const floatx4 v = *(const floatx4 *)(ct + swz((uint32_t)x));
         switch (g.out_kind) {
           case OUT_F32: {
             floatx4 w;
@@ -414,7 +418,7 @@ __device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmAr
       const uint64_t lo = deposit_c<LB>((uint64_t)tid, g.lpos, LB);
       for (int it = 0; it * 256 < TT; ++it) {
         const uint64_t addr = base + lo + deposit_c<(NCB > LB ? NCB - LB : 1), LB>((uint64_t)it, g.lpos, NCB - LB);
-        const float v = ct[it * 256 + tid];
+        const float v = ct[swz((uint32_t)(it * 256 + tid))];
         store_out(g, scale, addr, v);
         if (want_stats) note((double)v * scale);
       }

@@ -66,15 +66,18 @@ struct LongShape {
 
 // XOR permutation of the 16-byte chunks of row r.  A fragment read
 // (ds_read_b128) has lane (lr, lg) read row lr of a 16-row block at logical
-// chunk lg (+ 4 for the second MFMA group of a 128-byte row).  With the
-// chunk XORed by the row's low three bits (128-byte rows) such reads run
-// without bank conflicts on gfx950, as does the pairwise permutation of
-// 64-byte rows (both measured with the LDS bank-conflict counter; the
-// identity costs 12 extra cycles per read, other permutations 4).
-template <int CPR>
+// chunk lg (+ 4 for the second MFMA group of a 128-byte row; float64 reads
+// chunks 2 lg and 2 lg + 1).  The permutations below run these reads
+// without LDS bank conflicts on gfx950: the chunk XORed with the row's low
+// three bits (float32 and 16-bit planes), with those bits rotated (float64)
+// and the pairwise permutation of 64-byte rows (all measured with the LDS
+// bank-conflict counter; the identity costs 12 extra cycles per read, most
+// other permutations tried 4).
+template <int P, int CPR>
 __device__ __host__ inline uint32_t chunk_swz(uint32_t r) {
-  if constexpr (CPR == 8) return r & 7u;
-  else return ((r >> 1) ^ (r >> 2)) & 3u;
+  if constexpr (CPR == 4) return ((r >> 1) ^ (r >> 2)) & 3u;
+  else if constexpr (P == 0) return ((r & 3u) << 1) | ((r >> 2) & 1u);
+  else return r & 7u;
 }
 
 // s_waitcnt immediate (gfx9 layout): vector-memory count v, LDS/scalar count
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   for (int j = 0; j < IPW; ++j) {
     const int region = j / (IPP / 4), ni = (j % (IPP / 4)) * 4 + wave;
     const uint32_t r = (uint32_t)(ni * (64 / CPR) + lane / CPR);
-    const uint32_t c = (uint32_t)(lane % CPR) ^ chunk_swz<CPR>(r);
+    const uint32_t c = (uint32_t)(lane % CPR) ^ chunk_swz<P, CPR>(r);
     const bool isA = region < NP;
     const int p = isA ? region : region - NP;
     const void *base = isA ? (p == 0 ? g.a0 : (p == 1 ? g.a1 : g.a2)) : (p == 0 ? g.b0 : (p == 1 ? g.b1 : g.b2));
@@ -154,12 +157,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     const uint32_t r = (uint32_t)(wm * 64 + i * 16 + lr);
-    aoff[i] = r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<CPR>(r)) * 16u);
+    aoff[i] = r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<P, CPR>(r)) * 16u);
   }
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
     const uint32_t r = (uint32_t)(wn * 64 + j * 16 + lr);
-    boff[j] = NP * L::PLANE_B + r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<CPR>(r)) * 16u);
+    boff[j] = NP * L::PLANE_B + r * L::ROWB + (((uint32_t)(lg * FH0) ^ chunk_swz<P, CPR>(r)) * 16u);
   }
 
   using Acc = typename PrecTraits<P>::Acc;  // float64 accumulates in place, no fold
