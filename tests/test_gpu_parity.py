@@ -552,6 +552,9 @@ LONG_CASES = [
     # K = 256 as the first step of a chain, 1024 tiles (the kernel takes it
     # in float64 only)
     ([(0, 1)] * 4 + [(1, 2)] * 2, [12, 8, 5], "f32", [(0, 1), (3, 2)]),
+    # sliced over one of six cuts: K = 1024 per slice, the final step adds the
+    # four slices into its float64 accumulator
+    ([(0, 1)] * 6, [11, 11], "f32", "sliced"),
 ]
 
 
@@ -571,12 +574,15 @@ def _long_eligible(st, form):
 def test_long_k_kernel(case, form):
     spec, out_dtype = _long_spec(case)
     order = LONG_CASES[case][3]
+    kw = dict(sliced=[2]) if order == "sliced" else dict(order=order)
     N = tqc.Network.from_spec(spec)
-    P0 = tqc.Plan(N, precision=form, out_dtype=out_dtype, order=order)
+    P0 = tqc.Plan(N, precision=form, out_dtype=out_dtype, **kw)
     if not any(_long_eligible(st, form) for st in P0.steps):
         assert case == 4 and form != "fp64", P0.steps
         pytest.skip("K = 256 runs on the general kernel except in float64")
-    P2 = tqc.Plan(N, precision=form, out_dtype=out_dtype, order=order, tile_policy=2)
+    if order == "sliced":
+        assert P0.sliced == [2]
+    P2 = tqc.Plan(N, precision=form, out_dtype=out_dtype, tile_policy=2, **kw)
     a = P0.execute().clone()
     b = P2.execute()
     torch.cuda.synchronize()
