@@ -606,6 +606,16 @@ def test_long_k_kernel(case, form):
         floor = 0.0 if out_dtype == "f64" else 2.0 ** -149 + 2.0 ** -24 * np.abs(ref)
     err = np.abs(got - ref)
     assert np.all(err <= gamma * A + floor), (case, form, (err / A).max())
+    # the summary of the same plan: the long-k final step writes the tile
+    # statistics its top-k and total are read from
+    if order is None:
+        out, idx, val, tot, _ = P0.execute_summary(k=100)
+        torch.cuda.synchronize()
+        assert torch.equal(out, a)
+        ri, rv = tqc.topk(out, 100)
+        assert torch.equal(idx, ri) and torch.equal(val, rv), (case, form)
+        rt = tqc.marginal(out, P0.stats["out_qubits"], []).item()
+        assert abs(tot.item() - rt) <= 1e-12 * max(1.0, out.double().abs().sum().item())
 
 
 # --------------------------------------------- precision study (2^30 slice)
