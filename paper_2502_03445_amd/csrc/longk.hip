@@ -21,8 +21,8 @@
 //     fragment reads run without LDS bank conflicts.
 // A 128 x 128 output tile per workgroup of four waves (64 x 64 each, as in
 // the general kernel); the MFMA sequence per accumulator, the float64 fold of
-// every 256-long k chunk and the epilogue are those of the general kernel,
-// so both give the same bits.
+// every 256-long k chunk (the float32-accumulating forms) and the epilogue
+// are those of the general kernel, so both give the same bits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -297,8 +297,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 
 template <int P>
 hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
+  using L = LongShape<P>;
   const uint64_t tiles = (1ull << g.lm) / kLBM * ((1ull << g.ln) / kLBN);
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+  // the prologue requests NS stages, and k runs in whole 256-long chunks
+  if (g.kpad < 8 || ((1ull << g.kpad) / L::BK) < (uint64_t)L::NS) return hipErrorInvalidValue;
   prepare_gemm_args(g, P, kLBM, kLBN);
   g.ksplit = 0;
   hipLaunchKernelGGL(gemm_long_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, g);
@@ -312,11 +315,11 @@ bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
   // k >= 512, or k >= 256 for float64: with 8 or fewer stages per tile the
   // general kernel's two workgroups per CU hide their prologue and epilogue
   // behind each other's MFMAs and win (measured), except in float64, where
-  // the general kernel runs one workgroup per CU as well.  (At k = 256 the
-  // single fold chunk equals the general kernel's plain conversion, so the
-  // results stay equal.)  Whole 128 x 128 tiles only.
+  // the general kernel runs one workgroup per CU as well.  Whole 128 x 128
+  // tiles only.
   if (g.kpad < (prec == 0 ? 8 : 9) || g.lm < 7 || g.ln < 7) return false;
-  if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;   // 32-bit row offsets within a tile
+  // 32-bit row offsets within a tile: 127 rows x 2^22 k x 8 bytes < 2^32
+  if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;
   const uint64_t tiles = (1ull << (g.lm - 7)) << (g.ln - 7);
   return tiles >= min_tiles;
 }
