@@ -40,12 +40,16 @@ constexpr int kLBM = 128, kLBN = 128;
 // stages, 64 k of 16-bit values in two 64 KiB stages: every request is one
 // whole cache line); the three-plane form moves 64-byte slices (32 k) in
 // three 48 KiB stages.
-template <int P>
+//
+// SHORT: the k = 256 variant of float32 and the two-plane forms, two
+// workgroups per CU (each hides the other's prologue and epilogue): one
+// 256-long chunk, so no float64 fold, and two 32 KiB stages.
+template <int P, bool SHORT = false>
 struct LongShape {
   using T = PrecTraits<P>;
   static constexpr int NP = T::planes;
   static constexpr int ES = sizeof(typename T::E);
-  static constexpr int BK = (P == 0) ? 16 : ((P == 1 || NP == 3) ? 32 : 64);  // k per stage
+  static constexpr int BK = (P == 0) ? 16 : ((P == 1 || NP == 3 || SHORT) ? 32 : 64);  // k per stage
   static constexpr int KG = T::kgroup;            // k per MFMA group (register set)
   static constexpr int KH = BK / KG;              // MFMA groups per stage
   static constexpr int ROWB = BK * ES;            // bytes of one row's k slice per plane
@@ -54,12 +58,13 @@ struct LongShape {
   static constexpr int IPP = PLANE_B / 1024;      // 1 KiB load instructions per plane
   static constexpr int STAGE_B = 2 * NP * PLANE_B;
   static constexpr int IPW = STAGE_B / 1024 / 4;  // load instructions per wave per stage
-  static constexpr int NS = (P <= 1) ? 4 : (NP == 3 ? 3 : 2);
+  static constexpr int NS = SHORT ? 2 : ((P <= 1) ? 4 : (NP == 3 ? 3 : 2));
   static constexpr int RING_B = NS * STAGE_B;
   static constexpr int CT_B = kLBM * kLBN * 4;    // staged float tile of the epilogue
   static constexpr int MAIN_B = RING_B > CT_B ? RING_B : CT_B;
   static constexpr int LDS_B = MAIN_B + 64;       // + tile statistics
-  static_assert(LDS_B <= 160 * 1024, "LDS");
+  static_assert(LDS_B <= (SHORT ? 80 : 160) * 1024, "LDS");
+  static_assert(!SHORT || P == 1 || P == 2 || P == 4, "short variant: float32 and two-plane forms");
   static_assert(IPW * 4 * 1024 == STAGE_B && 64 % CPR == 0, "whole instructions");
   static_assert(KH * KG == BK && (KH == 1 || KG * ES == 64), "MFMA groups split a row slice in halves");
 };
@@ -95,14 +100,14 @@ __device__ inline void ring_barrier() {
 
 typedef __attribute__((address_space(3))) void *lds_ptr;
 
-// one workgroup per CU by design (LDS): let the register allocator use the
-// whole register file instead of trading latency hiding for occupancy
-template <int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) gemm_long_kernel(GemmArgs g) {
-  using L = LongShape<P>;
+// One workgroup per CU by design (LDS): let the register allocator use the
+// whole register file instead of trading latency hiding for occupancy.  The
+// short variant runs two per CU and must fit 256 registers per lane.
+template <int P, bool SHORT>
+__device__ __attribute__((always_inline)) inline void gemm_long_body(const GemmArgs &g, char *smem) {
+  using L = LongShape<P, SHORT>;
   constexpr int NP = L::NP, NS = L::NS, CPR = L::CPR, IPW = L::IPW, IPP = L::IPP, KH = L::KH;
   constexpr int FM = 4, FN = 4;
-  __shared__ __attribute__((aligned(1024))) char smem[L::LDS_B];
 
   const uint64_t M = 1ull << g.lm, N = 1ull << g.ln;
   const uint64_t KP = 1ull << g.kpad;
@@ -222,7 +227,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
   };
   auto fold = [&]() {
-    if constexpr (P == 0) return;
+    if constexpr (P == 0 || SHORT) return;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -289,22 +294,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 
   const bool staged = P != 0 && g.staged && g.out_kind != OUT_F64 && g.out_kind != OUT_F64_ACC;
   auto result = [&](int i, int j, int r) -> double {
-    if constexpr (P == 0) return acc[i][j][r];
+    if constexpr (P == 0 || SHORT) return acc[i][j][r];
     else return acc2[i][j][r];
   };
   gemm_epilogue<P, kLBM, kLBN>(g, smem, L::MAIN_B, tm, tn, 0, staged, result);
 }
 
 template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) gemm_long_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(1024))) char smem[LongShape<P>::LDS_B];
+  gemm_long_body<P, false>(g, smem);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) gemm_short_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(1024))) char smem[LongShape<P, true>::LDS_B];
+  gemm_long_body<P, true>(g, smem);
+}
+
+template <int P, bool SHORT>
 hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
-  using L = LongShape<P>;
+  using L = LongShape<P, SHORT>;
   const uint64_t tiles = (1ull << g.lm) / kLBM * ((1ull << g.ln) / kLBN);
   if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
   // the prologue requests NS stages, and k runs in whole 256-long chunks
+  // (exactly one for the short variant)
   if (g.kpad < 8 || ((1ull << g.kpad) / L::BK) < (uint64_t)L::NS) return hipErrorInvalidValue;
+  if (SHORT && g.kpad != 8) return hipErrorInvalidValue;
   prepare_gemm_args(g, P, kLBM, kLBN);
   g.ksplit = 0;
-  hipLaunchKernelGGL(gemm_long_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, g);
+  if constexpr (SHORT)
+    hipLaunchKernelGGL(gemm_short_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(gemm_long_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -312,12 +334,13 @@ hipError_t launch_long_t(GemmArgs g, hipStream_t s) {
 
 bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
   if (prec < 0 || prec > 4) return false;
-  // k >= 512, or k >= 256 for float64: with 8 or fewer stages per tile the
-  // general kernel's two workgroups per CU hide their prologue and epilogue
-  // behind each other's MFMAs and win (measured), except in float64, where
-  // the general kernel runs one workgroup per CU as well.  Whole 128 x 128
-  // tiles only.
-  if (g.kpad < (prec == 0 ? 8 : 9) || g.lm < 7 || g.ln < 7) return false;
+  // k >= 256 on whole 128 x 128 tiles.  At k = 256 the one-workgroup-per-CU
+  // kernel loses to the general kernel, whose two workgroups per CU hide
+  // their prologue and epilogue behind each other's MFMAs (measured), except
+  // in float64, where the general kernel runs one per CU as well; the other
+  // forms take the short variant there (two per CU), bf16x6 (too many
+  // registers for it) keeps the general kernel.
+  if (g.kpad < (prec == 3 ? 9 : 8) || g.lm < 7 || g.ln < 7) return false;
   // 32-bit row offsets within a tile: 127 rows x 2^22 k x 8 bytes < 2^32
   if ((uint64_t)1 << g.kpad > (1ull << 22)) return false;
   const uint64_t tiles = (1ull << (g.lm - 7)) << (g.ln - 7);
@@ -325,12 +348,13 @@ bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
 }
 
 hipError_t launch_gemm_long(int prec, const GemmArgs &g, hipStream_t s) {
+  const bool sh = g.kpad == 8 && prec != 0;
   switch (prec) {
-    case 0: return launch_long_t<0>(g, s);
-    case 1: return launch_long_t<1>(g, s);
-    case 2: return launch_long_t<2>(g, s);
-    case 3: return launch_long_t<3>(g, s);
-    case 4: return launch_long_t<4>(g, s);
+    case 0: return launch_long_t<0, false>(g, s);
+    case 1: return sh ? launch_long_t<1, true>(g, s) : launch_long_t<1, false>(g, s);
+    case 2: return sh ? launch_long_t<2, true>(g, s) : launch_long_t<2, false>(g, s);
+    case 3: return launch_long_t<3, false>(g, s);
+    case 4: return sh ? launch_long_t<4, true>(g, s) : launch_long_t<4, false>(g, s);
     default: return hipErrorInvalidValue;
   }
 }
