@@ -406,6 +406,28 @@ __device__ __attribute__((always_inline)) inline void gemm_epilogue(const GemmAr
               for (int e = 0; e < 4; ++e) note((double)v[e] * scale);
             break;
           }
+          case OUT_SPLIT2:
+          case OUT_SPLIT3: {
+            // the next step's bfloat16 planes: the four values of each plane
+            // in one 8-byte store (addr is a multiple of 4 here), so a
+            // wave's store covers whole lines
+            uint32_t h[2] = {0, 0}, m[2] = {0, 0}, l[2] = {0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float f = (float)((double)v[e] * scale);
+              const uint16_t hi = f32_to_bf16_rne(f);
+              const float r1 = f - bf16_to_f32(hi);
+              const uint16_t b1 = f32_to_bf16_rne(r1);
+              h[e >> 1] |= (uint32_t)hi << (16 * (e & 1));
+              m[e >> 1] |= (uint32_t)b1 << (16 * (e & 1));
+              if (g.out_kind == OUT_SPLIT3)
+                l[e >> 1] |= (uint32_t)f32_to_bf16_rne(r1 - bf16_to_f32(b1)) << (16 * (e & 1));
+            }
+            *(uint2 *)((uint16_t *)g.c0 + addr) = uint2{h[0], h[1]};
+            *(uint2 *)((uint16_t *)g.c1 + addr) = uint2{m[0], m[1]};
+            if (g.out_kind == OUT_SPLIT3) *(uint2 *)((uint16_t *)g.c2 + addr) = uint2{l[0], l[1]};
+            break;
+          }
           default: {
 #pragma unroll
             for (int e = 0; e < 4; ++e) store_out(g, scale, addr + e, v[e]);
