@@ -41,9 +41,10 @@ constexpr int kLBM = 128, kLBN = 128;
 // whole cache line); the three-plane form moves 64-byte slices (32 k) in
 // three 48 KiB stages.
 //
-// SHORT: the k = 256 variant of float32 and the two-plane forms, two
-// workgroups per CU (each hides the other's prologue and epilogue): one
-// 256-long chunk, so no float64 fold, and two 32 KiB stages.
+// SHORT: the k = 256 variant of float64, float32 and the two-plane forms,
+// two workgroups per CU (each hides the other's prologue and epilogue): one
+// 256-long chunk, so no float64 fold, and two 32 KiB stages; float64 keeps
+// one fragment register set (the other workgroup's waves cover the reads).
 template <int P, bool SHORT = false>
 struct LongShape {
   using T = PrecTraits<P>;
@@ -64,7 +65,7 @@ struct LongShape {
   static constexpr int MAIN_B = RING_B > CT_B ? RING_B : CT_B;
   static constexpr int LDS_B = MAIN_B + 64;       // + tile statistics
   static_assert(LDS_B <= (SHORT ? 80 : 160) * 1024, "LDS");
-  static_assert(!SHORT || P == 1 || P == 2 || P == 4, "short variant: float32 and two-plane forms");
+  static_assert(!SHORT || P != 3, "short variant: not the three-plane form");
   static_assert(IPW * 4 * 1024 == STAGE_B && 64 % CPR == 0, "whole instructions");
   static_assert(KH * KG == BK && (KH == 1 || KG * ES == 64), "MFMA groups split a row slice in halves");
 };
@@ -187,7 +188,9 @@ __device__ __attribute__((always_inline)) inline void gemm_long_body(const GemmA
   // chunks 2 lg and 2 lg + 1, i.e. positions p and p ^ 1.
   using Frag = typename std::conditional<P == 1, floatx4, typename std::conditional<P == 0, double2v, bf16x8>::type>::type;
   constexpr int FH = (P == 0) ? 2 : 1;  // 16-byte reads per fragment
-  Frag fa[2][NP][FM][FH], fb[2][NP][FN][FH];
+  constexpr bool ONESET = P == 0 && SHORT;
+  constexpr int NSET = ONESET ? 1 : 2;
+  Frag fa[NSET][NP][FM][FH], fb[NSET][NP][FN][FH];
   auto read_one = [&](auto SET, const char *st, uint32_t hx, int k) {
     constexpr int q = decltype(SET)::value;
     const int h = k % FH, f = k / FH, p = f / 8, w = f % 8;
@@ -286,7 +289,23 @@ __device__ __attribute__((always_inline)) inline void gemm_long_body(const GemmA
           __builtin_amdgcn_sched_barrier(0);
         }
       };
-      if (u & 1) body(std::integral_constant<int, 1>{});
+      // one register set: this group's MFMAs (with the ring loads between
+      // them), then the reads of the next group into the same registers
+      auto body1 = [&]() {
+        constexpr auto S0 = std::integral_constant<int, 0>{};
+#pragma unroll
+        for (int k = 0; k < NREAD; ++k) {
+          if (k < IPW && dma_here) issue_one(sN, k < IPW ? k : 0);
+#pragma unroll
+          for (int m = k * MPS; m < (k + 1) * MPS; ++m) mfma_one(S0, m);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NREAD; ++k) read_one(S0, stn, hx, k);
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      if constexpr (ONESET) body1();
+      else if (u & 1) body(std::integral_constant<int, 1>{});
       else body(std::integral_constant<int, 0>{});
     }
     fold();
@@ -348,9 +367,9 @@ bool gemm_long_eligible(int prec, const GemmArgs &g, uint64_t min_tiles) {
 }
 
 hipError_t launch_gemm_long(int prec, const GemmArgs &g, hipStream_t s) {
-  const bool sh = g.kpad == 8 && prec != 0;
+  const bool sh = g.kpad == 8;
   switch (prec) {
-    case 0: return launch_long_t<0, false>(g, s);
+    case 0: return sh ? launch_long_t<0, true>(g, s) : launch_long_t<0, false>(g, s);
     case 1: return sh ? launch_long_t<1, true>(g, s) : launch_long_t<1, false>(g, s);
     case 2: return sh ? launch_long_t<2, true>(g, s) : launch_long_t<2, false>(g, s);
     case 3: return launch_long_t<3, false>(g, s);
