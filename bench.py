@@ -243,6 +243,9 @@ BATCH_MODES = {"graph_4streams": dict(use_graph=True, streams=4),
                "graph_grouped": dict(use_graph=True, grouped=True),
                "graph_grouped_2waves": dict(use_graph=True, grouped=True, waves=2),
                "graph_grouped_4waves": dict(use_graph=True, grouped=True, waves=4),
+               "graph_heads_4waves": dict(use_graph=True, grouped="heads", waves=4, streams=8),
+               "graph_heads_8waves": dict(use_graph=True, grouped="heads", waves=8, streams=8),
+               "graph_heads_16waves": dict(use_graph=True, grouped="heads", waves=16, streams=8),
                "sequential_plain": dict(use_graph=False, streams=1)}
 
 

@@ -436,8 +436,8 @@ tqc_status tqc_network_select_states(tqc_network_t net, const int32_t *counts, c
  * tqc_multi_job_times then waits for the last execute and gives each job's
  * start and end in ms after that execute began (num_jobs doubles in each
  * array; either may be NULL).  Errors: INVALID_ARG (also job times without
- * timed, or before any execute), UNSUPPORTED (sliced plan), SHAPE,
- * OUT_OF_MEMORY, DEVICE (also a failed capture). */
+ * timed, or before any execute, and grouped outside 0..2), UNSUPPORTED
+ * (sliced plan), SHAPE, OUT_OF_MEMORY, DEVICE (also a failed capture). */
 typedef struct tqc_multi_s *tqc_multi_t;
 tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams,
@@ -457,18 +457,28 @@ tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *con
  * the same workgroup of that launch would, so results equal tqc_execute's
  * bit for bit.  num_streams is unused in this mode.  With timed = 1 every
  * job starts with the first launch and ends with the launch that runs its
- * final step.  tqc_multi_info: launches per execute (-1 unless grouped),
- * final steps in shared persistent launches, and those launches. */
+ * final step.  grouped = 2 (grouped heads): only the launches before the
+ * pairwise steps are shared, per wave (transform passes, per-entry
+ * transforms, scales, leaf packs of the wave's jobs), the waves one after
+ * another on one extra stream; each job's pairwise steps and final step are
+ * its own launches, as tqc_execute makes them, on one of num_streams worker
+ * streams (each wave's jobs, largest first, to the least-loaded stream),
+ * after its wave's shared launches; job times as without grouping.
+ * tqc_multi_info: launches per execute (-1 unless grouped; with grouped
+ * heads the shared launches only), final steps in shared persistent
+ * launches, and those launches. */
 typedef struct {
   int32_t use_graph;      /* as tqc_multi_create                          */
   int32_t num_streams;    /* as tqc_multi_create (0 = 4, at most 16)       */
   int32_t timed;          /* as tqc_multi_create                          */
-  int32_t grouped;        /* 1: every kind of work in shared launches     */
+  int32_t grouped;        /* 1: every kind of work in shared launches;
+                             2: the launches before the pairwise steps  */
   int32_t waves;          /* grouped: the jobs split into this many waves
                              of about equal predicted cost (0 = 1), each a
                              launch list on its own stream; wave w + 1's
                              launches start when wave w's launches before
-                             its final steps are done                    */
+                             its final steps are done (grouped = 2: when
+                             wave w's shared launches are done)          */
 } tqc_multi_options;
 tqc_status tqc_multi_create_ex(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                                const uint64_t *out_bytes, const tqc_multi_options *opt, void *stream,

@@ -616,7 +616,11 @@ class Multi:
     """Independent unsliced reconstructions replayed as one HIP graph
     (``use_graph``) or enqueued as plain launches, spread over ``streams``
     streams; ``streams=1, use_graph=False`` runs them one after another.
-    Outputs equal each plan's own ``execute`` bit for bit."""
+    ``grouped=True``: every kind of work of all jobs in shared launches, in
+    ``waves`` waves; ``grouped="heads"``: only the launches before the
+    pairwise steps shared (per wave), each job's pairwise steps and final
+    step its own launches on ``streams`` worker streams.  Outputs equal each
+    plan's own ``execute`` bit for bit."""
 
     def __init__(self, plans, outs=None, use_graph=True, streams=4, timed=False, stream=None,
                  grouped=False, waves=1):
@@ -633,7 +637,8 @@ class Multi:
         oh = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
         ob = (ctypes.c_uint64 * n)(*[o.numel() * o.element_size() for o in self.outs])
         h = ctypes.c_void_p()
-        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), int(bool(grouped)), int(waves))
+        g = 2 if grouped == "heads" else int(bool(grouped))
+        opt = MultiOptions(int(bool(use_graph)), int(streams), int(self.timed), g, int(waves))
         _check(L.tqc_multi_create_ex(n, ph, oh, ob, ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 

@@ -261,8 +261,14 @@ static ScratchLease stream_scratch(uint64_t bytes, hipStream_t s) {
 // two scratch buffers of `scr_bytes` each so that the last pass lands in dst.
 // Appends pass i of the tensor to levels[i]; passes of one level (of
 // different tensors) share a launch, and levels run in order.
+// AbsMax (optional): the last pass also takes the abs-max of what it writes.
+struct AbsMaxOut {
+  unsigned long long *p = nullptr;
+  uint64_t mask = 0, base = 0;
+};
+
 static void schedule_passes(const TensorIn &t, double *dst, double *s0, double *s1, uint64_t scr_bytes,
-                            std::vector<std::vector<TransformPassArgs>> &levels) {
+                            std::vector<std::vector<TransformPassArgs>> &levels, AbsMaxOut am = {}) {
   const TransformSchedule sc = transform_schedule(t);
   const int P = (int)sc.passes.size();
   if (P > 1 && sc.max_intermediate * 8 > scr_bytes) fail(TQC_ERR_INTERNAL, "transform scratch too small");
@@ -273,13 +279,27 @@ static void schedule_passes(const TensorIn &t, double *dst, double *s0, double *
     double *out = i == P - 1 ? dst : ((P - 2 - i) % 2 == 0 ? s0 : s1);
     a.in = in;
     a.out = out;
+    if (i == P - 1) {
+      a.amax = am.p;
+      a.amask = am.mask;
+      a.abase = am.base;
+    }
     levels[i].push_back(a);
     in = out;
   }
 }
 
-static void launch_levels(const std::vector<std::vector<TransformPassArgs>> &levels, hipStream_t s) {
-  for (const auto &lv : levels) HIP_OK(launch_transform_passes(lv.data(), (int)lv.size(), s));
+// zero (optional): cleared by the first level's launch, which holds no
+// tensor's last pass (every tensor on passes has at least two)
+static void launch_levels(const std::vector<std::vector<TransformPassArgs>> &levels, hipStream_t s,
+                          unsigned long long *zero = nullptr, int nzero = 0) {
+  for (size_t L = 0; L < levels.size(); ++L) {
+    if (L == 0 && zero)
+      for (const auto &a : levels[0])
+        if (a.amax) fail(TQC_ERR_INTERNAL, "a one-pass transform in the clearing launch");
+    HIP_OK(launch_transform_passes(levels[L].data(), (int)levels[L].size(), s, L == 0 ? zero : nullptr,
+                                   L == 0 ? nzero : 0));
+  }
 }
 
 static void transform_tensor(const TensorIn &t, double *out, hipStream_t s) {
@@ -408,12 +428,9 @@ static ScaleBuf scale_buffers(Plan *p) {
                   (unsigned long long *)(b + 16)};
 }
 
-static std::vector<AbsMaxArgs> absmax_records(Plan *p, const ScaleBuf &sb) {
-  Network &net = *p->net;
-  const int m = net.m;
-  std::vector<AbsMaxArgs> all(m);
-  for (int j = 0; j < m; ++j) {
-    const TensorIn &t = net.t[j];
+static AbsMaxArgs absmax_record(Plan *p, const ScaleBuf &sb, int j) {
+  {
+    const TensorIn &t = p->net->t[j];
     PackArgs pa = make_pack_args(p, j, nullptr, nullptr, nullptr, 0, 0);
     AbsMaxArgs a{};
     a.src = t.dev_pauli;
@@ -436,17 +453,30 @@ static std::vector<AbsMaxArgs> absmax_records(Plan *p, const ScaleBuf &sb) {
     // positions make consecutive threads read consecutive addresses (the
     // packing order puts the cut digits, the slowest source bits, first)
     std::sort(a.inpos, a.inpos + a.nbits);
-    all[j] = a;
+    return a;
   }
-  return all;
 }
 
-static void compute_scales(Plan *p, const ScaleBuf &sb, hipStream_t s) {
-  const int m = p->net->m;
-  HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
-  const std::vector<AbsMaxArgs> all = absmax_records(p, sb);
-  HIP_OK(launch_absmax(all.data(), m, s));
-  HIP_OK(launch_scale_exponents(sb.maxbits, m, p->net->K, sb.exps, sb.root_scale, s));
+// The abs-max of leaf j as the transform that writes its Pauli tensor can
+// take it: over the entries whose fixed output bits (the lowest bits of a
+// Pauli index) hold their values.  Empty when leaf j's gathered entries are
+// not exactly those, or it is not transformed.
+static AbsMaxOut fused_absmax(Plan *p, const ScaleBuf &sb, int j) {
+  const TensorIn &t = p->net->t[j];
+  if (t.basis != TQC_BASIS_RAW) return {};
+  const AbsMaxArgs a = absmax_record(p, sb, j);
+  const int c = (int)t.cuts.size(), o = (int)t.outputs.size();
+  AbsMaxOut am;
+  int nfixed = 0;
+  for (int i = 0; i < o; ++i)
+    if (std::find(p->fixed_q.begin(), p->fixed_q.end(), t.outputs[i]) != p->fixed_q.end()) {
+      am.mask |= 1ull << i;
+      ++nfixed;
+    }
+  if (a.nbits != 2 * c + o - nfixed) return {};
+  am.p = a.out;
+  am.base = a.base;
+  return am;
 }
 
 static TransformArgs make_transform_args(const TensorIn &t, double *out) {
@@ -571,11 +601,56 @@ static bool root_on_persistent(const Plan *p, const Step &st, const GemmArgs &g)
   return st.root && st.tile == 0 && p->tile_policy != 2 && root_gemm_eligible(step_prec(p, st), g);
 }
 
+// The pairwise steps of one slice of a plan whose leaf operands are packed:
+// every step for the first slice, only the slice-dependent ones after it.
+// store_first: the final step stores where the run accumulates (its first
+// slice of a float64 accumulation).
+static void run_steps(Plan *p, void *root_out, int root_kind, const ScaleBuf &sb, bool first, bool store_first,
+                      hipStream_t s, Timing *tm, unsigned long long *tkey, double *tsum, bool defer_root) {
+  for (size_t si = 0; si < p->steps.size(); ++si) {
+    const Step &st = p->steps[si];
+    Node &on = p->nodes[st.out];
+    if (!first && !on.slice_dep) continue;
+    GemmArgs g = make_gemm_args(p, st, root_out, root_kind, sb.root_scale);
+    if (st.root && store_first) g.out_kind = OUT_F64;
+    if (st.root && tkey) {
+      g.tkey = tkey;
+      g.tsum = tsum;
+    }
+    if (tm) tm->begin(2 + (int)si);
+    const int sp = step_prec(p, st);
+    if (st.root && p->prec == Prec::F16X3) {
+      // float32 operands of the final step -> two float16 planes each
+      const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
+      char *ha = (char *)p->ws + p->h16_off[0], *hb = (char *)p->ws + p->h16_off[1];
+      HIP_OK(launch_f16_split((const float *)((char *)p->ws + na.offset), na.elems(), (uint16_t *)ha,
+                              (uint16_t *)(ha + p->h16_plane[0]), (const float *)((char *)p->ws + nb.offset),
+                              nb.elems(), (uint16_t *)hb, (uint16_t *)(hb + p->h16_plane[1]), sb.maxbits16,
+                              sb.root_scale, sb.root_scale2, s));
+    }
+    if (root_on_persistent(p, st, g)) {
+      // deferred: the caller runs it in a launch shared with other jobs
+      if (!defer_root) HIP_OK(launch_root_gemm(sp, g, s));
+    } else {
+      HIP_OK(launch_gemm(sp, g, st.tile, s, p->tile_policy == 2));
+    }
+    if (tm) tm->end();
+  }
+}
+
 static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint64_t s1,
                        bool accumulate_first, hipStream_t s, Timing *tm = nullptr,
                        unsigned long long *tkey = nullptr, double *tsum = nullptr, bool defer_root = false) {
   Network &net = *p->net;
   const int m = net.m;
+  // operand scales (two or more tensors): the transform that writes a
+  // leaf's Pauli tensor also takes its abs-max, and the first pack launch
+  // turns the maxima into exponents and the output scale; a leaf given in
+  // the Pauli basis gets an abs-max launch of its own
+  const bool scaled = m >= 2;
+  ScaleBuf sb{};
+  if (scaled) sb = scale_buffers(p);
+  std::vector<AbsMaxArgs> unfused;
   if (tm) tm->begin(0);
   {
     // tensors with several cuts: separable passes; the rest: the per-entry
@@ -584,15 +659,26 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
     std::vector<std::vector<TransformPassArgs>> levels;
     for (int j = 0; j < m; ++j) {
       TensorIn &t = net.t[j];
+      const AbsMaxOut am = scaled ? fused_absmax(p, sb, j) : AbsMaxOut{};
+      if (scaled && !am.p) unfused.push_back(absmax_record(p, sb, j));
       if (t.basis != TQC_BASIS_RAW) continue;
       if ((int)t.cuts.size() >= kPassMinCuts) {
         char *b = (char *)p->ws + p->tscr_off[j];
-        schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], levels);
+        schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], levels,
+                        am);
       } else {
-        ta.push_back(make_transform_args(t, t.dev_pauli));
+        TransformArgs a = make_transform_args(t, t.dev_pauli);
+        a.amax = am.p;
+        a.amask = am.mask;
+        a.abase = am.base;
+        ta.push_back(a);
       }
     }
-    launch_levels(levels, s);
+    // the maxima start from zero: cleared by the first pass level's launch,
+    // else by a launch of their own, before any transform writes
+    const bool fold = scaled && !levels.empty();
+    if (scaled && !fold) HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
+    launch_levels(levels, s, fold ? sb.maxbits : nullptr, fold ? m : 0);
     if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
   }
   if (tm) tm->end();
@@ -604,10 +690,12 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
     return;
   }
   bool first_done = false;
-  const ScaleBuf sb = scale_buffers(p);
-  if (tm) tm->begin(1);
-  compute_scales(p, sb, s);
-  if (tm) tm->end();
+  if (!unfused.empty()) {
+    if (tm) tm->begin(1);
+    HIP_OK(launch_absmax(unfused.data(), (int)unfused.size(), s));
+    if (tm) tm->end();
+  }
+  const ScaleRec sr{sb.maxbits, m, net.K, sb.exps, sb.root_scale};
   for (uint64_t sl = s0; sl < s1; ++sl) {
     const bool first = (sl == s0);
     if (tm) tm->begin(1);
@@ -617,40 +705,13 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
       if (!first && !nd.slice_dep) continue;
       char *b = (char *)p->ws + nd.offset;
       packs.push_back(make_pack_args(p, j, b, nd.planes > 1 ? b + nd.plane_bytes : nullptr,
-                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pack_prec(p), sl,
-                                     sb.exps + j));
+                                     nd.planes > 2 ? b + 2 * nd.plane_bytes : nullptr, pack_prec(p), sl));
+      packs.back().dmax = sb.maxbits + j;
     }
-    if (!packs.empty()) HIP_OK(launch_packs(packs.data(), (int)packs.size(), s));
+    if (!packs.empty()) HIP_OK(launch_packs(packs.data(), (int)packs.size(), s, first ? &sr : nullptr));
     if (tm) tm->end();
-    for (size_t si = 0; si < p->steps.size(); ++si) {
-      const Step &st = p->steps[si];
-      Node &on = p->nodes[st.out];
-      if (!first && !on.slice_dep) continue;
-      GemmArgs g = make_gemm_args(p, st, root_out, root_kind, sb.root_scale);
-      if (st.root && root_kind == OUT_F64_ACC && !accumulate_first && !first_done) g.out_kind = OUT_F64;
-      if (st.root && tkey) {
-        g.tkey = tkey;
-        g.tsum = tsum;
-      }
-      if (tm) tm->begin(2 + (int)si);
-      const int sp = step_prec(p, st);
-      if (st.root && p->prec == Prec::F16X3) {
-        // float32 operands of the final step -> two float16 planes each
-        const Node &na = p->nodes[st.a], &nb = p->nodes[st.b];
-        char *ha = (char *)p->ws + p->h16_off[0], *hb = (char *)p->ws + p->h16_off[1];
-        HIP_OK(launch_f16_split((const float *)((char *)p->ws + na.offset), na.elems(), (uint16_t *)ha,
-                                (uint16_t *)(ha + p->h16_plane[0]), (const float *)((char *)p->ws + nb.offset),
-                                nb.elems(), (uint16_t *)hb, (uint16_t *)(hb + p->h16_plane[1]), sb.maxbits16,
-                                sb.root_scale, sb.root_scale2, s));
-      }
-      if (root_on_persistent(p, st, g)) {
-        // deferred: the caller runs it in a launch shared with other jobs
-        if (!defer_root) HIP_OK(launch_root_gemm(sp, g, s));
-      } else {
-        HIP_OK(launch_gemm(sp, g, st.tile, s, p->tile_policy == 2));
-      }
-      if (tm) tm->end();
-    }
+    const bool store_first = root_kind == OUT_F64_ACC && !accumulate_first && !first_done;
+    run_steps(p, root_out, root_kind, sb, first, store_first, s, tm, tkey, tsum, defer_root);
     first_done = true;
   }
 }
@@ -930,7 +991,7 @@ static BatchTables build_batch_tables(int njobs, Plan *const *plans, void *const
     }
     const int leaf0 = T.job_leaf0.back();
     if (m >= 2) {
-      // abs-max of every leaf, as in compute_scales
+      // abs-max of every leaf (its gathered entries, all slices)
       for (int t = 0; t < m; ++t) {
         const TensorIn &ti = net.t[t];
         PackArgs pa = make_pack_args(p, t, nullptr, nullptr, nullptr, 0, 0);
@@ -1795,6 +1856,11 @@ struct Multi {
   // (built at creation, replayed by each execute); stamp slot of each step
   // and, per job, the step that completes it
   bool grouped = false;
+  // grouped heads: only the launches before the pairwise steps are shared
+  // (one list per wave on the last stream); every job then runs its own
+  // pairwise steps and final step on its worker stream
+  bool heads_only = false;
+  std::vector<std::vector<int>> wave_jobs;  // jobs of each wave, largest first
   struct Wave {
     std::vector<std::function<void(hipStream_t)>> steps;  // up to the final steps
     std::vector<std::function<void(hipStream_t)>> roots;  // shared persistent final steps
@@ -1830,7 +1896,7 @@ struct JobOps {
   std::vector<TransformArgs> transforms;
   bool scaled = false;  // m >= 2: zero / abs-max / exponents
   ZeroRec zero{};
-  std::vector<AbsMaxArgs> absmax;
+  std::vector<AbsMaxArgs> absmax;  // leaves whose abs-max no transform takes
   ScaleRec scale{};
   std::vector<PackArgs> packs;
   struct GemmOp {
@@ -1854,24 +1920,34 @@ static JobOps job_ops(Plan *p, void *out) {
   Network &net = *p->net;
   const int m = net.m;
   const int root_kind = p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32;
+  // as in a plan's own execution: the transforms take the abs-max of the
+  // leaves they write, the others get abs-max records
+  const bool scaled = m >= 2;
+  ScaleBuf sb{};
+  if (scaled) sb = scale_buffers(p);
   for (int j = 0; j < m; ++j) {
     TensorIn &t = net.t[j];
+    const AbsMaxOut am = scaled ? fused_absmax(p, sb, j) : AbsMaxOut{};
+    if (scaled && !am.p) o.absmax.push_back(absmax_record(p, sb, j));
     if (t.basis != TQC_BASIS_RAW) continue;
     if ((int)t.cuts.size() >= kPassMinCuts) {
       char *b = (char *)p->ws + p->tscr_off[j];
-      schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], o.pass_levels);
+      schedule_passes(t, t.dev_pauli, (double *)b, (double *)(b + p->tscr_bytes[j]), p->tscr_bytes[j], o.pass_levels,
+                      am);
     } else {
-      o.transforms.push_back(make_transform_args(t, t.dev_pauli));
+      TransformArgs a = make_transform_args(t, t.dev_pauli);
+      a.amax = am.p;
+      a.amask = am.mask;
+      a.abase = am.base;
+      o.transforms.push_back(a);
     }
   }
   if (m == 1) {
     o.packs.push_back(make_pack_args(p, 0, out, nullptr, nullptr, root_kind == OUT_F64 ? 0 : 1, 0));
     return o;
   }
-  const ScaleBuf sb = scale_buffers(p);
   o.scaled = true;
   o.zero = ZeroRec{sb.maxbits, (uint64_t)m};
-  o.absmax = absmax_records(p, sb);
   o.scale = ScaleRec{sb.maxbits, m, net.K, sb.exps, sb.root_scale};
   for (int j = 0; j < m; ++j) {
     Node &nd = p->nodes[j];
@@ -1953,7 +2029,8 @@ struct WavePlan {
 };
 
 // The launches of one wave (a subset of the jobs, `sel`), their tables in A.
-static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<JobOps> &all_ops, TableArena &A) {
+static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<JobOps> &all_ops, TableArena &A,
+                          bool heads_only) {
   WavePlan W;
   const int njobs = (int)sel.size();
   std::vector<JobOps> ops(njobs);
@@ -1963,6 +2040,19 @@ static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<Job
     W.steps.push_back(std::move(f));
     W.step_jobs.push_back(std::move(jobs));
   };
+  // 0. the abs-max accumulators start from zero (the transforms take maxima)
+  {
+    std::vector<ZeroRec> zr;
+    for (auto &o : ops)
+      if (o.scaled) zr.push_back(o.zero);
+    if (!zr.empty()) {
+      const uint64_t zo = A.add_vec(zr);
+      const int nz = (int)zr.size();
+      add_launch([=](char *d) {
+        return [=](hipStream_t s) { HIP_OK(launch_grouped_zero((const ZeroRec *)(d + zo), nz, s)); };
+      });
+    }
+  }
   // 1. transform passes, level by level, then per-entry transforms
   size_t nlev = 0;
   for (auto &o : ops) nlev = std::max(nlev, o.pass_levels.size());
@@ -1999,29 +2089,28 @@ static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<Job
       });
     }
   }
-  // 2. scales
+  // 2. scales: abs-max of leaves no transform wrote, then exponents
   {
-    std::vector<ZeroRec> zr;
     std::vector<ScaleRec> sr;
     Group<AbsMaxArgs> g;
     for (auto &o : ops) {
       if (!o.scaled) continue;
-      zr.push_back(o.zero);
       sr.push_back(o.scale);
       for (auto &a : o.absmax) g.push(a, grouped_absmax_blocks(a));
     }
-    if (!zr.empty()) {
-      const uint64_t zo = A.add_vec(zr), so = A.add_vec(sr), ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
-      const int nz = (int)zr.size(), n = (int)g.recs.size();
+    if (!g.empty()) {
+      const uint64_t ro = A.add_vec(g.recs), fo = A.add_vec(g.first);
+      const int n = (int)g.recs.size();
       const uint32_t blocks = g.first.back();
-      add_launch([=](char *d) {
-        return [=](hipStream_t s) { HIP_OK(launch_grouped_zero((const ZeroRec *)(d + zo), nz, s)); };
-      });
       add_launch([=](char *d) {
         return [=](hipStream_t s) {
           HIP_OK(launch_grouped_absmax((const AbsMaxArgs *)(d + ro), (const uint32_t *)(d + fo), n, blocks, s));
         };
       });
+    }
+    if (!sr.empty()) {
+      const uint64_t so = A.add_vec(sr);
+      const int nz = (int)sr.size();
       add_launch([=](char *d) {
         return [=](hipStream_t s) { HIP_OK(launch_grouped_scales((const ScaleRec *)(d + so), nz, s)); };
       });
@@ -2046,6 +2135,7 @@ static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<Job
       }, done);
     }
   }
+  if (heads_only) return W;
   // 4. pairwise steps by depth; persistent final steps collected for the end
   int maxd = 0;
   for (auto &o : ops)
@@ -2146,8 +2236,9 @@ static WavePlan plan_wave(Multi *b, const std::vector<int> &sel, std::vector<Job
 // own stream, and wave w + 1 starts once wave w's launches before its final
 // steps are done, so one wave's final steps (store bound) run beside the
 // next wave's earlier launches.
-static void build_grouped(Multi *b, int nwaves) {
+static void build_grouped(Multi *b, int nwaves, bool heads_only) {
   b->grouped = true;
+  b->heads_only = heads_only;
   const int njobs = (int)b->plans.size();
   std::vector<JobOps> ops(njobs);
   for (int j = 0; j < njobs; ++j) {
@@ -2168,7 +2259,10 @@ static void build_grouped(Multi *b, int nwaves) {
   TableArena A;
   std::vector<WavePlan> plans;
   for (int w = 0; w < nwaves; ++w)
-    if (!sel[w].empty()) plans.push_back(plan_wave(b, sel[w], ops, A));
+    if (!sel[w].empty()) {
+      plans.push_back(plan_wave(b, sel[w], ops, A, heads_only));
+      b->wave_jobs.push_back(sel[w]);
+    }
   // upload the tables, then bind the launches to them
   if (!A.host.empty()) {
     HIP_OK(hipMalloc(&b->gtab, A.host.size()));
@@ -2190,7 +2284,8 @@ static void build_grouped(Multi *b, int nwaves) {
   }
   b->nslots = slot;
   for (int j = 0; j < njobs; ++j)
-    if (b->done_at[j] < 0) fail(TQC_ERR_INTERNAL, "job %d has no completing launch", j);
+    if (b->done_at[j] < 0 && !(heads_only && b->plans[j]->net->m >= 2))
+      fail(TQC_ERR_INTERNAL, "job %d has no completing launch", j);
 }
 
 static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, const uint64_t *out_bytes,
@@ -2198,6 +2293,7 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
                            int waves = 1) {
   if (njobs < 1 || !plans || !outs) fail(TQC_ERR_INVALID_ARG, "no jobs");
   if (nstreams < 0 || nstreams > 16) fail(TQC_ERR_INVALID_ARG, "streams %d (0..16)", nstreams);
+  if (grouped < 0 || grouped > 2) fail(TQC_ERR_INVALID_ARG, "grouped %d (0..2)", grouped);
   if (nstreams == 0) nstreams = 4;
   std::unique_ptr<Multi> b(new Multi());
   b->use_graph = use_graph != 0;
@@ -2235,9 +2331,21 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
     b->stream_of[j] = k;
     load[k] += cost[j];
   }
-  if (grouped) {
-    build_grouped(b.get(), waves);
+  if (grouped == 1) {
+    build_grouped(b.get(), waves, false);
     nstreams = std::max<int>(nstreams, (int)b->waves.size());
+  } else if (grouped == 2) {
+    build_grouped(b.get(), waves, true);
+    // worker streams by wave: the jobs of each wave, largest first, each to
+    // the least-loaded stream; the extra last stream runs the shared launches
+    std::fill(load.begin(), load.end(), 0.0);
+    for (const auto &wj : b->wave_jobs)
+      for (int j : wj) {
+        const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+        b->stream_of[j] = k;
+        load[k] += cost[j];
+      }
+    nstreams += 1;
   }
   if (b->timed) {
     int khz = 0;
@@ -2262,9 +2370,55 @@ static Multi *create_multi(int njobs, Plan *const *plans, void *const *outs, con
   return b.release();
 }
 
+// A single-slice plan's launches after its leaf packs (pairwise steps, the
+// final step), as its execute runs them.
+static void run_tail(Plan *p, void *out, hipStream_t s) {
+  const ScaleBuf sb = scale_buffers(p);
+  run_steps(p, out, p->out_dtype == TQC_F64 ? OUT_F64 : OUT_F32, sb, true, false, s, nullptr, nullptr, nullptr,
+            false);
+}
+
 // fork from `origin`, every job on its stream (between its two stamps), join
 static void multi_enqueue(Multi *b, hipStream_t origin) {
   if (b->timed) HIP_OK(launch_stamp(b->stamps, origin));
+  if (b->heads_only) {
+    // the waves' shared launches one after another on the last stream; each
+    // job's own launches on its worker stream once its wave's are done (a
+    // single-tensor job is done with its wave's pack launch: its stamps go
+    // around the wave's shared launches)
+    hipStream_t hs = b->streams.back();
+    const size_t nw = b->streams.size() - 1;
+    HIP_OK(hipEventRecord(b->fork, origin));
+    for (auto st : b->streams) HIP_OK(hipStreamWaitEvent(st, b->fork, 0));
+    for (size_t w = 0; w < b->waves.size(); ++w) {
+      if (b->timed)
+        for (int j : b->wave_jobs[w])
+          if (b->plans[j]->net->m < 2) HIP_OK(launch_stamp(b->stamps + 1 + 2 * j, hs));
+      for (auto &f : b->waves[w].steps) f(hs);
+      HIP_OK(hipEventRecord(b->head_done[w], hs));
+      if (b->timed)
+        for (int j : b->wave_jobs[w])
+          if (b->plans[j]->net->m < 2) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, hs));
+    }
+    for (size_t w = 0; w < b->waves.size(); ++w) {
+      std::vector<char> waited(nw, 0);
+      for (int j : b->wave_jobs[w]) {
+        if (b->plans[j]->net->m < 2) continue;
+        const int k = b->stream_of[j];
+        hipStream_t st = b->streams[k];
+        if (!waited[k]) HIP_OK(hipStreamWaitEvent(st, b->head_done[w], 0));
+        waited[k] = 1;
+        if (b->timed) HIP_OK(launch_stamp(b->stamps + 1 + 2 * j, st));
+        run_tail(b->plans[j], b->outs[j], st);
+        if (b->timed) HIP_OK(launch_stamp(b->stamps + 2 + 2 * j, st));
+      }
+    }
+    for (size_t k = 0; k < b->streams.size(); ++k) {
+      HIP_OK(hipEventRecord(b->join[k], b->streams[k]));
+      HIP_OK(hipStreamWaitEvent(origin, b->join[k], 0));
+    }
+    return;
+  }
   if (b->grouped) {
     // wave w on worker stream w: its launches up to the final steps start
     // once wave w - 1's are done, then its shared final-step launches; every
@@ -2346,9 +2500,11 @@ static void multi_times(Multi *b, double *start_ms, double *end_ms) {
   HIP_OK(hipMemcpy(st.data(), b->stamps, st.size() * 8, hipMemcpyDeviceToHost));
   for (size_t j = 0; j < n; ++j) {
     // grouped: every job starts with the launch and ends with the shared
-    // launch that runs its final step
-    const uint64_t s0 = b->grouped ? 0 : 1 + 2 * j;
-    const uint64_t e = b->grouped ? (uint64_t)b->done_at[j] : 2 + 2 * j;
+    // launch that runs its final step; grouped heads: its own launches'
+    // stamps, as without grouping
+    const bool shared = b->grouped && !b->heads_only;
+    const uint64_t s0 = shared ? 0 : 1 + 2 * j;
+    const uint64_t e = shared ? (uint64_t)b->done_at[j] : 2 + 2 * j;
     if (start_ms) start_ms[j] = double((long long)(st[s0] - st[0])) * b->tick_ms;
     if (end_ms) end_ms[j] = double((long long)(st[e] - st[0])) * b->tick_ms;
   }
@@ -3302,7 +3458,7 @@ tqc_status tqc_multi_info(tqc_multi_t multi, int32_t *launches, int32_t *shared_
     const Multi *m = static_cast<Multi *>(multi);
     int32_t nl = 0;
     for (auto &w : m->waves) nl += (int32_t)(w.steps.size() + w.roots.size());
-    if (launches) *launches = m->grouped ? nl : -1;
+    if (launches) *launches = m->grouped ? nl : -1;  // grouped heads: the shared launches only
     if (shared_root_jobs) *shared_root_jobs = m->shared_root_jobs;
     if (shared_root_launches) *shared_root_launches = m->shared_roots;
   });

@@ -50,7 +50,7 @@ __device__ inline double down_coef(int s, int o) {
 
 // The options of all cuts are enumerated like an odometer (last cut
 // fastest); the option digits are packed two bits per cut in a register.
-__device__ inline void transform_elem(const TransformArgs &a, uint64_t e) {
+__device__ inline double transform_elem(const TransformArgs &a, uint64_t e) {
   const uint64_t cols = 1ull << (a.o + a.u);
   const uint64_t x = e & ((1ull << a.o) - 1);
   const uint64_t row = e >> a.o;  // Pauli digit of cut t at bits 2 (c - 1 - t)
@@ -87,6 +87,27 @@ __device__ inline void transform_elem(const TransformArgs &a, uint64_t e) {
     if (t < 0) break;
   }
   a.out[e] = sum;
+  return sum;
+}
+
+// Exponent e that brings an operand's largest |value| into [1, 2) by 2^e
+// (0 for an all-zero operand); the bits are those of a non-negative double.
+__device__ inline int scale_exp(unsigned long long bits) {
+  const double mx = __longlong_as_double((long long)bits);
+  return mx > 0.0 ? -ilogb(mx) : 0;
+}
+
+// Wave maximum of mx, then an atomic max (non-negative doubles order like
+// their bit patterns) unless the value already there, read from L2, is at
+// least as large: the maximum only grows while a launch runs, so most waves
+// of a large tensor skip the atomic.  Every lane of the wave calls it.
+__device__ inline void amax_commit(unsigned long long *p, double mx) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63u) == 0 && mx > 0.0) {
+    const unsigned long long v = (unsigned long long)__double_as_longlong(mx);
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) atomicMax(p, v);
+  }
 }
 
 // ================================================================= pack
@@ -94,7 +115,7 @@ __device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
   const uint64_t kmask = (1ull << a.lk) - 1;
   uint64_t src = a.base;
   for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
-  const double sc = a.dexp ? ldexp(a.scale, *a.dexp) : a.scale;
+  const double sc = a.dmax ? ldexp(a.scale, scale_exp(*a.dmax)) : (a.dexp ? ldexp(a.scale, *a.dexp) : a.scale);
   const double v = a.src[src] * sc;
   const uint64_t d = ((e >> a.lk) << a.kpad) | (e & kmask);
   switch (a.prec) {

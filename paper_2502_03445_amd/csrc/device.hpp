@@ -32,6 +32,11 @@ struct TransformArgs {
   int up[kMaxCutsT];        // 1 if upstream end
   int bbit[kMaxCutsT];      // upstream: index of its measured bit in b
   uint64_t w[kMaxCutsT];    // mixed-radix weight of the cut's raw row digit
+  // optional (amax non-null): the largest |value| written among the entries
+  // whose index bits under amask equal abase (the fixed output qubits), as
+  // float64 bits, atomically maxed into *amax
+  unsigned long long *amax;
+  uint64_t amask, abase;
 };
 
 // One pass of the separable Pauli transform: one or two cuts of a tensor
@@ -55,6 +60,8 @@ struct TransformPassArgs {
   uint64_t seg_ext[kPassSegs], seg_in[kPassSegs], seg_out[kPassSegs];
   uint64_t row_in[2], bit_in[2], row_out[2];
   uint64_t out_entries;       // destination size (for host-side checks)
+  unsigned long long *amax;   // optional abs-max of the written entries, as
+  uint64_t amask, abase;      // in TransformArgs (a tensor's last pass only)
 };
 
 // ---------------------------------------------------------------- pack
@@ -70,6 +77,8 @@ struct PackArgs {
   int prec;                  // 0 f64, 1 f32, 2 bf16x2 split, 3 bf16x3 split
   double scale;              // exact power of two
   const int *dexp;           // optional device exponent e: values scaled by 2^e
+  const unsigned long long *dmax;  // optional device abs-max bits (instead of
+                                   // dexp): e = -floor(log2 max), 0 if max = 0
 };
 
 // Largest |value| of a leaf operand over every slice (the gathered bits plus

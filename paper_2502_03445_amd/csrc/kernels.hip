@@ -8,11 +8,24 @@
 
 namespace tqc {
 
-__global__ void __launch_bounds__(256) transform_kernel(TransformArgs a) {
+// abs-max of a transform's written entry e (fixed-qubit filter)
+template <typename A>
+__device__ inline void amax_take(const A &a, uint64_t e, double v, double &mx) {
+  if ((e & a.amask) == a.abase) mx = fmax(mx, fabs(v));
+}
+
+__device__ inline void transform_range(const TransformArgs &a, uint64_t e0, uint64_t step) {
   const uint64_t total = (1ull << (2 * a.c)) << a.o;
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    transform_elem(a, e);
+  double mx = 0.0;
+  for (uint64_t e = e0; e < total; e += step) {
+    const double v = transform_elem(a, e);
+    if (a.amax) amax_take(a, e, v, mx);
+  }
+  if (a.amax) amax_commit(a.amax, mx);
+}
+
+__global__ void __launch_bounds__(256) transform_kernel(TransformArgs a) {
+  transform_range(a, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
 }
 
 // several tensors per launch (blockIdx.y selects the tensor)
@@ -20,11 +33,8 @@ struct TransformBatch {
   TransformArgs a[4];
 };
 __global__ void __launch_bounds__(256) transform_multi_kernel(TransformBatch tb) {
-  const TransformArgs &a = tb.a[blockIdx.y];
-  const uint64_t total = (1ull << (2 * a.c)) << a.o;
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    transform_elem(a, e);
+  transform_range(tb.a[blockIdx.y], blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                  (uint64_t)gridDim.x * blockDim.x);
 }
 
 __global__ void __launch_bounds__(256) pack_kernel(PackArgs a) {
@@ -37,8 +47,11 @@ __global__ void __launch_bounds__(256) pack_kernel(PackArgs a) {
 // several leaf operands per launch (blockIdx.y selects the leaf)
 struct PackBatch {
   PackArgs a[kPackBatch];
+  ScaleRec sr;  // optional (maxbits non-null): exponents and output scale
 };
+__device__ inline void write_scales(const ScaleRec &q);
 __global__ void __launch_bounds__(256) pack_multi_kernel(PackBatch pb) {
+  if (pb.sr.maxbits && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_scales(pb.sr);
   const PackArgs &a = pb.a[blockIdx.y];
   const uint64_t total = 1ull << a.nbits;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
@@ -90,17 +103,14 @@ __global__ void __launch_bounds__(256) absmax_kernel(AbsMaxBatch ab) {
 
 // exponents e_j = -floor(log2 max_j) (0 for an all-zero operand) and the
 // output scale 2^(-K - sum e_j)
-__global__ void scale_exponents_kernel(const unsigned long long *maxbits, int m, int K, int *exps,
-                                       double *root_scale) {
-  if (threadIdx.x != 0) return;
+__device__ inline void write_scales(const ScaleRec &q) {
   int sum = 0;
-  for (int j = 0; j < m; ++j) {
-    const double mx = __longlong_as_double((long long)maxbits[j]);
-    const int e = mx > 0.0 ? -ilogb(mx) : 0;
-    exps[j] = e;
+  for (int j = 0; j < q.m; ++j) {
+    const int e = scale_exp(q.maxbits[j]);
+    q.exps[j] = e;
     sum += e;
   }
-  *root_scale = ldexp(1.0, -K - sum);
+  *q.root_scale = ldexp(1.0, -q.K - sum);
 }
 
 // split-K reduction: entry e = m * N + n adds its 2^ksplit partial sums in
@@ -176,6 +186,7 @@ __device__ inline void pass_body(const TransformPassArgs &a, uint64_t bid, uint6
   constexpr int NB = G == 2 ? (UB ? 6 : 4) : 1;
   const uint64_t stride = nblk * blockDim.x;
   const bool small = a.nfree <= 0xffffffffull;
+  double mx = 0.0;
   for (uint64_t f = bid * blockDim.x + threadIdx.x; f < a.nfree; f += stride) {
     uint64_t ib = 0, ob = 0;
     if (small) {
@@ -222,24 +233,34 @@ __device__ inline void pass_body(const TransformPassArgs &a, uint64_t bid, uint6
     }
     if constexpr (G == 1) {
 #pragma unroll
-      for (int sa = 0; sa < 4; ++sa) a.out[ob + (uint64_t)sa * a.row_out[0]] = t[sa];
+      for (int sa = 0; sa < 4; ++sa) {
+        const uint64_t o = ob + (uint64_t)sa * a.row_out[0];
+        a.out[o] = t[sa];
+        if (a.amax) amax_take(a, o, t[sa], mx);
+      }
     } else {
 #pragma unroll
       for (int sa = 0; sa < 4; ++sa) {
         double p[4];
         cut_map<UB>(t + sa * NB, p);
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb)
-          a.out[ob + (uint64_t)sa * a.row_out[0] + (uint64_t)sb * a.row_out[1]] = p[sb];
+        for (int sb = 0; sb < 4; ++sb) {
+          const uint64_t o = ob + (uint64_t)sa * a.row_out[0] + (uint64_t)sb * a.row_out[1];
+          a.out[o] = p[sb];
+          if (a.amax) amax_take(a, o, p[sb], mx);
+        }
       }
     }
   }
+  if (a.amax) amax_commit(a.amax, mx);
 }
 
 // several passes per launch (blockIdx.y selects the pass; one pass of each
 // of several tensors): the variant is uniform over a workgroup
 struct PassBatch {
   TransformPassArgs a[kPassBatch];
+  unsigned long long *zero;  // optional: cleared by the first workgroup
+  int nzero;
 };
 __device__ inline void pass_dispatch(const TransformPassArgs &a, uint64_t bid, uint64_t nblk) {
   if (a.g == 1) {
@@ -255,15 +276,22 @@ __device__ inline void pass_dispatch(const TransformPassArgs &a, uint64_t bid, u
 }
 
 __global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
+  if (pb.zero && blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = (int)threadIdx.x; i < pb.nzero; i += (int)blockDim.x) pb.zero[i] = 0ull;
   pass_dispatch(pb.a[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
-hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s) {
+hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s, unsigned long long *zero,
+                                   int nzero) {
   for (int i = 0; i < n; ++i)
     if (args[i].nseg < 1 || args[i].nseg > kPassSegs || args[i].g < 1 || args[i].g > 2)
       return hipErrorInvalidValue;
   for (int i0 = 0; i0 < n; i0 += kPassBatch) {
     PassBatch pb{};
+    if (i0 == 0) {
+      pb.zero = zero;
+      pb.nzero = nzero;
+    }
     const int cnt = n - i0 < kPassBatch ? n - i0 : kPassBatch;
     uint64_t most = 1;
     for (int i = 0; i < cnt; ++i) {
@@ -322,9 +350,10 @@ hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s) {
+hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s, const ScaleRec *sr) {
   for (int i0 = 0; i0 < n; i0 += kPackBatch) {
     PackBatch pb{};
+    if (i0 == 0 && sr) pb.sr = *sr;
     const int cnt = n - i0 < kPackBatch ? n - i0 : kPackBatch;
     uint64_t most = 1;
     for (int i = 0; i < cnt; ++i) {
@@ -334,12 +363,6 @@ hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s) {
     }
     hipLaunchKernelGGL(pack_multi_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, pb);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
-                                  double *root_scale, hipStream_t s) {
-  hipLaunchKernelGGL(scale_exponents_kernel, dim3(1), dim3(64), 0, s, maxbits, m, K, exps, root_scale);
   return hipGetLastError();
 }
 
@@ -677,11 +700,8 @@ __global__ void __launch_bounds__(256) grouped_pass_kernel(const TransformPassAr
 __global__ void __launch_bounds__(256) grouped_transform_kernel(const TransformArgs *recs, const uint32_t *first,
                                                                 int n) {
   const int r = group_record(first, n, blockIdx.x);
-  const TransformArgs &a = recs[r];
-  const uint64_t total = (1ull << (2 * a.c)) << a.o;
   const uint64_t nb = first[r + 1] - first[r];
-  for (uint64_t e = (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x)
-    transform_elem(a, e);
+  transform_range(recs[r], (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x, nb * blockDim.x);
 }
 
 __global__ void __launch_bounds__(256) grouped_zero_kernel(const ZeroRec *recs, int n) {
@@ -710,15 +730,7 @@ __global__ void __launch_bounds__(256) grouped_absmax_kernel(const AbsMaxArgs *r
 __global__ void __launch_bounds__(64) grouped_scale_kernel(const ScaleRec *recs, int n) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const ScaleRec &q = recs[r];
-  int sum = 0;
-  for (int j = 0; j < q.m; ++j) {
-    const double mx = __longlong_as_double((long long)q.maxbits[j]);
-    const int e = mx > 0.0 ? -ilogb(mx) : 0;
-    q.exps[j] = e;
-    sum += e;
-  }
-  *q.root_scale = ldexp(1.0, -q.K - sum);
+  write_scales(recs[r]);
 }
 
 __global__ void __launch_bounds__(256) grouped_pack_kernel(const PackArgs *recs, const uint32_t *first, int n) {

@@ -7,6 +7,15 @@
 
 namespace tqc {
 
+// operand exponents e_j of m leaves from their abs-max bits, and the output
+// scale 2^(-K - sum e_j)
+struct ScaleRec {
+  const unsigned long long *maxbits;
+  int m, K;
+  int *exps;
+  double *root_scale;
+};
+
 hipError_t launch_transform(const TransformArgs &a, hipStream_t s);
 hipError_t launch_transforms(const TransformArgs *args, int n, hipStream_t s);  // n tensors
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
@@ -25,12 +34,14 @@ hipError_t launch_column_norms(const double *T, uint64_t rows, uint64_t cols, do
                                hipStream_t s);
 hipError_t launch_gather_columns(const double *src, uint64_t rows, uint64_t src_cols, const int32_t *states,
                                  uint64_t count, uint64_t dst_cols, double *dst, hipStream_t s);
-hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s);  // n passes
-hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s);                    // n leaves
+// n passes; the first launch's first workgroup clears zero[0 .. nzero) first
+hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s,
+                                   unsigned long long *zero = nullptr, int nzero = 0);
+// n leaves; with sr, the first launch's first thread also writes its
+// exponents and output scale (for packs that read the abs-max directly)
+hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s, const ScaleRec *sr = nullptr);
 int root_gemm_warm();  // caches the device's CU count (call outside graph capture)
 hipError_t launch_absmax(const AbsMaxArgs *args, int n, hipStream_t s);                  // n leaves
-hipError_t launch_scale_exponents(const unsigned long long *maxbits, int m, int K, int *exps,
-                                  double *root_scale, hipStream_t s);
 // prec: 0 f64, 1 f32, 2 bf16x3, 3 bf16x6; tile: 0 = 128x128, 1 = 64x64, 2 = 32x32
 // general = true: the general kernel even where the long-k kernel applies
 hipError_t launch_gemm(int prec, const GemmArgs &g, int tile, hipStream_t s, bool general = false);
@@ -66,12 +77,6 @@ hipError_t launch_root_multi(int prec, int kpad, const RootJob *jobs, int njobs,
 struct ZeroRec {
   unsigned long long *p;
   uint64_t n;
-};
-struct ScaleRec {
-  const unsigned long long *maxbits;
-  int m, K;
-  int *exps;
-  double *root_scale;
 };
 uint32_t grouped_pass_blocks(const TransformPassArgs &a);
 uint32_t grouped_transform_blocks(const TransformArgs &a);

@@ -95,6 +95,12 @@ def test_multi_rejects_bad_jobs():
         tqc.Multi([plans[0]], outs=[small])
     with pytest.raises(tqc.TqcError):
         tqc.Multi(plans[:2], streams=17)
+    opt = tqc.MultiOptions(1, 4, 0, 3, 1)  # grouped outside 0..2
+    ph = (tqc.ctypes.c_void_p * 2)(*[p.handle.value for p in plans[:2]])
+    keep = [p.output_tensor() for p in plans[:2]]
+    oh = (tqc.ctypes.c_void_p * 2)(*[o.data_ptr() for o in keep])
+    h = tqc.ctypes.c_void_p()
+    assert tqc.lib().tqc_multi_create_ex(2, ph, oh, None, tqc.ctypes.byref(opt), None, tqc.ctypes.byref(h)) != 0
     untimed = tqc.Multi(plans[:2])
     untimed.execute()
     with pytest.raises(tqc.TqcError):
@@ -155,6 +161,56 @@ def test_grouped_equals_plain_execution(form, use_graph, waves):
     for spec, o in zip(specs, mj.outs):
         ref = full_distribution(spec)
         assert np.abs(o.double().cpu().numpy() - ref).max() <= tol(form, ref)
+
+
+@pytest.mark.parametrize("form,use_graph,waves,streams", [("fp32", True, 1, 4), ("fp32", False, 3, 2),
+                                                          ("bf16x3", True, 2, 8), ("bf16x6", True, 4, 3),
+                                                          ("fp16x3", True, 2, 4), ("fp64", False, 1, 1)])
+def test_grouped_heads_equal_plain_execution(form, use_graph, waves, streams):
+    """Grouped heads: the transforms, scales and packs of each wave's jobs in
+    shared launches, then every job's own pairwise steps and final step on a
+    worker stream; outputs equal the plan's own execution bit for bit, over
+    graph replays with unrelated eager work between them."""
+    specs, nets, plans = jobs(form)
+    plain = [p.execute().clone() for p in plans]
+    mj = tqc.Multi(plans, use_graph=use_graph, streams=streams, timed=True, grouped="heads", waves=waves)
+    nl, nb, nr = mj.info()
+    assert 0 < nl <= 8 * waves and nb == 0 and nr == 0, (nl, nb, nr)
+    for rep in range(3):
+        for o in mj.outs:
+            o.fill_(-7.0)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        mj.execute()
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        for i, (o, ref_gpu) in enumerate(zip(mj.outs, plain)):
+            assert torch.equal(o, ref_gpu), (rep, i)
+        st, en = mj.job_times()
+        assert np.all(st >= 0) and np.all(en >= st), rep
+    for spec, o in zip(specs, mj.outs):
+        ref = full_distribution(spec)
+        assert np.abs(o.double().cpu().numpy() - ref).max() <= tol(form, ref)
+
+
+def test_grouped_heads_large_jobs():
+    """Twelve jobs of the batch workload with n 20..28 (multi-pass
+    transforms, several depths, split-k steps among them) with grouped
+    heads in three waves over eight streams: bit-identical to their own
+    executions."""
+    from workloads import batch
+    ids = [18, 7, 1, 5, 28, 3, 22, 2, 16, 11, 19, 46]
+    specs = [batch.job(i) for i in ids]
+    plans = [tqc.Plan(tqc.Network.from_spec(s), precision="fp32") for s in specs]
+    plain = [p.execute().clone() for p in plans]
+    torch.cuda.synchronize()
+    mj = tqc.Multi(plans, use_graph=True, streams=8, grouped="heads", waves=3)
+    for o in mj.outs:
+        o.fill_(-7.0)
+    mj.execute()
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(mj.outs, plain)):
+        assert torch.equal(o, r), ids[i]
 
 
 def test_grouped_final_steps_of_many_shapes_and_ks():
