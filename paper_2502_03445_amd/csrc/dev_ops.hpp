@@ -97,18 +97,21 @@ __device__ inline int scale_exp(unsigned long long bits) {
   return mx > 0.0 ? -ilogb(mx) : 0;
 }
 
-// Wave maximum of mx, then an atomic max (non-negative doubles order like
-// their bit patterns) unless the value already there, read from L2, is at
-// least as large: the maximum only grows while a launch runs, so most waves
-// of a large tensor skip the atomic.  Every lane of the wave calls it.
+// Maximum of mx over the 256-thread workgroup, then one atomic max by its
+// first thread (non-negative doubles order like their bit patterns; the
+// result is not waited for).  Every thread of the workgroup calls it.
 __device__ inline void amax_commit(unsigned long long *p, double mx) {
+  __shared__ double red[4];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-  if ((threadIdx.x & 63u) == 0 && mx > 0.0) {
-    const unsigned long long v = (unsigned long long)__double_as_longlong(mx);
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) atomicMax(p, v);
+  if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(p, (unsigned long long)__double_as_longlong(m));
   }
 }
+
 
 // ================================================================= pack
 __device__ inline void pack_elem(const PackArgs &a, uint64_t e) {

@@ -140,7 +140,19 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 // each measured here), so 1024 workgroups spend ~27 us on them alone.
 constexpr unsigned kMaxGrid = 256;
 
-static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u) {
+static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u);
+
+// Per-entry transform grid: one entry per thread; with an abs-max, past 256
+// workgroups about eight entries per thread, so that a workgroup's atomic
+// covers about 2048 entries.
+static inline unsigned transform_grid(uint64_t total, bool amax) {
+  const unsigned g = grid_for(total);
+  if (!amax || g <= 256) return g;
+  const unsigned g8 = grid_for(total / 8 + 1);
+  return g8 > 256 ? g8 : 256;
+}
+
+static inline unsigned grid_for(uint64_t n, unsigned cap) {
   uint64_t b = (n + 255) / 256;
   if (b < 1) b = 1;
   return (unsigned)(b > cap ? cap : b);
@@ -305,7 +317,7 @@ hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStre
 
 hipError_t launch_transform(const TransformArgs &a, hipStream_t s) {
   const uint64_t total = (1ull << (2 * a.c)) << a.o;
-  hipLaunchKernelGGL(transform_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(transform_kernel, dim3(transform_grid(total, a.amax != nullptr)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -313,13 +325,14 @@ hipError_t launch_transforms(const TransformArgs *args, int n, hipStream_t s) {
   for (int i0 = 0; i0 < n; i0 += 4) {
     TransformBatch tb{};
     const int cnt = n - i0 < 4 ? n - i0 : 4;
-    uint64_t most = 1;
+    unsigned blocks = 1;
     for (int i = 0; i < cnt; ++i) {
       tb.a[i] = args[i0 + i];
       const uint64_t total = (1ull << (2 * args[i0 + i].c)) << args[i0 + i].o;
-      most = total > most ? total : most;
+      const unsigned b = transform_grid(total, args[i0 + i].amax != nullptr);
+      blocks = b > blocks ? b : blocks;
     }
-    hipLaunchKernelGGL(transform_multi_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, tb);
+    hipLaunchKernelGGL(transform_multi_kernel, dim3(blocks, cnt), dim3(256), 0, s, tb);
   }
   return hipGetLastError();
 }
@@ -750,7 +763,9 @@ __global__ void __launch_bounds__(256) grouped_gemm_kernel(const GemmArgs *recs,
 }
 
 uint32_t grouped_pass_blocks(const TransformPassArgs &a) { return grid_for(a.nfree); }
-uint32_t grouped_transform_blocks(const TransformArgs &a) { return grid_for((1ull << (2 * a.c)) << a.o); }
+uint32_t grouped_transform_blocks(const TransformArgs &a) {
+  return transform_grid((1ull << (2 * a.c)) << a.o, a.amax != nullptr);
+}
 uint32_t grouped_absmax_blocks(const AbsMaxArgs &a) { return grid_for((1ull << a.nbits) / 8 + 1, kMaxGrid); }
 uint32_t grouped_pack_blocks(const PackArgs &a) { return grid_for(1ull << a.nbits); }
 
