@@ -678,8 +678,19 @@ static void run_slices(Plan *p, void *root_out, int root_kind, uint64_t s0, uint
     // else by a launch of their own, before any transform writes
     const bool fold = scaled && !levels.empty();
     if (scaled && !fold) HIP_OK(launch_zero_u64(sb.maxbits, (uint64_t)m, s));
-    launch_levels(levels, s, fold ? sb.maxbits : nullptr, fold ? m : 0);
-    if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
+    // the per-entry transforms join the last level's launch when it is not
+    // the first (every tensor on passes has at least two) and both fit one
+    const bool join = levels.size() >= 2 && !ta.empty() && ta.size() <= 4 &&
+                      levels.back().size() <= (size_t)kPassBatch;
+    if (join) {
+      std::vector<TransformPassArgs> last = std::move(levels.back());
+      levels.pop_back();
+      launch_levels(levels, s, fold ? sb.maxbits : nullptr, fold ? m : 0);
+      HIP_OK(launch_transform_level(last.data(), (int)last.size(), ta.data(), (int)ta.size(), s));
+    } else {
+      launch_levels(levels, s, fold ? sb.maxbits : nullptr, fold ? m : 0);
+      if (!ta.empty()) HIP_OK(launch_transforms(ta.data(), (int)ta.size(), s));
+    }
   }
   if (tm) tm->end();
   if (m == 1) {

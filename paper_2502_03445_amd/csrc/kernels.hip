@@ -293,6 +293,46 @@ __global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
   pass_dispatch(pb.a[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
+// The last pass level of some tensors and the per-entry transforms of others
+// in one launch: blockIdx.y < np selects a pass, the rest a tensor, which
+// runs on the first blocks[i] workgroups of its row (its own launch's grid).
+struct TransformRows {
+  uint32_t blocks[4];
+};
+__global__ void __launch_bounds__(256) transform_level_kernel(PassBatch pb, TransformBatch tb, TransformRows tr,
+                                                              int np) {
+  const int y = (int)blockIdx.y;
+  if (y < np) {
+    pass_dispatch(pb.a[y], blockIdx.x, gridDim.x);
+    return;
+  }
+  const uint32_t nb = tr.blocks[y - np];
+  if (blockIdx.x >= nb) return;  // whole workgroup
+  transform_range(tb.a[y - np], blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)nb * blockDim.x);
+}
+
+hipError_t launch_transform_level(const TransformPassArgs *pa, int np, const TransformArgs *ta, int nt,
+                                  hipStream_t s) {
+  if (np < 1 || np > kPassBatch || nt < 1 || nt > 4) return hipErrorInvalidValue;
+  PassBatch pb{};
+  TransformBatch tb{};
+  TransformRows tr{};
+  unsigned blocks = 1;
+  for (int i = 0; i < np; ++i) {
+    if (pa[i].nseg < 1 || pa[i].nseg > kPassSegs || pa[i].g < 1 || pa[i].g > 2) return hipErrorInvalidValue;
+    pb.a[i] = pa[i];
+    const unsigned b = grid_for(pa[i].nfree);
+    blocks = b > blocks ? b : blocks;
+  }
+  for (int i = 0; i < nt; ++i) {
+    tb.a[i] = ta[i];
+    tr.blocks[i] = transform_grid((1ull << (2 * ta[i].c)) << ta[i].o, ta[i].amax != nullptr);
+    blocks = tr.blocks[i] > blocks ? tr.blocks[i] : blocks;
+  }
+  hipLaunchKernelGGL(transform_level_kernel, dim3(blocks, np + nt), dim3(256), 0, s, pb, tb, tr, np);
+  return hipGetLastError();
+}
+
 hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s, unsigned long long *zero,
                                    int nzero) {
   for (int i = 0; i < n; ++i)

@@ -37,6 +37,10 @@ hipError_t launch_gather_columns(const double *src, uint64_t rows, uint64_t src_
 // n passes; the first launch's first workgroup clears zero[0 .. nzero) first
 hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStream_t s,
                                    unsigned long long *zero = nullptr, int nzero = 0);
+// np (<= kPassBatch) passes of one level and nt (<= 4) per-entry transforms
+// of other tensors in one launch
+hipError_t launch_transform_level(const TransformPassArgs *pa, int np, const TransformArgs *ta, int nt,
+                                  hipStream_t s);
 // n leaves; with sr, the first launch's first thread also writes its
 // exponents and output scale (for packs that read the abs-max directly)
 hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s, const ScaleRec *sr = nullptr);
