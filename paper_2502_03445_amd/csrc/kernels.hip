@@ -142,14 +142,14 @@ constexpr unsigned kMaxGrid = 256;
 
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u);
 
-// Per-entry transform grid: one entry per thread; with an abs-max, past 256
-// workgroups about eight entries per thread, so that a workgroup's atomic
-// covers about 2048 entries.
-static inline unsigned transform_grid(uint64_t total, bool amax) {
-  const unsigned g = grid_for(total);
-  if (!amax || g <= 256) return g;
-  const unsigned g8 = grid_for(total / 8 + 1);
-  return g8 > 256 ? g8 : 256;
+// Workgroups of a transform record (one entry or free coordinate per
+// thread, grid-stride beyond): one that also takes an abs-max ends in one
+// atomic per workgroup on the leaf's address, and such atomics serialize
+// (about 26 ns each), so its grid stops at 1024 workgroups.
+constexpr unsigned kAmaxGrid = 1024;
+static inline unsigned transform_grid(uint64_t n, bool amax) {
+  const unsigned g = grid_for(n);
+  return amax && g > kAmaxGrid ? kAmaxGrid : g;
 }
 
 static inline unsigned grid_for(uint64_t n, unsigned cap) {
@@ -271,7 +271,8 @@ __device__ inline void pass_body(const TransformPassArgs &a, uint64_t bid, uint6
 // of several tensors): the variant is uniform over a workgroup
 struct PassBatch {
   TransformPassArgs a[kPassBatch];
-  unsigned long long *zero;  // optional: cleared by the first workgroup
+  uint32_t nblk[kPassBatch];  // workgroups of each pass (the first ones of its row)
+  unsigned long long *zero;   // optional: cleared by the first workgroup
   int nzero;
 };
 __device__ inline void pass_dispatch(const TransformPassArgs &a, uint64_t bid, uint64_t nblk) {
@@ -290,7 +291,9 @@ __device__ inline void pass_dispatch(const TransformPassArgs &a, uint64_t bid, u
 __global__ void __launch_bounds__(256) transform_pass_kernel(PassBatch pb) {
   if (pb.zero && blockIdx.x == 0 && blockIdx.y == 0)
     for (int i = (int)threadIdx.x; i < pb.nzero; i += (int)blockDim.x) pb.zero[i] = 0ull;
-  pass_dispatch(pb.a[blockIdx.y], blockIdx.x, gridDim.x);
+  const uint32_t nb = pb.nblk[blockIdx.y];
+  if (blockIdx.x >= nb) return;  // whole workgroup
+  pass_dispatch(pb.a[blockIdx.y], blockIdx.x, nb);
 }
 
 // The last pass level of some tensors and the per-entry transforms of others
@@ -303,7 +306,8 @@ __global__ void __launch_bounds__(256) transform_level_kernel(PassBatch pb, Tran
                                                               int np) {
   const int y = (int)blockIdx.y;
   if (y < np) {
-    pass_dispatch(pb.a[y], blockIdx.x, gridDim.x);
+    const uint32_t nb = pb.nblk[y];
+    if (blockIdx.x < nb) pass_dispatch(pb.a[y], blockIdx.x, nb);
     return;
   }
   const uint32_t nb = tr.blocks[y - np];
@@ -321,8 +325,8 @@ hipError_t launch_transform_level(const TransformPassArgs *pa, int np, const Tra
   for (int i = 0; i < np; ++i) {
     if (pa[i].nseg < 1 || pa[i].nseg > kPassSegs || pa[i].g < 1 || pa[i].g > 2) return hipErrorInvalidValue;
     pb.a[i] = pa[i];
-    const unsigned b = grid_for(pa[i].nfree);
-    blocks = b > blocks ? b : blocks;
+    pb.nblk[i] = transform_grid(pa[i].nfree, pa[i].amax != nullptr);
+    blocks = pb.nblk[i] > blocks ? pb.nblk[i] : blocks;
   }
   for (int i = 0; i < nt; ++i) {
     tb.a[i] = ta[i];
@@ -345,12 +349,13 @@ hipError_t launch_transform_passes(const TransformPassArgs *args, int n, hipStre
       pb.nzero = nzero;
     }
     const int cnt = n - i0 < kPassBatch ? n - i0 : kPassBatch;
-    uint64_t most = 1;
+    unsigned blocks = 1;
     for (int i = 0; i < cnt; ++i) {
       pb.a[i] = args[i0 + i];
-      most = args[i0 + i].nfree > most ? args[i0 + i].nfree : most;
+      pb.nblk[i] = transform_grid(args[i0 + i].nfree, args[i0 + i].amax != nullptr);
+      blocks = pb.nblk[i] > blocks ? pb.nblk[i] : blocks;
     }
-    hipLaunchKernelGGL(transform_pass_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, pb);
+    hipLaunchKernelGGL(transform_pass_kernel, dim3(blocks, cnt), dim3(256), 0, s, pb);
   }
   return hipGetLastError();
 }
@@ -802,7 +807,7 @@ __global__ void __launch_bounds__(256) grouped_gemm_kernel(const GemmArgs *recs,
   gemm_tile<P, BM, BN, BK, A64>(recs[r], blockIdx.x - first[r], smem);
 }
 
-uint32_t grouped_pass_blocks(const TransformPassArgs &a) { return grid_for(a.nfree); }
+uint32_t grouped_pass_blocks(const TransformPassArgs &a) { return transform_grid(a.nfree, a.amax != nullptr); }
 uint32_t grouped_transform_blocks(const TransformArgs &a) {
   return transform_grid((1ull << (2 * a.c)) << a.o, a.amax != nullptr);
 }
