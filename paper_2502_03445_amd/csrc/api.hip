@@ -355,6 +355,39 @@ static int step_prec(const Plan *p, const Step &st) {
 }
 static int pack_prec(const Plan *p) { return p->prec == Prec::F16X3 ? 1 : int(p->prec); }
 
+// Tiling of a pack (PackArgs::tkb): the destination's lowest bits (k bits)
+// and the source's lowest bits (output qubits) both in one LDS tile, when
+// there are at least 2^2 and 2^3 of them: tkb = min(k bits, 5), tsb = the
+// longest run of source positions 0, 1, ... gathered by destination bits
+// above tkb, at most 10 - tkb.  Else tkb = 0 (one entry per thread).
+static void set_pack_tiling(PackArgs &a) {
+  a.tkb = a.tsb = 0;
+  a.tmask = 0;
+  const int kb = std::min(a.lk, 5);
+  if (kb < 2) return;
+  int sb = 0;
+  int at[8];
+  while (sb < 8 && kb + sb < 10) {
+    int j = -1;
+    for (int i = kb; i < a.nbits; ++i)
+      if (a.inpos[i] == sb) j = i;
+    if (j < 0) break;
+    at[sb++] = j;
+  }
+  if (sb < 3) return;
+  for (int i = 0; i < kb; ++i)
+    if (a.inpos[i] < sb) return;  // a k bit among the source's lowest bits
+  a.tkb = kb;
+  a.tsb = sb;
+  uint64_t in_tile = (1ull << kb) - 1;
+  for (int q = 0; q < sb; ++q) {
+    const int j = at[q];
+    in_tile |= 1ull << j;
+    a.dpos[q] = (int8_t)(j < a.lk ? j : j - a.lk + a.kpad);
+  }
+  a.tmask = ((a.nbits >= 64 ? ~0ull : (1ull << a.nbits) - 1)) & ~in_tile;
+}
+
 static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst2, int prec_code,
                                uint64_t slice, const int *dexp = nullptr) {
   Network &net = *p->net;
@@ -399,6 +432,7 @@ static PackArgs make_pack_args(Plan *p, int j, void *dst0, void *dst1, void *dst
       a.inpos[i] = int(std::find(t.outputs.begin(), t.outputs.end(), q) - t.outputs.begin());
     }
   }
+  set_pack_tiling(a);
   return a;
 }
 

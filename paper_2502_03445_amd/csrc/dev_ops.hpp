@@ -114,13 +114,13 @@ __device__ inline void amax_commit(unsigned long long *p, double mx) {
 
 
 // ================================================================= pack
-__device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
-  const uint64_t kmask = (1ull << a.lk) - 1;
-  uint64_t src = a.base;
-  for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
-  const double sc = a.dmax ? ldexp(a.scale, scale_exp(*a.dmax)) : (a.dexp ? ldexp(a.scale, *a.dexp) : a.scale);
-  const double v = a.src[src] * sc;
-  const uint64_t d = ((e >> a.lk) << a.kpad) | (e & kmask);
+// the power of two a leaf's values are scaled by before the cast or split
+__device__ inline double pack_scale(const PackArgs &a) {
+  return a.dmax ? ldexp(a.scale, scale_exp(*a.dmax)) : (a.dexp ? ldexp(a.scale, *a.dexp) : a.scale);
+}
+
+// one scaled value to destination entry d, cast or split into planes
+__device__ inline void pack_store(const PackArgs &a, uint64_t d, double v) {
   switch (a.prec) {
     case 0:
       ((double *)a.dst0)[d] = v;
@@ -146,6 +146,60 @@ __device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
       break;
     }
   }
+}
+
+__device__ inline void pack_elem(const PackArgs &a, uint64_t e) {
+  const uint64_t kmask = (1ull << a.lk) - 1;
+  uint64_t src = a.base;
+  for (int i = 0; i < a.nbits; ++i) src += ((e >> i) & 1ull) << a.inpos[i];
+  const double v = a.src[src] * pack_scale(a);
+  pack_store(a, ((e >> a.lk) << a.kpad) | (e & kmask), v);
+}
+
+// Tiled pack, tile t of a record with tkb > 0 (2^(tkb + tsb) <= 1024
+// entries; every thread of the workgroup calls it): the entries are read in
+// runs of 2^tsb consecutive source entries into LDS and written in runs of
+// 2^tkb consecutive destination entries (the same value per entry as
+// pack_elem).
+constexpr int kPackTileEntries = 1024;
+__device__ inline void pack_tile(const PackArgs &a, uint64_t t, double *tile) {
+  const int kb = a.tkb, sb = a.tsb, SB = 1 << sb, LD = SB + 1, n = 1 << (kb + sb);
+  const uint64_t kmask = (1ull << a.lk) - 1;
+  // the tile's fixed destination-index bits: t deposited into tmask
+  uint64_t e0 = 0, src0 = a.base;
+  {
+    uint64_t tt = t;
+    for (int j = 0; j < a.nbits && tt; ++j)
+      if ((a.tmask >> j) & 1ull) {
+        if (tt & 1ull) {
+          e0 |= 1ull << j;
+          src0 += 1ull << a.inpos[j];
+        }
+        tt >>= 1;
+      }
+  }
+  const uint64_t d0 = ((e0 >> a.lk) << a.kpad) | (e0 & kmask);
+  const double sc = pack_scale(a);
+  // reads: source bits 0..sb-1 fastest
+  for (int l = (int)threadIdx.x; l < n; l += (int)blockDim.x) {
+    const int s = l & (SB - 1), kk = l >> sb;
+    uint64_t src = src0 + (uint64_t)s;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < kb) src += (uint64_t)((kk >> i) & 1) << a.inpos[i];
+    tile[kk * LD + s] = a.src[src] * sc;
+  }
+  __syncthreads();
+  // writes: destination bits 0..kb-1 (the k bits) fastest
+  for (int l = (int)threadIdx.x; l < n; l += (int)blockDim.x) {
+    const int kk = l & ((1 << kb) - 1), s = l >> kb;
+    uint64_t d = d0 + (uint64_t)kk;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < sb) d += (uint64_t)((s >> q) & 1) << a.dpos[q];
+    pack_store(a, d, tile[kk * LD + s]);
+  }
+  __syncthreads();  // the tile is free for the workgroup's next one
 }
 
 __device__ inline double gathered_abs(const AbsMaxArgs &a, uint64_t e) {

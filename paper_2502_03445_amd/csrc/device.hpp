@@ -79,6 +79,13 @@ struct PackArgs {
   const int *dexp;           // optional device exponent e: values scaled by 2^e
   const unsigned long long *dmax;  // optional device abs-max bits (instead of
                                    // dexp): e = -floor(log2 max), 0 if max = 0
+  // optional tiling (tkb > 0): a workgroup moves the entries whose
+  // destination bits 0..tkb-1 and source bits 0..tsb-1 vary through LDS;
+  // source bit t < tsb is destination bit dpos[t]; the workgroup's tile
+  // index fills the destination index bits in tmask (the others)
+  int tkb, tsb;
+  int8_t dpos[8];
+  uint64_t tmask;
 };
 
 // Largest |value| of a leaf operand over every slice (the gathered bits plus

@@ -47,16 +47,29 @@ __global__ void __launch_bounds__(256) pack_kernel(PackArgs a) {
 // several leaf operands per launch (blockIdx.y selects the leaf)
 struct PackBatch {
   PackArgs a[kPackBatch];
-  ScaleRec sr;  // optional (maxbits non-null): exponents and output scale
+  uint32_t nblk[kPackBatch];  // workgroups of each leaf (the first ones of its row)
+  ScaleRec sr;                // optional (maxbits non-null): exponents and output scale
 };
 __device__ inline void write_scales(const ScaleRec &q);
-__global__ void __launch_bounds__(256) pack_multi_kernel(PackBatch pb) {
-  if (pb.sr.maxbits && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_scales(pb.sr);
-  const PackArgs &a = pb.a[blockIdx.y];
+
+// workgroup b of nb for one leaf: tiles b, b + nb, ... or entries
+// grid-stride (every thread of the workgroup calls it)
+__device__ inline void pack_range(const PackArgs &a, uint64_t b, uint64_t nb, double *tile) {
+  if (a.tkb > 0) {
+    const uint64_t tiles = 1ull << (a.nbits - a.tkb - a.tsb);
+    for (uint64_t t = b; t < tiles; t += nb) pack_tile(a, t, tile);
+    return;
+  }
   const uint64_t total = 1ull << a.nbits;
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    pack_elem(a, e);
+  for (uint64_t e = b * blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x) pack_elem(a, e);
+}
+
+__global__ void __launch_bounds__(256) pack_multi_kernel(PackBatch pb) {
+  __shared__ double tile[kPackTileEntries + 32];
+  if (pb.sr.maxbits && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) write_scales(pb.sr);
+  const uint32_t nb = pb.nblk[blockIdx.y];
+  if (blockIdx.x >= nb) return;  // whole workgroup
+  pack_range(pb.a[blockIdx.y], blockIdx.x, nb, tile);
 }
 
 __global__ void __launch_bounds__(256) f64_to_f32_kernel(const double *in, float *out, uint64_t n) {
@@ -141,6 +154,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 constexpr unsigned kMaxGrid = 256;
 
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65536u * 4u);
+
+// Workgroups of a leaf's pack: one per tile when tiled, else one entry per
+// thread.
+static inline unsigned pack_blocks(const PackArgs &a) {
+  if (a.tkb > 0) return grid_for((1ull << (a.nbits - a.tkb - a.tsb)) * 256);
+  return grid_for(1ull << a.nbits);
+}
 
 // Workgroups of a transform record (one entry or free coordinate per
 // thread, grid-stride beyond): one that also takes an abs-max ends in one
@@ -413,13 +433,13 @@ hipError_t launch_packs(const PackArgs *args, int n, hipStream_t s, const ScaleR
     PackBatch pb{};
     if (i0 == 0 && sr) pb.sr = *sr;
     const int cnt = n - i0 < kPackBatch ? n - i0 : kPackBatch;
-    uint64_t most = 1;
+    unsigned blocks = 1;
     for (int i = 0; i < cnt; ++i) {
       pb.a[i] = args[i0 + i];
-      const uint64_t total = 1ull << args[i0 + i].nbits;
-      most = total > most ? total : most;
+      pb.nblk[i] = pack_blocks(args[i0 + i]);
+      blocks = pb.nblk[i] > blocks ? pb.nblk[i] : blocks;
     }
-    hipLaunchKernelGGL(pack_multi_kernel, dim3(grid_for(most), cnt), dim3(256), 0, s, pb);
+    hipLaunchKernelGGL(pack_multi_kernel, dim3(blocks, cnt), dim3(256), 0, s, pb);
   }
   return hipGetLastError();
 }
@@ -792,12 +812,9 @@ __global__ void __launch_bounds__(64) grouped_scale_kernel(const ScaleRec *recs,
 }
 
 __global__ void __launch_bounds__(256) grouped_pack_kernel(const PackArgs *recs, const uint32_t *first, int n) {
+  __shared__ double tile[kPackTileEntries + 32];
   const int r = group_record(first, n, blockIdx.x);
-  const PackArgs &a = recs[r];
-  const uint64_t total = 1ull << a.nbits;
-  const uint64_t nb = first[r + 1] - first[r];
-  for (uint64_t e = (blockIdx.x - first[r]) * (uint64_t)blockDim.x + threadIdx.x; e < total; e += nb * blockDim.x)
-    pack_elem(a, e);
+  pack_range(recs[r], blockIdx.x - first[r], first[r + 1] - first[r], tile);
 }
 
 template <int P, int BM, int BN, int BK, bool A64>
@@ -812,7 +829,7 @@ uint32_t grouped_transform_blocks(const TransformArgs &a) {
   return transform_grid((1ull << (2 * a.c)) << a.o, a.amax != nullptr);
 }
 uint32_t grouped_absmax_blocks(const AbsMaxArgs &a) { return grid_for((1ull << a.nbits) / 8 + 1, kMaxGrid); }
-uint32_t grouped_pack_blocks(const PackArgs &a) { return grid_for(1ull << a.nbits); }
+uint32_t grouped_pack_blocks(const PackArgs &a) { return pack_blocks(a); }
 
 hipError_t launch_grouped_passes(const TransformPassArgs *recs, const uint32_t *first, int n, uint32_t blocks,
                                  hipStream_t s) {
