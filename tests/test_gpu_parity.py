@@ -238,6 +238,54 @@ def test_budget_slicing_and_resume():
     assert np.abs(a - b).max() <= 1e-15 * max(1.0, np.abs(a).max()) * 16
 
 
+def _tiny_when_fixed(spec, j, i, shift):
+    """The raw network with tensor j's columns whose output bit i is 1
+    scaled by 2^-shift (the Pauli transform is linear per output column, so
+    its Pauli entries with that bit set shrink alike)."""
+    from workloads.cutting import Network, TensorSpec
+    ts = []
+    for k, t in enumerate(spec.tensors):
+        d = np.array(t.data, dtype=np.float64, copy=True)
+        if k == j:
+            u = sum(1 for c in t.cut_ids if spec.role(k, c) == "up")
+            cols = np.arange(d.shape[1])
+            d[:, ((cols >> u) >> i) & 1 == 1] *= 2.0 ** -shift
+        ts.append(TensorSpec(cut_ids=list(t.cut_ids), outputs=list(t.outputs), basis=t.basis, data=d))
+    return Network(n=spec.n, cuts=list(spec.cuts), tensors=ts)
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("basis", ["raw", "pauli"])
+def test_operand_scale_follows_fixed_qubits(form, basis):
+    """Operand exponents are taken over the entries a fixed-qubit slice
+    gathers (Sec. III-E's slicing applied to outputs).  One tensor's entries
+    with a fixed output bit set are scaled by 2^-140: only an abs-max over
+    the gathered entries lifts them back into the float32 / bf16 normal
+    range; one taken over the whole tensor would leave them subnormal
+    (about 9 bits kept) and fail 1e-6.  Raw leaves get their abs-max from
+    the transform that writes their Pauli tensor, Pauli-basis leaves from a
+    launch of its own."""
+    from workloads.cutting import Network, TensorSpec
+    base = configs.aqft(10, 3, 2)
+    j, i = 1, 0
+    q = base.tensors[j].outputs[i]
+    spec = _tiny_when_fixed(base, j, i, 140)
+    if basis == "pauli":
+        ts = [TensorSpec(cut_ids=c, outputs=o, basis="pauli", data=T) for c, o, T in network_pauli_tensors(spec)]
+        spec = Network(n=spec.n, cuts=list(spec.cuts), tensors=ts)
+    fixed = {q: 1}
+    got, P = run(spec, precision=form, out_dtype="f64", fixed=fixed)
+    free = [x for x in range(spec.n) if x not in fixed]
+    xs = np.zeros(1 << len(free), dtype=np.uint64)
+    for k, x in enumerate(free):
+        xs |= ((np.arange(1 << len(free), dtype=np.uint64) >> np.uint64(k)) & np.uint64(1)) << np.uint64(x)
+    xs |= np.uint64(1) << np.uint64(q)
+    ref = entries_bruteforce(spec, xs)
+    assert np.abs(ref).max() < 2.0 ** -120  # the whole slice is tiny
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err <= 1e-6, (form, basis, err)
+
+
 @pytest.mark.parametrize("form", ["fp64", "fp32", "fp16x3"])
 def test_fixed_qubit_slice(form):
     spec = synthetic.random_network(4, 5, [3, 4, 3, 3], seed=55)
