@@ -294,11 +294,14 @@ __global__ void __launch_bounds__(1024) topk_sort(const uint64_t *cand_key, cons
                                                   int k, int dtype, uint64_t *idx_out,
                                                   double *val_out, const unsigned int *gate) {
   if (gated_off(gate)) return;
-  __shared__ uint64_t sk[kMaxK];
-  __shared__ uint64_t si[kMaxK];
+  // keys and indices, 2 x n entries (dynamic: 16 n bytes, n = k rounded up
+  // to a power of two), so that the launch of a small k fits on a CU beside
+  // another reconstruction's running final step
+  extern __shared__ uint64_t sort_lds[];
   const int cnt = k;
   int n = 1;
   while (n < cnt) n <<= 1;
+  uint64_t *sk = sort_lds, *si = sort_lds + n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     if (i < cnt) {
       sk[i] = cand_key[i];
@@ -503,7 +506,9 @@ static void exact_topk(const void *probs, int dtype, uint64_t len, int k, uint64
   hipLaunchKernelGGL(topk_scan, dim3(1), dim3(1024), 0, s, blockcnt, nblocks, gate);
   hipLaunchKernelGGL(topk_collect_eq, dim3(cg), dim3(256), 0, s, probs, dtype, len, st, k, cand_key, cand_idx,
                      blockcnt, gate);
-  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), 0, s, cand_key, cand_idx, k, dtype, idx_out,
+  int npow = 1;
+  while (npow < k) npow <<= 1;
+  hipLaunchKernelGGL(topk_sort, dim3(1), dim3(1024), (size_t)16 * npow, s, cand_key, cand_idx, k, dtype, idx_out,
                      val_out, gate);
 }
 
