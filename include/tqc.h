@@ -442,31 +442,34 @@ typedef struct tqc_multi_s *tqc_multi_t;
 tqc_status tqc_multi_create(int32_t num_jobs, const tqc_plan_t *plans, void *const *outs,
                             const uint64_t *out_bytes, int32_t use_graph, int32_t num_streams,
                             int32_t timed, void *stream, tqc_multi_t *out);
-/* As tqc_multi_create, with options.  grouped = 1: the jobs' work runs as
- * a short list of shared launches on `stream` (one graph with use_graph)
- * instead of each job's own launches: the Pauli-transform passes of all
- * jobs level by level, their per-entry transforms, operand scales (zero,
- * abs-max, exponents) and leaf packs in one launch each, then the pairwise
- * steps depth by depth, one launch per kernel variant and depth (a step the
- * plain launcher would split over k, and the float16 split of a final step,
- * run alone), and last every final step that runs on the persistent
- * final-step kernel (float32 output, K <= 256, at least 2^7 rows and
- * columns): one persistent launch per (form, K), each job on a row of the
- * launch grid, jobs with the most tiles first.  Each record is the one the
- * job's own tqc_execute launches and a workgroup of a shared launch runs as
- * the same workgroup of that launch would, so results equal tqc_execute's
- * bit for bit.  num_streams is unused in this mode.  With timed = 1 every
- * job starts with the first launch and ends with the launch that runs its
- * final step.  grouped = 2 (grouped heads): only the launches before the
- * pairwise steps are shared, per wave (transform passes, per-entry
- * transforms, scales, leaf packs of the wave's jobs), the waves one after
- * another on one extra stream; each job's pairwise steps and final step are
- * its own launches, as tqc_execute makes them, on one of num_streams worker
- * streams (each wave's jobs, largest first, to the least-loaded stream),
- * after its wave's shared launches; job times as without grouping.
- * tqc_multi_info: launches per execute (-1 unless grouped; with grouped
- * heads the shared launches only), final steps in shared persistent
- * launches, and those launches. */
+/* As tqc_multi_create, with options.  grouped = 1: the jobs' work runs as a
+ * short list of shared launches on `stream` (one graph with use_graph)
+ * instead of each job's own launches: the clearing of the operand abs-max
+ * accumulators, the Pauli-transform passes of all jobs level by level and
+ * their per-entry transforms (which take each leaf's abs-max), the abs-max
+ * of leaves given in the Pauli basis, the exponents and the leaf packs in
+ * one launch each, then the pairwise steps depth by depth, one launch per
+ * kernel variant and depth (a step the plain launcher would split over k,
+ * and the float16 split of a final step, run alone), and last every final
+ * step that runs on the persistent final-step kernel (float32 output, K <=
+ * 256, at least 2^7 rows and columns): one persistent launch per (form, K),
+ * each job on a row of the launch grid, jobs with the most tiles first.
+ * Each record computes what the job's own tqc_execute computes (the same
+ * maxima give the same exponents, whether a pack or the exponent launch
+ * turns them into scales), and a workgroup of a shared launch runs as the
+ * same workgroup of that launch would, so results equal tqc_execute's bit
+ * for bit.  num_streams is unused in this mode.  With timed = 1 every job
+ * starts with the first launch and ends with the launch that runs its final
+ * step.  grouped = 2 (grouped heads): only the launches before the pairwise
+ * steps are shared, per wave (transform passes, per-entry transforms,
+ * scales, leaf packs of the wave's jobs), the waves one after another on one
+ * extra stream; each job's pairwise steps and final step are its own
+ * launches, as tqc_execute makes them, on one of num_streams worker streams
+ * (each wave's jobs, largest first, to the least-loaded stream), after its
+ * wave's shared launches; job times as without grouping.  tqc_multi_info:
+ * launches per execute (-1 unless grouped; with grouped heads the shared
+ * launches only), final steps in shared persistent launches, and those
+ * launches. */
 typedef struct {
   int32_t use_graph;      /* as tqc_multi_create                          */
   int32_t num_streams;    /* as tqc_multi_create (0 = 4, at most 16)       */
