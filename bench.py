@@ -252,12 +252,13 @@ BATCH_MODES = {"graph_4streams": dict(use_graph=True, streams=4),
 def batch_study(tqc, torch, form, num_jobs=512, workers=16, reps=5, modes=tuple(BATCH_MODES)):
     """Batched execution of uneven reconstructions: num_jobs seeded cut
     circuits (n uniform in 16..28 qubits, 2..5 subcircuits, 2..10 cuts, line
-    or grid layouts, exact subcircuit tensors) with autotuned tiles, run as one
-    HIP graph over four streams versus the same jobs as sequential plain
-    launches on one stream.  Reports the batch time (median of `reps`), jobs
-    per second, per-job time (end - start) and completion time (end - batch
-    start) percentiles from device timestamps, and that every output equals
-    the job's own plain execution bit for bit."""
+    or grid layouts, exact subcircuit tensors) with autotuned tiles, in the
+    executor modes of BATCH_MODES (per-job launches in one HIP graph over 4 or
+    8 streams, grouped launches in 1-4 waves, grouped heads in 4-16 waves,
+    sequential plain launches on one stream).  Reports the batch time (median
+    of `reps`), jobs per second, per-job time (end - start) and completion
+    time (end - batch start) percentiles from device timestamps, and that
+    every output equals the job's own plain execution bit for bit."""
     from workloads import batch
     t0 = time.perf_counter()
     specs = [None] * num_jobs
