@@ -59,6 +59,22 @@ def test_validation_errors():
     assert e.value.status == 1
 
 
+def test_multi_options_rejected_before_any_device_work():
+    """tqc_multi_create_ex checks its options before it touches a plan's
+    workspace or the device: a grouping mode outside 0..2 or more than 16
+    streams is INVALID_ARG (the output pointers are never read)."""
+    ok = [([0], [0], "pauli", np.ones((4, 2))), ([0], [1], "pauli", np.ones((4, 2)))]
+    plan = tqc.Plan(_net(2, ok, [(0, 1)]))
+    L = tqc.lib()
+    ph = (ctypes.c_void_p * 1)(plan.handle.value)
+    oh = (ctypes.c_void_p * 1)(0x1000)  # never dereferenced
+    h = ctypes.c_void_p()
+    for grouped, streams in ((3, 4), (-1, 4), (1, 17)):
+        opt = tqc.MultiOptions(1, streams, 0, grouped, 1)
+        st = L.tqc_multi_create_ex(1, ph, oh, None, ctypes.byref(opt), None, ctypes.byref(h))
+        assert st == 1 and not h.value, (grouped, streams, st)
+
+
 def test_worked_example_through_library():
     cut_lists = [[0], [0, 1, 2], [1, 3], [2, 3]]
     cuts = [(0, 1), (1, 2), (1, 3), (2, 3)]
